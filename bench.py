@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the KPM energy + gradient hot path on one MI355X.
+
+Workload (the 100x100 configuration): 100 x 100 torus (10^4 sites, BdG
+dimension 2 x 10^4) with two vortices (two superconducting flux quanta, Landau
+gauge Peierls phases) and a period-8 checkerboard pair/charge-density seed of
+amplitude 0.02, doping 0.125, t'/t = -0.3, J/t = 0.3, T = 0.005 t; M = 4096
+Chebyshev moments with Jackson damping; 256 colored Z4 probes (8 x 8 coloring,
+Nambu-split, two independent phase draws of weight 1/2); FP32 recurrence
+vectors with FP64 moments, bounds, coefficients and density-matrix sums;
+alpha checkpoints every 64 steps for the reversible adjoint.
+
+One step = one energy + gradient evaluation: build h from the order
+parameters, Gershgorin bounds, expansion coefficients, forward recursion with
+moments and Omega, adjoint recursion with the density matrix, the order-
+parameter map and the builder VJP (dOmega/dtheta for all ~1e5 parameters).
+Inputs are resident in HBM before the timed region; nothing is skipped.
+
+Prints ONE JSON line.  ``value`` is Chebyshev vector-steps per second: a
+vector-step is one application of H~ to one 2N-dimensional probe vector; one
+energy + gradient costs R (M - 1) forward and 2 R (M - 2) adjoint vector-steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+METRIC = "Chebyshev vector-steps/s + HBM GB/s; s per KPM energy+gradient at 100x100"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    src = os.path.join(ROOT, "paper_2212_05685_amd", "csrc", "kpm_cheb.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def traffic_record(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c5_fp32_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def make_problem(cfg, precision):
+    import torch
+    from paper_2212_05685_amd import kpm
+    from paper_2212_05685_amd.solver import KPMProblem
+    import workloads as wl
+
+    kinds = {"unit": kpm.KPM_PROBE_UNIT, "dense_z4": kpm.KPM_PROBE_DENSE_Z4,
+             "colored_z4": kpm.KPM_PROBE_COLORED_Z4}
+    specs = [kpm.ProbeSpec(kinds[p.kind], p.count, p.seed, p.px, p.py, p.split_nambu, p.first, p.weight)
+             for p in cfg.probes]
+    prec = kpm.KPM_FP32 if precision == "fp32" else kpm.KPM_FP64
+    prob = KPMProblem(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, cfg.T, cfg.M, specs,
+                      prec, cfg.ckpt_k)
+    n, chi, dlt = wl.make_theta(cfg)
+    th = (torch.from_numpy(n).cuda(), torch.from_numpy(chi).cuda(), torch.from_numpy(dlt).cuda())
+    return prob, th
+
+
+def energy_grad(prob, th):
+    """One full energy + gradient evaluation (every row of the hot path)."""
+    n, chi, dlt = th
+    h = prob.build_H(n, chi, dlt)
+    ab = prob.bounds(h)
+    C = prob.coefficients(ab)
+    out = prob.density_matrix(h, ab, C)
+    grads = prob.build_H_vjp(n, chi, dlt, out["rho"])
+    return out, grads
+
+
+def timed(prob, th, steps, warmup, profile):
+    import torch
+    from paper_2212_05685_amd import kpm
+
+    for w in range(warmup):
+        energy_grad(prob, th)
+        torch.cuda.synchronize()
+        log(f"{'fp32' if prob.precision else 'fp64'} warmup {w + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    if profile:
+        kpm.kpm_profile_begin()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        out, grads = energy_grad(prob, th)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = kpm.kpm_profile_end() if profile else None
+    if prob.status() != 0:
+        raise RuntimeError(f"device status {prob.status()}")
+    log(f"{'fp32' if prob.precision else 'fp64'} timed {steps} steps: {(t1 - t0) / steps * 1e3:.1f} ms/step")
+    return (t1 - t0) / steps, out, grads, prof
+
+
+def cpu_baseline(cfg):
+    """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
+    probe of the same workload, single thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import builder, chebyshev, kpm_plain, probes
+
+    n, chi, dlt = __import__("workloads").make_theta(cfg)
+    with threadpool_limits(1):
+        st = builder.build_stencil(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, n, chi, dlt)
+        Hs = builder.sparse_from_stencil(st, cfg.Lx, cfg.Ly)
+        a, b = chebyshev.rescale(*chebyshev.gershgorin_sparse(Hs))
+        C = chebyshev.kpm_coefficients(cfg.M, cfg.T, a, b)
+        p = cfg.probes[0]
+        g = probes.ProbeGroup(probes.COLORED_Z4, p.count, p.seed, p.px, p.py, p.split_nambu, p.first, p.weight)
+        r = probes.probe_vector(g, 0, cfg.Lx, cfg.Ly)[None, :]
+        w = np.array([p.weight])
+        log("cpu baseline: oracle forward + adjoint on 1 probe ...")
+        t0 = time.perf_counter()
+        kpm_plain.plain_kpm(Hs, a, b, r, w, C, cfg.Lx, cfg.Ly, want_grad=True)
+        t1 = time.perf_counter()
+    vsteps = 3 * cfg.M - 5
+    log(f"cpu baseline: {t1 - t0:.1f} s")
+    return {"value": vsteps / (t1 - t0), "unit": "vector-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 of {cfg.R} probes of the 100x100 workload (M={cfg.M}): plain FP64 forward "
+                      f"recursion + beta adjoint with every vector stored (oracle O2), single thread, "
+                      f"{t1 - t0:.1f} s for {vsteps} vector-steps"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-form", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one MI355X: this build runs on a single GPU only "
+              "(multi-GPU probe sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as wl
+
+    cfg = wl.C5("fp32")
+    prob, th = make_problem(cfg, "fp32")
+    R, M, N = prob.R, cfg.M, cfg.N
+    log(f"workload 100x100 M={M} R={R}; building and warming up")
+    dt, out32, grads32, prof = timed(prob, th, args.steps, args.warmup, profile=True)
+    vsteps = R * (M - 1) + 2 * R * (M - 2)
+    fwd_ms, n_fwd, adj_ms, n_adj = prof
+    rec = 16                                    # FP32 complex record of one site (2 components)
+    coef_bytes = 36 * 8 * N                     # row-form H~ coefficients, FP32 complex
+    adj_bytes = 6 * rec * R * N + coef_bytes     # read a_{m+1}, g_{m+1}, a_{m+2}, g_{m+2}; write a_m, g_m
+    fwd_bytes = 3 * rec * R * N + coef_bytes     # read a_m, a_{m-1}; write a_{m+1}
+    adj_avg_s = adj_ms / max(n_adj, 1) * 1e-3
+    fwd_avg_s = fwd_ms / max(n_fwd, 1) * 1e-3
+    achieved = adj_bytes / adj_avg_s / 1e9
+    traffic = traffic_record("k_adj")
+
+    result = {
+        "metric": METRIC,
+        "value": vsteps / dt,
+        "unit": "vector-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "s_per_energy_grad": dt,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "reductions_dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "100x100 torus, 2 vortices + period-8 PDW/CDW seed (0.02), doping 0.125, "
+                        "M=4096 Jackson, 256 colored Z4 probes (8x8, Nambu split, 2 draws), "
+                        "FP32 recurrence, checkpoints every 64; step = energy + gradient",
+            "Lx": cfg.Lx, "Ly": cfg.Ly, "M": M, "R": R, "ckpt_k": cfg.ckpt_k,
+            "vector_steps_per_step": vsteps,
+        },
+        "roofline": {
+            "kernel": "k_adj (fused adjoint step)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": adj_bytes,
+            "avg_launch_us": adj_avg_s * 1e6,
+            "launches_timed": n_adj,
+        },
+        "forward_kernel": {
+            "kernel": "k_fwd (forward step)", "algorithmic_bytes_per_launch": fwd_bytes,
+            "avg_launch_us": fwd_avg_s * 1e6, "achieved_GBs": fwd_bytes / fwd_avg_s / 1e9,
+            "launches_timed": n_fwd,
+        },
+        "hbm_GBs_algorithmic_whole_step": (n_fwd * fwd_bytes + n_adj * adj_bytes) / args.steps / dt / 1e9,
+    }
+
+    if not args.no_fp64_form:
+        del prob
+        torch.cuda.empty_cache()
+        prob64, th64 = make_problem(wl.C5("fp64"), "fp64")
+        dt64, out64, grads64, _ = timed(prob64, th64, 2, 1, profile=False)
+        om32 = float(out32["omega"].item())
+        om64 = float(out64["omega"].item())
+        r32, r64 = out32["rho"].cpu().numpy(), out64["rho"].cpu().numpy()
+        g32, g64 = grads32[1].cpu().numpy(), grads64[1].cpu().numpy()
+        result["fp64_form"] = {
+            "ms_per_step": dt64 * 1e3,
+            "speedup_fp32_over_fp64": dt64 / dt,
+            "fp32_vs_fp64_rel_err_omega": abs(om32 - om64) / abs(om64),
+            "fp32_vs_fp64_rel_err_rho": float(np.max(np.abs(r32 - r64)) / np.max(np.abs(r64))),
+            "fp32_vs_fp64_rel_err_dchi": float(np.max(np.abs(g32 - g64)) / np.max(np.abs(g64))),
+        }
+        del prob64
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

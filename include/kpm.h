@@ -1,0 +1,247 @@
+/*
+ * kpm.h -- C ABI of the MI355X (gfx950) kernel-polynomial-method library for
+ * the renormalized mean-field t-t'-J model with vortices (Liu, Tu, Chern, Lee,
+ * "Intertwined Orders and Electronic Structure in Superconducting Vortex
+ * Halos", arXiv:2212.05685).
+ *
+ * The library computes, for the 2N x 2N Nambu (BdG) single-particle matrix h
+ * of an Lx x Ly torus, the Chebyshev moments mu_m, the grand potential
+ * Omega = sum_m C_m mu_m and its adjoint dOmega/dh, which is the density
+ * matrix rho_IJ = <d^dag_I d_J> restricted to the stencil (App. B).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers are DEVICE pointers unless the argument says "host".  The caller
+ *   owns every buffer; the library allocates device memory only inside batch
+ *   plans (kpm_batch_create).
+ * - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *   device work is enqueued on it; calls return before it finishes.
+ * - Argument errors are returned synchronously (nothing is enqueued then).
+ *   Errors found by the device (spectrum outside the rescaled interval,
+ *   non-finite values) are latched in the workspace status word; read it with
+ *   kpm_status_read.
+ * - Complex numbers are stored as interleaved (re, im) doubles.
+ * - Sites are i = y*Lx + x.  Stencil directions d = 0..3 are +x, +y, +x+y,
+ *   +x-y; every undirected bond is stored once, at its tail site i, pointing to
+ *   j = i + d on the torus.  Nambu index I = 2i + a with a = 0 for c_{i up} and
+ *   a = 1 for c^dag_{i dn}.
+ * - STENCIL layout ([19][N] complex, entry-major): entry 4d + 2a + b holds the
+ *   matrix element (i a, j b) of the bond block, j = i + d; entry 16 holds
+ *   (i0, i0), 17 holds (i1, i1) (both real, imaginary part ignored on input and
+ *   written as 0), 18 holds (i0, i1).  Every other element of the matrix
+ *   follows by Hermiticity.  Both h and rho = dOmega/dh use this layout.
+ * - Functions are re-entrant for distinct workspaces.  Calls that share one
+ *   workspace must be ordered on one stream.
+ * - Lx, Ly >= 3 (the eight neighbours of a site must be distinct sites);
+ *   n_vortex even (whole electron flux quanta through the torus); M >= 2.
+ */
+#ifndef KPM_H
+#define KPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KPM_OK = 0,
+  KPM_EINVAL = -1,     /* bad argument (size, pointer, option)                  */
+  KPM_ENOMEM = -2,     /* plan allocation failed                                */
+  KPM_EDEVICE = -3,    /* HIP runtime error                                     */
+  KPM_EBOUNDS = -4,    /* device status: |mu_m| > mu_0 or non-finite value, i.e.
+                          the spectrum is not inside the rescaled interval       */
+  KPM_ENOTSUP = -5,    /* option not supported                                  */
+  KPM_EWORKSPACE = -6  /* workspace too small or not prepared by the forward call */
+};
+
+enum { KPM_FP64 = 0, KPM_FP32 = 1 };   /* recurrence vectors; reductions always FP64 */
+
+enum { KPM_PROBE_UNIT = 0, KPM_PROBE_DENSE_Z4 = 1, KPM_PROBE_COLORED_Z4 = 2 };
+
+typedef struct {
+  int32_t Lx, Ly;      /* torus sides, >= 3                                     */
+  int32_t n_vortex;    /* superconducting flux quanta through the torus (even); */
+} kpm_lattice;         /* B = n_vortex Phi0 / (Lx Ly), App. C                    */
+
+typedef struct {
+  double t, tp;        /* nn and nnn bare hoppings (-t c^dag c convention)      */
+  double J;            /* nn exchange                                           */
+  double mu;           /* chemical potential (Lagrange multiplier of App. A)    */
+} kpm_model;
+
+/* One group of probe vectors for the stochastic trace (App. B).  The Z4 phase
+ * of Nambu index I in draw s is i^k with k the top two bits of
+ * SplitMix64(seed, s * 2^32 + I) (Steele, Lea & Flood 2014; Vigna's form:
+ * z = seed + (counter + 1) * 0x9E3779B97F4A7C15, then the two xor-shift-
+ * multiply rounds and a final xor-shift).
+ *   UNIT        count vectors e_I, I = first .. first + count - 1.
+ *   DENSE_Z4    count vectors, every entry a Z4 phase (draw s = probe index).
+ *   COLORED_Z4  count draws; in each, one probe per colour (x mod px) +
+ *               px (y mod py) (and per Nambu component if split_nambu), Z4
+ *               phases on its colour class, zero elsewhere; probe q of the
+ *               group is draw q / C, colour (q % C) [/ 2 if split], component
+ *               (q % 2 if split), C = px py (2 if split).
+ * `weight` multiplies every probe of the group in Omega and in rho. */
+typedef struct {
+  int32_t kind;
+  int32_t count;
+  int32_t px, py;
+  int32_t split_nambu;
+  int32_t first;
+  uint64_t seed;
+  double weight;
+} kpm_probe_group;
+
+#define KPM_MAX_PROBE_GROUPS 4
+
+typedef struct {
+  const kpm_probe_group* groups;   /* host array                               */
+  int32_t ngroups;                 /* 1 .. KPM_MAX_PROBE_GROUPS                */
+} kpm_probes;
+
+/* Number of probe vectors R described by `probes` (host only), or < 0 on error. */
+int32_t kpm_probe_count(const kpm_lattice* lat, const kpm_probes* probes);
+
+/* Build h on the stencil from the order parameters at m_i = 0
+ * (App. A eqs. Tij, Dij, mu_i; App. B Nambu matrix; Peierls phases of Model
+ * and methods / App. C).  h_IJ = dW/drho_IJ for the spin-singlet energy
+ *   W = -sum_bonds 4 g_i g_j Re(t_ij chi_ij) - (3/2) J sum_nn g^s_i g^s_j
+ *       (|chi_ij|^2 + |Delta_ij|^2) - mu sum_i n_i,
+ * g_i = sqrt(2 delta_i/(1+delta_i)), g^s_i = 2/(1+delta_i), delta_i = 1 - n_i:
+ *   (i0,j0) = T = -g_i g_j t_ij - (3/4) J g^s_i g^s_j conj(chi_ij) [nn only for J],
+ *   (i1,j1) = -conj(T), (i0,j1) = P = (3/4) J g^s_i g^s_j Delta_ij (nn only),
+ *   (i1,j0) = conj(P), (i0,i0) = eps_i = dW/dn_i = -(i1,i1), (i0,i1) = 0.
+ * n     [N] real, electron density per site (0 < 1 - n < 1).
+ * chi   [4][N] complex, <c^dag_{i s} c_{j s}> per spin on bond (i, i+d).
+ * delta [4][N] complex, singlet <c_{i up} c_{j dn}> on bond (i, i+d); the
+ *       diagonal directions d = 2, 3 do not enter W (no nnn pairing).
+ * h     [19][N] complex out (STENCIL layout). */
+int kpm_build_H(const kpm_lattice* lat, const kpm_model* model, const double* n,
+                const double* chi, const double* delta, double* h, void* stream);
+
+/* Vector-Jacobian product of kpm_build_H: given rho = dOmega/dh on the
+ * stencil ([19][N] complex), writes dOmega/dtheta = sum_IJ rho_IJ dh_IJ/dtheta
+ * over all matrix elements (both halves).  Complex gradients use the
+ * convention dOmega/dRe z + i dOmega/dIm z.  dn [N], dchi [4][N], ddelta [4][N]
+ * (complex) are overwritten; ddelta is 0 on the diagonal directions. */
+int kpm_build_H_vjp(const kpm_lattice* lat, const kpm_model* model, const double* n,
+                    const double* chi, const double* delta, const double* rho,
+                    double* dn, double* dchi, double* ddelta, void* stream);
+
+/* Spectral rescale (App. B: all eigenvalues must lie in [-1, 1]): Gershgorin
+ * bounds Emin, Emax of h and ab[0] = a = (Emax - Emin)/1.99,
+ * ab[1] = b = (Emax + Emin)/2, so H~ = (h - b)/a has spectrum in
+ * [-0.995, 0.995].  ab: device double[2]. */
+int kpm_bounds(const kpm_lattice* lat, const double* h, double* ab, void* stream);
+
+/* Expansion coefficients C_m, m < M, of the grand-potential density
+ * f(e) = -T log(1 + e^{-e/T}) (App. B eq. F_KPM):
+ *   C_m = (2 - delta_m0) g_m (1/K) sum_k cos(m th_k) f(a cos th_k + b),
+ * th_k = pi (k + 1/2)/K (Chebyshev-Gauss quadrature), g_m the Jackson kernel
+ * of Weisse et al. (Rev. Mod. Phys. 78, 275), (a, b) read from ab on the
+ * device.  K = 0 selects max(4M, 16384).  C: device double[M]. */
+int kpm_coefficients(int32_t M, double T, const double* ab, int32_t K, double* C, void* stream);
+
+/* Workspace bytes needed by kpm_moments / kpm_grand_potential(_grad) /
+ * kpm_density_matrix for this lattice, R probes, M moments, checkpoint
+ * interval ckpt_k (>= 2) and precision.  Returns 0 on invalid arguments. */
+size_t kpm_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int32_t ckpt_k,
+                          int32_t precision);
+
+/* Chebyshev moments mu_{l,m} = r_l^dag T_m(H~) r_l, H~ = (h - ab[1])/ab[0],
+ * from the recursion alpha_0 = r, alpha_1 = H~ r, alpha_{m+1} = 2 H~ alpha_m -
+ * alpha_{m-1} (App. B eq. alpha).  Vectors in `precision`, sums in FP64.
+ * mu: [R][M] doubles (real parts; the imaginary parts vanish for Hermitian h).
+ * ws: workspace of at least kpm_workspace_size(lat, R, M, ckpt_k, precision)
+ * bytes, 256-byte aligned. */
+int kpm_moments(const kpm_lattice* lat, const double* h, const double* ab,
+                const kpm_probes* probes, int32_t M, int32_t precision, int32_t ckpt_k,
+                double* mu, void* ws, size_t ws_bytes, void* stream);
+
+/* Grand potential Omega = sum_l w_l sum_m C_m mu_{l,m} (App. B eq. F_KPM with
+ * the probe average).  Runs the forward recursion, keeps the checkpoint pairs
+ * (alpha_{jk}, alpha_{jk+1}), j = 0,1,..., in ws for kpm_grand_potential_grad.
+ * omega: device double[1].  mu: optional ([R][M] doubles) or NULL. */
+int kpm_grand_potential(const kpm_lattice* lat, const double* h, const double* ab,
+                        const kpm_probes* probes, int32_t M, const double* C,
+                        int32_t precision, int32_t ckpt_k, double* omega, double* mu,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of kpm_grand_potential (App. B eqs. dFdH, dalphadH and the beta
+ * recursion): with gamma_m = beta_m^dag,
+ *   gamma_{M-1} = 0, gamma_{M-2} = w C_{M-1} r,
+ *   gamma_m = w C_{m+1} r + 2 H~ gamma_{m+1} - gamma_{m+2},
+ *   rho_IJ = omega_bar/a * sum_l [conj(gamma_{0,I}) alpha_{0,J}
+ *            + 2 sum_{m=1}^{M-2} conj(gamma_{m,I}) alpha_{m,J}],
+ * on the stencil.  alpha_m is recomputed backwards by the reversible
+ * recursion alpha_m = 2 H~ alpha_{m+1} - alpha_{m+2}, reset at each stored
+ * checkpoint pair.  Must follow kpm_grand_potential on the same ws with the
+ * same arguments.  omega_bar: device double[1] or NULL (= 1).  rho: [19][N]
+ * complex out (STENCIL layout, FP64). */
+int kpm_grand_potential_grad(const kpm_lattice* lat, const double* h, const double* ab,
+                             const kpm_probes* probes, int32_t M, const double* C,
+                             int32_t precision, int32_t ckpt_k, const double* omega_bar,
+                             double* rho, void* ws, size_t ws_bytes, void* stream);
+
+/* kpm_grand_potential followed by kpm_grand_potential_grad with omega_bar = 1,
+ * then the order parameters (Model and methods eqs. delta, chi, pairing, via
+ * App. B): n_up = rho_{i0,i0}, n_dn = 1 - rho_{i1,i1},
+ * chi_up = rho_{i0,j0}, chi_dn = -conj(rho_{i1,j1}),
+ * delta_up = <c_{i up} c_{j dn}> = -conj(rho_{i0,j1}),
+ * delta_dn = <c_{j up} c_{i dn}> = -rho_{i1,j0}, for every bond (i, j = i+d).
+ * omega [1], rho [19][N] complex, n_up/n_dn [N], chi_up/chi_dn/delta_up/
+ * delta_dn [4][N] complex; any output except omega and rho may be NULL. */
+int kpm_density_matrix(const kpm_lattice* lat, const double* h, const double* ab,
+                       const kpm_probes* probes, int32_t M, const double* C,
+                       int32_t precision, int32_t ckpt_k, double* omega, double* rho,
+                       double* n_up, double* n_dn, double* chi_up, double* chi_dn,
+                       double* delta_up, double* delta_dn, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* Device status word latched by the last recursion on ws: KPM_OK or
+ * KPM_EBOUNDS.  Synchronises `stream`. *status is host memory. */
+int kpm_status_read(const void* ws, int32_t* status, void* stream);
+
+/* ---- batches of uneven lattices (many instances per launch) -------------- */
+
+/* Create a plan for n_inst lattices of possibly different size, vortex count
+ * and probes, all with the same M, precision and checkpoint interval.  The
+ * plan owns its device memory and chooses the probes-per-thread blocking of
+ * the recursion kernels by timing candidates on first use (autotune),
+ * remembered per shape in the process.  lats/probes: host arrays [n_inst]. */
+int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* probes,
+                     int32_t M, int32_t precision, int32_t ckpt_k, void** plan);
+
+/* Energy + gradient for every instance: for instance k, with h[k], ab[k],
+ * C[k] (host arrays of device pointers), writes omega[k] (device double
+ * [n_inst]) and rho[k] ([19][N_k] complex, device).  The forward and adjoint
+ * recursions of all instances run as one sequence of batched kernels,
+ * captured once into a hipGraph and replayed on later calls with the same
+ * pointers (use_graph != 0). */
+int kpm_batch_energy_grad(void* plan, const double* const* h, const double* const* ab,
+                          const double* const* C, double* omega, double* const* rho,
+                          int32_t use_graph, void* stream);
+
+int kpm_batch_destroy(void* plan);
+
+/* Probes-per-thread blocking used by the single-lattice calls (0 = automatic,
+ * else one of 1, 2, 4, 8, 16, 32).  Process-wide; returns the previous value. */
+int32_t kpm_set_probe_block(int32_t probes_per_thread);
+
+/* ---- measurement ----------------------------------------------------------
+ * Between kpm_profile_begin and kpm_profile_end every forward-step and
+ * adjoint-step kernel launched by this library (not inside a graph capture)
+ * carries start/stop events recorded by its own dispatch on its own stream.
+ * kpm_profile_end synchronises those events and returns the summed kernel
+ * durations (milliseconds, host memory) and launch counts of both kinds. */
+int kpm_profile_begin(void);
+int kpm_profile_end(double* fwd_ms, int32_t* n_fwd, double* adj_ms, int32_t* n_adj);
+
+const char* kpm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPM_H */

@@ -1,0 +1,38 @@
+"""Omega as a torch.autograd.Function (App. B: the density matrix is the
+derivative of the grand potential; the backward pass is the adjoint Chebyshev
+recursion of the library, followed by the builder VJP).
+
+    omega = GrandPotential.apply(n, chi, delta, problem)
+
+n: float64 [N]; chi, delta: complex128 [4, N] on the GPU.  The spectral
+bounds (a, b) and the expansion coefficients are computed in the forward pass
+and held constant for differentiation.  Gradients for complex inputs follow
+torch's convention dOmega/dRe z + i dOmega/dIm z.
+"""
+from __future__ import annotations
+
+import torch
+
+from .solver import KPMProblem
+
+
+class GrandPotential(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, n, chi, delta, problem: KPMProblem):
+        n, chi, delta = n.contiguous(), chi.contiguous(), delta.contiguous()
+        h = problem.build_H(n, chi, delta)
+        ab = problem.bounds(h)
+        C = problem.coefficients(ab)
+        omega = problem.grand_potential(h, ab, C)
+        ctx.problem = problem
+        ctx.save_for_backward(n, chi, delta, h, ab, C)
+        return omega.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        n, chi, delta, h, ab, C = ctx.saved_tensors
+        p = ctx.problem
+        gbar = grad_out.reshape(1).to(torch.float64).contiguous()
+        rho = p.grand_potential_grad(h, ab, C, omega_bar=gbar)
+        dn, dchi, ddelta = p.build_H_vjp(n, chi, delta, rho)
+        return dn, dchi, ddelta, None

@@ -1,0 +1,743 @@
+// Host side of the C ABI declared in include/kpm.h: argument validation,
+// workspace layout, launch sequencing, batch plans (hipGraph) and the
+// probes-per-thread autotuner.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/kpm.h"
+#include "kpm_internal.h"
+
+namespace kpm {
+hipError_t launch_build_h(const ModelDev&, const double*, const double*, const double*, double*,
+                          hipStream_t);
+hipError_t launch_build_vjp(const ModelDev&, const double*, const double*, const double*,
+                            const double*, double*, double*, double*, hipStream_t);
+hipError_t launch_bounds(int, int, const double*, double*, hipStream_t);
+hipError_t launch_rescale(const InstDev*, const int2*, int, bool, hipStream_t);
+hipError_t launch_coeffs(int, int, double, const double*, double*, hipStream_t);
+hipError_t launch_cheb(bool, int, int, const InstDev*, const int2*, int, int, int, int, int, int,
+                       hipStream_t);
+hipError_t launch_mom_reduce(const InstDev*, int, int, int, double*, hipStream_t);
+hipError_t launch_omega(const InstDev*, int, int, hipStream_t);
+hipError_t launch_rho(const InstDev*, const int2*, int, hipStream_t);
+hipError_t launch_map(int, const double*, double*, double*, double*, double*, double*, double*,
+                      hipStream_t);
+hipError_t profile_begin();
+hipError_t profile_end(double*, int*, double*, int*);
+
+// Sets every instance's status word (a kernel, not a memset, so that the
+// sequence can be captured in a hipGraph).
+__global__ void k_set_status(const InstDev* __restrict__ insts, int ninst, int v) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ninst && insts[k].status) *insts[k].status = v;
+}
+}  // namespace kpm
+
+using namespace kpm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxN = 1 << 26;
+constexpr int kMaxR = 1 << 20;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+#define KPM_HIP(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return KPM_EDEVICE; \
+  } while (0)
+
+bool valid_lattice(const kpm_lattice* L) {
+  if (!L) return false;
+  if (L->Lx < 3 || L->Ly < 3) return false;
+  if ((L->n_vortex % 2) != 0) return false;
+  long long N = (long long)L->Lx * L->Ly;
+  return N <= kMaxN;
+}
+
+long long group_nprobes(const kpm_probe_group& g) {
+  if (g.kind == KPM_PROBE_COLORED_Z4)
+    return (long long)g.count * g.px * g.py * (g.split_nambu ? 2 : 1);
+  return g.count;
+}
+
+// Fills the device group table; returns R or < 0.
+int build_groups(const kpm_lattice* L, const kpm_probes* pr, GroupDev* out, int* ng) {
+  if (!pr || !pr->groups || pr->ngroups < 1 || pr->ngroups > KPM_MAX_PROBE_GROUPS) return -1;
+  const long long N = (long long)L->Lx * L->Ly;
+  long long R = 0;
+  for (int k = 0; k < pr->ngroups; ++k) {
+    const kpm_probe_group& g = pr->groups[k];
+    if (g.count < 1 || !std::isfinite(g.weight)) return -1;
+    switch (g.kind) {
+      case KPM_PROBE_UNIT:
+        if (g.first < 0 || (long long)g.first + g.count > 2 * N) return -1;
+        break;
+      case KPM_PROBE_DENSE_Z4:
+        break;
+      case KPM_PROBE_COLORED_Z4:
+        if (g.px < 1 || g.py < 1 || g.px > L->Lx || g.py > L->Ly) return -1;
+        if (g.split_nambu != 0 && g.split_nambu != 1) return -1;
+        break;
+      default:
+        return -1;
+    }
+    const long long np = group_nprobes(g);
+    if (np < 1 || np > kMaxR) return -1;
+    if (out) {
+      GroupDev& d = out[k];
+      d.kind = g.kind;
+      d.count = g.count;
+      d.px = g.px;
+      d.py = g.py;
+      d.split = g.split_nambu;
+      d.first = g.first;
+      d.nprobes = (int)np;
+      d.base = (int)R;
+      d.seed = g.seed;
+      d.weight = g.weight;
+    }
+    R += np;
+    if (R > kMaxR) return -1;
+  }
+  if (ng) *ng = pr->ngroups;
+  return (int)R;
+}
+
+bool valid_P(int P) { return P == 1 || P == 2 || P == 4 || P == 8 || P == 16 || P == 32; }
+
+// Enough threads to give every SIMD of the 256 CUs several waves, then the
+// largest block that keeps the per-thread register footprint reasonable.
+int auto_probe_block(long long sites_total, int Rmax, bool fp32, bool adjoint) {
+  const long long want = 256LL * 4 * 4 * 64;
+  const int pmax = adjoint ? (fp32 ? 8 : 4) : (fp32 ? 16 : 8);
+  int P = 1;
+  while (P < pmax && sites_total * ((Rmax + 2 * P - 1) / (2 * P)) >= want) P *= 2;
+  return P;
+}
+
+std::mutex g_mu;
+int g_probe_block = 0;   // 0 = automatic
+
+// ------------------------------------------------------------ instance layout
+struct Sizes {
+  int N, R, nchunk;
+  size_t rec, coef, vec, ckpt, mom, musum, gpart;
+  long long nslots;
+};
+
+Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32) {
+  Sizes z{};
+  z.N = L->Lx * L->Ly;
+  z.R = R;
+  z.nchunk = (z.N + kBlock - 1) / kBlock;
+  z.rec = fp32 ? 16 : 32;
+  z.coef = align_up((size_t)kNcoef * z.N * 2 * (fp32 ? 4 : 8));
+  z.vec = align_up((size_t)R * z.N * z.rec);
+  z.nslots = 2LL * ((M - 1) / k + 1);
+  z.ckpt = align_up((size_t)R * z.N * z.rec * (size_t)z.nslots);
+  z.mom = align_up(sizeof(double) * (size_t)M * R * z.nchunk);
+  z.musum = align_up(sizeof(double) * (size_t)M * R);
+  z.gpart = align_up(sizeof(double) * 2 * kNent * (size_t)z.N * R);   // sized for P = 1
+  return z;
+}
+
+size_t inst_bytes(const Sizes& z) {
+  return align_up(sizeof(int)) + z.coef + 4 * z.vec + z.ckpt + z.mom + z.musum + z.gpart;
+}
+
+// Carve one instance's buffers out of `base` (which must hold inst_bytes).
+void carve(InstDev& I, const Sizes& z, char* base) {
+  char* o = base;
+  I.status = reinterpret_cast<int*>(o);   o += align_up(sizeof(int));
+  I.coef = o;                             o += z.coef;
+  I.A[0] = o;                             o += z.vec;
+  I.A[1] = o;                             o += z.vec;
+  I.G[0] = o;                             o += z.vec;
+  I.G[1] = o;                             o += z.vec;
+  I.ckpt = o;                             o += z.ckpt;
+  I.mom = reinterpret_cast<double*>(o);   o += z.mom;
+  I.musum = reinterpret_cast<double*>(o); o += z.musum;
+  I.gpart = reinterpret_cast<double2*>(o);
+}
+
+// ------------------------------------------------------------ run context
+struct Ctx {
+  std::vector<InstDev> inst;
+  std::vector<int2> cmap;
+  InstDev* d_inst = nullptr;
+  int2* d_cmap = nullptr;
+  int M = 0, k = 0;
+  bool fp32 = false;
+  int Pf = 1, Pa = 1;
+  int Rmax = 0;
+  long long sites = 0;
+  int npbf() const { return (Rmax + Pf - 1) / Pf; }
+  int npba() const { return (Rmax + Pa - 1) / Pa; }
+  int nch() const { return (int)cmap.size(); }
+};
+
+void finish_ctx(Ctx& c) {
+  c.cmap.clear();
+  c.Rmax = 0;
+  c.sites = 0;
+  for (size_t q = 0; q < c.inst.size(); ++q) {
+    for (int ch = 0; ch < c.inst[q].nchunk; ++ch) c.cmap.push_back(make_int2((int)q, ch * kBlock));
+    c.Rmax = std::max(c.Rmax, c.inst[q].R);
+    c.sites += c.inst[q].N;
+  }
+}
+
+void set_npb(Ctx& c) {
+  for (auto& I : c.inst) I.npb = (I.R + c.Pa - 1) / c.Pa;
+}
+
+// Host copies of the tables uploaded for single-lattice calls, kept alive per
+// workspace so that an asynchronous copy never reads freed host memory.
+struct HostTables {
+  std::vector<InstDev> inst;
+  std::vector<int2> cmap;
+};
+std::map<const void*, HostTables> g_tables;
+std::mutex g_tables_mu;
+
+int upload_from(const std::vector<InstDev>& inst, const std::vector<int2>& cmap, InstDev* d_inst,
+                int2* d_cmap, hipStream_t s) {
+  KPM_HIP(hipMemcpyAsync(d_inst, inst.data(), sizeof(InstDev) * inst.size(),
+                         hipMemcpyHostToDevice, s));
+  KPM_HIP(hipMemcpyAsync(d_cmap, cmap.data(), sizeof(int2) * cmap.size(), hipMemcpyHostToDevice,
+                         s));
+  return KPM_OK;
+}
+
+// Plans own their tables (Ctx lives as long as the plan).
+int upload(Ctx& c, hipStream_t s) { return upload_from(c.inst, c.cmap, c.d_inst, c.d_cmap, s); }
+
+// Single-lattice calls: copy the tables into the per-workspace host store first.
+int upload_single(Ctx& c, const void* ws, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_tables_mu);
+  HostTables& t = g_tables[ws];
+  // a copy from pageable memory is staged before hipMemcpyAsync returns, so
+  // the previous upload from this store no longer reads it
+  t.inst = c.inst;
+  t.cmap = c.cmap;
+  return upload_from(t.inst, t.cmap, c.d_inst, c.d_cmap, s);
+}
+
+int run_forward(const Ctx& c, bool ckpt, int nsteps, hipStream_t s) {
+  const int ninst = (int)c.inst.size();
+  hipLaunchKernelGGL(k_set_status, dim3((ninst + 63) / 64), dim3(64), 0, s, c.d_inst, ninst, 0);
+  KPM_HIP(hipGetLastError());
+  KPM_HIP(launch_rescale(c.d_inst, c.d_cmap, c.nch(), c.fp32, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_cmap, c.nch(), c.npbf(), 0, c.M, c.k,
+                      ckpt ? 1 : 0, s));
+  for (int m = 0; m + 1 < nsteps; ++m)
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_cmap, c.nch(), c.npbf(), m, c.M, c.k,
+                        ckpt ? 1 : 0, s));
+  return KPM_OK;
+}
+
+int run_moments(const Ctx& c, double* mu_user, hipStream_t s) {
+  int maxRM = 0;
+  for (auto& I : c.inst) maxRM = std::max(maxRM, I.R * c.M);
+  KPM_HIP(launch_mom_reduce(c.d_inst, (int)c.inst.size(), maxRM, c.M, mu_user, s));
+  return KPM_OK;
+}
+
+int run_adjoint(const Ctx& c, hipStream_t s) {
+  const int M = c.M;
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_cmap, c.nch(), c.npba(), 0, M, c.k, 0, s));
+  for (int m = M - 3; m >= 0; --m)
+    KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_cmap, c.nch(), c.npba(), m, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_cmap, c.nch(), c.npba(), 0, M, c.k, 1, s));
+  KPM_HIP(launch_rho(c.d_inst, c.d_cmap, c.nch(), s));
+  return KPM_OK;
+}
+
+// ------------------------------------------------------------ single lattice
+// Workspace = [InstDev][cmap][instance buffers].
+struct WsLayout {
+  size_t off_inst, off_cmap, off_buf, total;
+};
+
+WsLayout ws_layout(const Sizes& z) {
+  WsLayout w{};
+  size_t o = 0;
+  w.off_inst = o; o = align_up(o + sizeof(InstDev));
+  w.off_cmap = o; o = align_up(o + sizeof(int2) * z.nchunk);
+  w.off_buf = o;  o += inst_bytes(z);
+  w.total = o;
+  return w;
+}
+
+struct FwdSig {
+  const double* h;
+  const double* ab;
+  const double* C;
+  int M, R, prec, k;
+};
+std::map<const void*, FwdSig> g_fwd;
+
+int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* ab,
+                   const kpm_probes* pr, int M, const double* C, int prec, int k, void* ws,
+                   size_t ws_bytes) {
+  if (!valid_lattice(L) || !h || !ab || !ws) return KPM_EINVAL;
+  if (M < 2 || k < 2) return KPM_EINVAL;
+  if (prec != KPM_FP64 && prec != KPM_FP32) return KPM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return KPM_EINVAL;
+  InstDev I;
+  std::memset(&I, 0, sizeof(I));
+  int ng = 0;
+  const int R = build_groups(L, pr, I.g, &ng);
+  if (R < 1) return KPM_EINVAL;
+  c.fp32 = prec == KPM_FP32;
+  const Sizes z = sizes(L, R, M, k, c.fp32);
+  const WsLayout w = ws_layout(z);
+  if (ws_bytes < w.total) return KPM_EWORKSPACE;
+  char* base = static_cast<char*>(ws);
+  I.Lx = L->Lx;
+  I.Ly = L->Ly;
+  I.N = z.N;
+  I.R = R;
+  I.nchunk = z.nchunk;
+  I.ngroups = ng;
+  I.h = reinterpret_cast<const double2*>(h);
+  I.ab = ab;
+  I.C = C;
+  carve(I, z, base + w.off_buf);
+  c.inst.assign(1, I);
+  c.d_inst = reinterpret_cast<InstDev*>(base + w.off_inst);
+  c.d_cmap = reinterpret_cast<int2*>(base + w.off_cmap);
+  c.M = M;
+  c.k = k;
+  finish_ctx(c);
+  int P;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    P = g_probe_block;
+  }
+  c.Pf = P ? P : auto_probe_block(c.sites, c.Rmax, c.fp32, false);
+  c.Pa = P ? P : auto_probe_block(c.sites, c.Rmax, c.fp32, true);
+  set_npb(c);
+  return KPM_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ batch plans
+struct KpmBatchPlan {
+  Ctx c;
+  void* mem = nullptr;
+  hipStream_t capture_stream = nullptr;   // graphs are captured here, launched on the caller's
+  bool tuned = false;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::vector<const void*> graph_ptrs;   // pointers the captured graph was built with
+};
+
+namespace {
+
+std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+std::string shape_key(const Ctx& c) {
+  std::string key = std::to_string(c.M) + (c.fp32 ? "f" : "d");
+  for (auto& I : c.inst) key += ":" + std::to_string(I.N) + "x" + std::to_string(I.R);
+  return key;
+}
+
+// Times a few forward steps and a few adjoint steps for each candidate block.
+int autotune(KpmBatchPlan* pl, hipStream_t s) {
+  Ctx& c = pl->c;
+  const std::string key = shape_key(c);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c.Pf = it->second.first;
+      c.Pa = it->second.second;
+      set_npb(c);
+      pl->tuned = true;
+      return upload(c, s);
+    }
+  }
+  hipEvent_t e0, e1;
+  KPM_HIP(hipEventCreate(&e0));
+  KPM_HIP(hipEventCreate(&e1));
+  const int steps = std::min(c.M, 8);
+  float best_f = 1e30f, best_a = 1e30f;
+  int Pf = 1, Pa = 1;
+  for (int P : {2, 4, 8, 16}) {
+    c.Pf = P;
+    c.Pa = std::min(P, 8);
+    set_npb(c);
+    int st = upload(c, s);
+    if (st != KPM_OK) return st;
+    // forward: warm once, then time
+    for (int rep = 0; rep < 2; ++rep) {
+      KPM_HIP(hipEventRecord(e0, s));
+      st = run_forward(c, false, steps, s);
+      if (st != KPM_OK) return st;
+      KPM_HIP(hipEventRecord(e1, s));
+    }
+    KPM_HIP(hipEventSynchronize(e1));
+    float tf = 0.f;
+    KPM_HIP(hipEventElapsedTime(&tf, e0, e1));
+    if (tf < best_f) {
+      best_f = tf;
+      Pf = P;
+    }
+    if (P <= 8 && c.M >= 3) {
+      // adjoint steps on whatever the buffers hold (timing only; m = M-3 >= 0)
+      KPM_HIP(hipEventRecord(e0, s));
+      KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_cmap, c.nch(), c.npba(), 0, c.M, c.k, 0, s));
+      for (int q = 0; q < steps; ++q)
+        KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_cmap, c.nch(), c.npba(), c.M - 3, c.M,
+                            c.M + 1, 0, s));
+      KPM_HIP(hipEventRecord(e1, s));
+      KPM_HIP(hipEventSynchronize(e1));
+      float ta = 0.f;
+      KPM_HIP(hipEventElapsedTime(&ta, e0, e1));
+      if (ta < best_a) {
+        best_a = ta;
+        Pa = P;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c.Pf = Pf;
+  c.Pa = Pa;
+  set_npb(c);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune_cache[key] = {Pf, Pa};
+  }
+  pl->tuned = true;
+  return upload(c, s);
+}
+
+int batch_sequence(KpmBatchPlan* pl, hipStream_t s) {
+  Ctx& c = pl->c;
+  int st = run_forward(c, true, c.M, s);
+  if (st != KPM_OK) return st;
+  if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
+  KPM_HIP(launch_omega(c.d_inst, (int)c.inst.size(), c.M, s));
+  return run_adjoint(c, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t kpm_probe_count(const kpm_lattice* lat, const kpm_probes* probes) {
+  if (!valid_lattice(lat)) return KPM_EINVAL;
+  int R = build_groups(lat, probes, nullptr, nullptr);
+  return R < 1 ? KPM_EINVAL : R;
+}
+
+int kpm_build_H(const kpm_lattice* lat, const kpm_model* model, const double* n, const double* chi,
+                const double* delta, double* h, void* stream) {
+  if (!valid_lattice(lat) || !model || !n || !chi || !delta || !h) return KPM_EINVAL;
+  ModelDev md{lat->Lx, lat->Ly, lat->n_vortex, lat->Lx * lat->Ly, model->t, model->tp, model->J,
+              model->mu};
+  KPM_HIP(launch_build_h(md, n, chi, delta, h, static_cast<hipStream_t>(stream)));
+  return KPM_OK;
+}
+
+int kpm_build_H_vjp(const kpm_lattice* lat, const kpm_model* model, const double* n,
+                    const double* chi, const double* delta, const double* rho, double* dn,
+                    double* dchi, double* ddelta, void* stream) {
+  if (!valid_lattice(lat) || !model || !n || !chi || !delta || !rho || !dn || !dchi || !ddelta)
+    return KPM_EINVAL;
+  ModelDev md{lat->Lx, lat->Ly, lat->n_vortex, lat->Lx * lat->Ly, model->t, model->tp, model->J,
+              model->mu};
+  KPM_HIP(launch_build_vjp(md, n, chi, delta, rho, dn, dchi, ddelta,
+                           static_cast<hipStream_t>(stream)));
+  return KPM_OK;
+}
+
+int kpm_bounds(const kpm_lattice* lat, const double* h, double* ab, void* stream) {
+  if (!valid_lattice(lat) || !h || !ab) return KPM_EINVAL;
+  KPM_HIP(launch_bounds(lat->Lx, lat->Ly, h, ab, static_cast<hipStream_t>(stream)));
+  return KPM_OK;
+}
+
+int kpm_coefficients(int32_t M, double T, const double* ab, int32_t K, double* C, void* stream) {
+  if (M < 2 || !(T > 0.0) || !std::isfinite(T) || !ab || !C || K < 0) return KPM_EINVAL;
+  if (K == 0) K = std::max(4 * M, 16384);
+  if (K < M || K > (1 << 28)) return KPM_EINVAL;
+  KPM_HIP(launch_coeffs(M, K, T, ab, C, static_cast<hipStream_t>(stream)));
+  return KPM_OK;
+}
+
+size_t kpm_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int32_t ckpt_k,
+                          int32_t precision) {
+  if (!valid_lattice(lat) || R < 1 || R > kMaxR || M < 2 || ckpt_k < 2) return 0;
+  if (precision != KPM_FP64 && precision != KPM_FP32) return 0;
+  return ws_layout(sizes(lat, R, M, ckpt_k, precision == KPM_FP32)).total;
+}
+
+int kpm_moments(const kpm_lattice* lat, const double* h, const double* ab, const kpm_probes* probes,
+                int32_t M, int32_t precision, int32_t ckpt_k, double* mu, void* ws,
+                size_t ws_bytes, void* stream) {
+  if (!mu) return KPM_EINVAL;
+  Ctx c;
+  int st = prepare_single(c, lat, h, ab, probes, M, nullptr, precision, ckpt_k, ws, ws_bytes);
+  if (st != KPM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+  if ((st = run_forward(c, false, M, s)) != KPM_OK) return st;
+  if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_fwd.erase(ws);
+  return KPM_OK;
+}
+
+int kpm_grand_potential(const kpm_lattice* lat, const double* h, const double* ab,
+                        const kpm_probes* probes, int32_t M, const double* C, int32_t precision,
+                        int32_t ckpt_k, double* omega, double* mu, void* ws, size_t ws_bytes,
+                        void* stream) {
+  if (!C || !omega) return KPM_EINVAL;
+  Ctx c;
+  int st = prepare_single(c, lat, h, ab, probes, M, C, precision, ckpt_k, ws, ws_bytes);
+  if (st != KPM_OK) return st;
+  c.inst[0].omega = omega;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+  if ((st = run_forward(c, true, M, s)) != KPM_OK) return st;
+  if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
+  KPM_HIP(launch_omega(c.d_inst, 1, M, s));
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_fwd[ws] = FwdSig{h, ab, C, M, c.Rmax, precision, ckpt_k};
+  return KPM_OK;
+}
+
+int kpm_grand_potential_grad(const kpm_lattice* lat, const double* h, const double* ab,
+                             const kpm_probes* probes, int32_t M, const double* C,
+                             int32_t precision, int32_t ckpt_k, const double* omega_bar,
+                             double* rho, void* ws, size_t ws_bytes, void* stream) {
+  if (!C || !rho) return KPM_EINVAL;
+  Ctx c;
+  int st = prepare_single(c, lat, h, ab, probes, M, C, precision, ckpt_k, ws, ws_bytes);
+  if (st != KPM_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_fwd.find(ws);
+    if (it == g_fwd.end()) return KPM_EWORKSPACE;
+    const FwdSig& f = it->second;
+    if (f.h != h || f.ab != ab || f.C != C || f.M != M || f.R != c.Rmax || f.prec != precision ||
+        f.k != ckpt_k)
+      return KPM_EWORKSPACE;
+  }
+  c.inst[0].rho = reinterpret_cast<double2*>(rho);
+  c.inst[0].omega_bar = omega_bar;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+  return run_adjoint(c, s);
+}
+
+int kpm_density_matrix(const kpm_lattice* lat, const double* h, const double* ab,
+                       const kpm_probes* probes, int32_t M, const double* C, int32_t precision,
+                       int32_t ckpt_k, double* omega, double* rho, double* n_up, double* n_dn,
+                       double* chi_up, double* chi_dn, double* delta_up, double* delta_dn,
+                       void* ws, size_t ws_bytes, void* stream) {
+  int st = kpm_grand_potential(lat, h, ab, probes, M, C, precision, ckpt_k, omega, nullptr, ws,
+                               ws_bytes, stream);
+  if (st != KPM_OK) return st;
+  st = kpm_grand_potential_grad(lat, h, ab, probes, M, C, precision, ckpt_k, nullptr, rho, ws,
+                                ws_bytes, stream);
+  if (st != KPM_OK) return st;
+  KPM_HIP(launch_map(lat->Lx * lat->Ly, rho, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn,
+                     static_cast<hipStream_t>(stream)));
+  return KPM_OK;
+}
+
+int kpm_status_read(const void* ws, int32_t* status, void* stream) {
+  if (!ws || !status) return KPM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the status word is the first field of the instance buffers
+  InstDev I;
+  KPM_HIP(hipMemcpyAsync(&I, ws, sizeof(InstDev), hipMemcpyDeviceToHost, s));
+  KPM_HIP(hipStreamSynchronize(s));
+  int v = 0;
+  if (I.status) {
+    KPM_HIP(hipMemcpyAsync(&v, I.status, sizeof(int), hipMemcpyDeviceToHost, s));
+    KPM_HIP(hipStreamSynchronize(s));
+  }
+  *status = v;
+  return KPM_OK;
+}
+
+int32_t kpm_set_probe_block(int32_t probes_per_thread) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int32_t old = g_probe_block;
+  if (probes_per_thread == 0 || valid_P(probes_per_thread)) g_probe_block = probes_per_thread;
+  return old;
+}
+
+int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* probes, int32_t M,
+                     int32_t precision, int32_t ckpt_k, void** plan) {
+  if (n_inst < 1 || !lats || !probes || !plan || M < 2 || ckpt_k < 2) return KPM_EINVAL;
+  if (precision != KPM_FP64 && precision != KPM_FP32) return KPM_EINVAL;
+  const bool fp32 = precision == KPM_FP32;
+  std::vector<Sizes> zs(n_inst);
+  std::vector<InstDev> insts(n_inst);
+  size_t total = align_up(sizeof(InstDev) * n_inst);
+  size_t nch = 0;
+  for (int q = 0; q < n_inst; ++q) {
+    if (!valid_lattice(&lats[q])) return KPM_EINVAL;
+    std::memset(&insts[q], 0, sizeof(InstDev));
+    int ng = 0;
+    const int R = build_groups(&lats[q], &probes[q], insts[q].g, &ng);
+    if (R < 1) return KPM_EINVAL;
+    zs[q] = sizes(&lats[q], R, M, ckpt_k, fp32);
+    insts[q].Lx = lats[q].Lx;
+    insts[q].Ly = lats[q].Ly;
+    insts[q].N = zs[q].N;
+    insts[q].R = R;
+    insts[q].nchunk = zs[q].nchunk;
+    insts[q].ngroups = ng;
+    nch += zs[q].nchunk;
+    total += inst_bytes(zs[q]);
+  }
+  total += align_up(sizeof(int2) * nch);
+  auto* pl = new (std::nothrow) KpmBatchPlan();
+  if (!pl) return KPM_ENOMEM;
+  if (hipMalloc(&pl->mem, total) != hipSuccess) {
+    delete pl;
+    return KPM_ENOMEM;
+  }
+  char* base = static_cast<char*>(pl->mem);
+  pl->c.d_inst = reinterpret_cast<InstDev*>(base);
+  char* o = base + align_up(sizeof(InstDev) * n_inst);
+  pl->c.d_cmap = reinterpret_cast<int2*>(o);
+  o += align_up(sizeof(int2) * nch);
+  for (int q = 0; q < n_inst; ++q) {
+    carve(insts[q], zs[q], o);
+    o += inst_bytes(zs[q]);
+  }
+  pl->c.inst = insts;
+  pl->c.M = M;
+  pl->c.k = ckpt_k;
+  pl->c.fp32 = fp32;
+  finish_ctx(pl->c);
+  int P;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    P = g_probe_block;
+  }
+  pl->c.Pf = P ? P : auto_probe_block(pl->c.sites, pl->c.Rmax, fp32, false);
+  pl->c.Pa = P ? P : auto_probe_block(pl->c.sites, pl->c.Rmax, fp32, true);
+  pl->tuned = P != 0;
+  set_npb(pl->c);
+  *plan = pl;
+  return KPM_OK;
+}
+
+int kpm_batch_energy_grad(void* plan, const double* const* h, const double* const* ab,
+                          const double* const* C, double* omega, double* const* rho,
+                          int32_t use_graph, void* stream) {
+  auto* pl = static_cast<KpmBatchPlan*>(plan);
+  if (!pl || !h || !ab || !C || !omega || !rho) return KPM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ctx& c = pl->c;
+  const int n = (int)c.inst.size();
+  std::vector<const void*> ptrs;
+  for (int q = 0; q < n; ++q) {
+    if (!h[q] || !ab[q] || !C[q] || !rho[q]) return KPM_EINVAL;
+    c.inst[q].h = reinterpret_cast<const double2*>(h[q]);
+    c.inst[q].ab = ab[q];
+    c.inst[q].C = C[q];
+    c.inst[q].omega = omega + q;
+    c.inst[q].rho = reinterpret_cast<double2*>(rho[q]);
+    c.inst[q].omega_bar = nullptr;
+    ptrs.insert(ptrs.end(), {h[q], ab[q], C[q], omega + q, rho[q]});
+  }
+  int st;
+  if (!pl->tuned) {
+    if ((st = upload(c, s)) != KPM_OK) return st;
+    if ((st = autotune(pl, s)) != KPM_OK) return st;
+  }
+  if ((st = upload(c, s)) != KPM_OK) return st;
+  if (!use_graph) return batch_sequence(pl, s);
+  if (pl->exec && pl->graph_ptrs != ptrs) {
+    (void)hipGraphExecDestroy(pl->exec);
+    (void)hipGraphDestroy(pl->graph);
+    pl->exec = nullptr;
+    pl->graph = nullptr;
+  }
+  if (!pl->exec) {
+    // The captured kernels read the instance table from device memory, so the
+    // graph stays valid as long as the table is re-uploaded before each replay.
+    // Capture on a private stream (the caller's may be the null stream, which
+    // cannot be captured); nothing runs during capture.
+    if (!pl->capture_stream) KPM_HIP(hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = pl->capture_stream;
+    KPM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    st = batch_sequence(pl, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st != KPM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return KPM_EDEVICE;
+    pl->graph = g;
+    KPM_HIP(hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0));
+    pl->graph_ptrs = ptrs;
+  }
+  KPM_HIP(hipGraphLaunch(pl->exec, s));
+  return KPM_OK;
+}
+
+int kpm_batch_destroy(void* plan) {
+  auto* pl = static_cast<KpmBatchPlan*>(plan);
+  if (!pl) return KPM_EINVAL;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
+  if (pl->mem) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(pl->mem);
+  }
+  delete pl;
+  return KPM_OK;
+}
+
+int kpm_profile_begin(void) {
+  KPM_HIP(profile_begin());
+  return KPM_OK;
+}
+
+int kpm_profile_end(double* fwd_ms, int32_t* n_fwd, double* adj_ms, int32_t* n_adj) {
+  if (!fwd_ms || !n_fwd || !adj_ms || !n_adj) return KPM_EINVAL;
+  int nf = 0, na = 0;
+  KPM_HIP(profile_end(fwd_ms, &nf, adj_ms, &na));
+  *n_fwd = nf;
+  *n_adj = na;
+  return KPM_OK;
+}
+
+const char* kpm_strerror(int status) {
+  switch (status) {
+    case KPM_OK: return "ok";
+    case KPM_EINVAL: return "invalid argument";
+    case KPM_ENOMEM: return "out of device memory";
+    case KPM_EDEVICE: return "HIP runtime error";
+    case KPM_EBOUNDS: return "spectrum outside the rescaled interval or non-finite value";
+    case KPM_ENOTSUP: return "not supported";
+    case KPM_EWORKSPACE: return "workspace too small or not prepared by the forward call";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,373 @@
+// Element-wise kernels around the recursion: the TB-BdG builder and its VJP,
+// Gershgorin bounds, the rescaled row-form coefficients and the Chebyshev
+// expansion coefficients of the grand-potential density.
+#include "kpm_internal.h"
+
+namespace kpm {
+
+// ---------------------------------------------------------------- geometry
+__device__ __forceinline__ void dir_step(int d, int& dx, int& dy) {
+  dx = (d == 1) ? 0 : 1;
+  dy = (d == 0) ? 0 : ((d == 3) ? -1 : 1);
+}
+
+// Peierls phase of bond (x, y) -> (x + dx, y + dy): the Landau-gauge line
+// integral -(pi/Phi0) int A.dl with A = B(0, x), B = nv Phi0/(Lx Ly), along the
+// straight segment, plus the gauge twist pi nv y_head/Ly on +x steps that
+// cross the x seam (makes the flux uniform on the torus, nv even).
+__device__ __forceinline__ double peierls(int x, int y, int d, int Lx, int Ly, int nv) {
+  int dx, dy;
+  dir_step(d, dx, dy);
+  double xm = (double)x + 0.5 * (double)dx;
+  double phi = -M_PI * (double)nv * xm * (double)dy / ((double)Lx * (double)Ly);
+  if (x + dx == Lx) {
+    int yh = y + dy;
+    yh = (yh < 0) ? yh + Ly : (yh >= Ly ? yh - Ly : yh);
+    phi += M_PI * (double)nv * (double)yh / (double)Ly;
+  }
+  return phi;
+}
+
+__device__ __forceinline__ int nbr_of(int i, int d, int sign, int Lx, int Ly) {
+  int y = i / Lx, x = i - y * Lx;
+  int dx, dy;
+  dir_step(d, dx, dy);
+  x += sign * dx;
+  y += sign * dy;
+  x = (x < 0) ? x + Lx : (x >= Lx ? x - Lx : x);
+  y = (y < 0) ? y + Ly : (y >= Ly ? y - Ly : y);
+  return y * Lx + x;
+}
+
+// Gutzwiller factors at m = 0 (App. A) and their derivatives in delta.
+struct GF {
+  double g, g1, g2;      // g = sqrt(2 d/(1+d)), g', g''
+  double s, s1, s2;      // g^s = 2/(1+d), g^s', g^s''
+};
+
+__device__ __forceinline__ GF gfac(double n) {
+  double d = 1.0 - n;
+  double q = 1.0 + d;
+  GF f;
+  double u = 2.0 * d / q, u1 = 2.0 / (q * q), u2 = -4.0 / (q * q * q);
+  f.g = sqrt(u);
+  f.g1 = u1 / (2.0 * f.g);
+  f.g2 = u2 / (2.0 * f.g) - u1 * u1 / (4.0 * f.g * f.g * f.g);
+  f.s = 2.0 / q;
+  f.s1 = -2.0 / (q * q);
+  f.s2 = 4.0 / (q * q * q);
+  return f;
+}
+
+__device__ __forceinline__ double2 hop(const ModelDev& md, int i, int d) {
+  int y = i / md.Lx, x = i - y * md.Lx;
+  double phi = peierls(x, y, d, md.Lx, md.Ly, md.nv);
+  double s, c;
+  sincos(phi, &s, &c);
+  double amp = (d < 2) ? md.t : md.tp;
+  return make_double2(amp * c, amp * s);
+}
+
+__device__ __forceinline__ double2 ld2(const double* p, long long idx) {
+  return reinterpret_cast<const double2*>(p)[idx];
+}
+
+// h = dW/drho on the stencil (see kpm_build_H in kpm.h).
+__global__ __launch_bounds__(kBlock) void k_build_h(ModelDev md, const double* __restrict__ n,
+                                                    const double* __restrict__ chi,
+                                                    const double* __restrict__ dlt,
+                                                    double2* __restrict__ h) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= md.N) return;
+  const int N = md.N;
+  GF fi = gfac(n[i]);
+  double eps = -md.mu;
+  for (int d = 0; d < 4; ++d) {
+    // forward bond (i, j = i + d), stored here
+    int j = nbr_of(i, d, +1, md.Lx, md.Ly);
+    GF fj = gfac(n[j]);
+    double2 t = hop(md, i, d);
+    double2 c = ld2(chi, (long long)d * N + i);
+    double2 D = ld2(dlt, (long long)d * N + i);
+    double gt = fi.g * fj.g;
+    double2 T = make_double2(-gt * t.x, -gt * t.y);
+    double2 P = make_double2(0.0, 0.0);
+    double R = t.x * c.x - t.y * c.y;                 // Re(t chi)
+    eps += 4.0 * fi.g1 * fj.g * R;
+    if (d < 2) {
+      double cb = 0.75 * md.J * fi.s * fj.s;
+      T.x -= cb * c.x;                                // - c conj(chi)
+      T.y += cb * c.y;
+      P = make_double2(cb * D.x, cb * D.y);
+      double Q = c.x * c.x + c.y * c.y + D.x * D.x + D.y * D.y;
+      eps += 1.5 * md.J * fi.s1 * fj.s * Q;
+    }
+    h[(long long)(4 * d + 0) * N + i] = T;
+    h[(long long)(4 * d + 1) * N + i] = P;
+    h[(long long)(4 * d + 2) * N + i] = make_double2(P.x, -P.y);
+    h[(long long)(4 * d + 3) * N + i] = make_double2(-T.x, T.y);
+    // backward bond (k = i - d, i), stored at k: its energy terms touch i too
+    int k = nbr_of(i, d, -1, md.Lx, md.Ly);
+    GF fk = gfac(n[k]);
+    double2 tb = hop(md, k, d);
+    double2 cbk = ld2(chi, (long long)d * N + k);
+    double2 Dbk = ld2(dlt, (long long)d * N + k);
+    eps += 4.0 * fi.g1 * fk.g * (tb.x * cbk.x - tb.y * cbk.y);
+    if (d < 2) {
+      double Q = cbk.x * cbk.x + cbk.y * cbk.y + Dbk.x * Dbk.x + Dbk.y * Dbk.y;
+      eps += 1.5 * md.J * fi.s1 * fk.s * Q;
+    }
+  }
+  h[(long long)16 * N + i] = make_double2(eps, 0.0);
+  h[(long long)17 * N + i] = make_double2(-eps, 0.0);
+  h[(long long)18 * N + i] = make_double2(0.0, 0.0);
+}
+
+// Per-site pieces of the VJP that every neighbour needs: w_i = Re rho16 -
+// Re rho17 (weight of eps_i in the linearised energy).
+__device__ __forceinline__ double onsite_w(const double2* rho, int N, int i) {
+  return rho[(long long)16 * N + i].x - rho[(long long)17 * N + i].x;
+}
+
+// dOmega/dtheta = sum_IJ rho_IJ dh_IJ/dtheta.  With the linearisation
+//   L = sum_b [2 Re(T_b U_b) + 2 Re(P_b V_b)] + sum_i w_i eps_i,
+//   U_b = rho_{e0} - conj(rho_{e3}),  V_b = rho_{e1} + conj(rho_{e2}),
+// the bond and site gradients are gathered per site from its 8 bonds.
+__global__ __launch_bounds__(kBlock) void k_build_vjp(ModelDev md, const double* __restrict__ n,
+                                                      const double* __restrict__ chi,
+                                                      const double* __restrict__ dlt,
+                                                      const double2* __restrict__ rho,
+                                                      double* __restrict__ dn,
+                                                      double2* __restrict__ dchi,
+                                                      double2* __restrict__ ddlt) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= md.N) return;
+  const int N = md.N;
+  const double J = md.J;
+  GF fi = gfac(n[i]);
+  double wi = onsite_w(rho, N, i);
+  double dLdd = 0.0;          // dL/d delta_i
+  double deps_self = 0.0;     // d eps_i / d delta_i
+  for (int d = 0; d < 4; ++d) {
+    for (int side = 0; side < 2; ++side) {
+      // side 0: bond (i, o = i + d) stored at i;  side 1: bond (o = i - d, i) stored at o
+      int o = nbr_of(i, d, side == 0 ? +1 : -1, md.Lx, md.Ly);
+      int tail = (side == 0) ? i : o;
+      GF fo = gfac(n[o]);
+      double wo = onsite_w(rho, N, o);
+      double2 t = hop(md, tail, d);
+      double2 c = ld2(chi, (long long)d * N + tail);
+      double2 D = ld2(dlt, (long long)d * N + tail);
+      double2 r0 = rho[(long long)(4 * d + 0) * N + tail];
+      double2 r1 = rho[(long long)(4 * d + 1) * N + tail];
+      double2 r2 = rho[(long long)(4 * d + 2) * N + tail];
+      double2 r3 = rho[(long long)(4 * d + 3) * N + tail];
+      double2 U = make_double2(r0.x - r3.x, r0.y + r3.y);
+      double2 V = make_double2(r1.x + r2.x, r1.y - r2.y);
+      double R = t.x * c.x - t.y * c.y;
+      double Q = c.x * c.x + c.y * c.y + D.x * D.x + D.y * D.y;
+      bool nn = d < 2;
+      // dT/d delta_i = -g_i' g_o t - [nn] (3/4) J s_i' s_o conj(chi);  dP/d delta_i = [nn] (3/4) J s_i' s_o Delta
+      double2 dT = make_double2(-fi.g1 * fo.g * t.x, -fi.g1 * fo.g * t.y);
+      double2 dP = make_double2(0.0, 0.0);
+      if (nn) {
+        double k3 = 0.75 * J * fi.s1 * fo.s;
+        dT.x -= k3 * c.x;
+        dT.y += k3 * c.y;
+        dP = make_double2(k3 * D.x, k3 * D.y);
+      }
+      dLdd += 2.0 * (dT.x * U.x - dT.y * U.y) + 2.0 * (dP.x * V.x - dP.y * V.y);
+      deps_self += 4.0 * fi.g2 * fo.g * R + (nn ? 1.5 * J * fi.s2 * fo.s * Q : 0.0);
+      // eps_o depends on delta_i through this bond
+      dLdd += wo * (4.0 * fo.g1 * fi.g1 * R + (nn ? 1.5 * J * fo.s1 * fi.s1 * Q : 0.0));
+      if (side == 0) {
+        // gradients of the bond variables stored at i
+        double cb = nn ? 0.75 * J * fi.s * fo.s : 0.0;
+        double kt = 4.0 * (wi * fi.g1 * fo.g + wo * fo.g1 * fi.g);     // * conj(t)
+        double kq = nn ? 3.0 * J * (wi * fi.s1 * fo.s + wo * fo.s1 * fi.s) : 0.0;
+        double2 gc = make_double2(-2.0 * cb * U.x + kt * t.x + kq * c.x,
+                                  -2.0 * cb * U.y - kt * t.y + kq * c.y);
+        double2 gd = nn ? make_double2(2.0 * cb * V.x + kq * D.x, -2.0 * cb * V.y + kq * D.y)
+                        : make_double2(0.0, 0.0);
+        dchi[(long long)d * N + i] = gc;
+        ddlt[(long long)d * N + i] = gd;
+      }
+    }
+  }
+  dLdd += wi * deps_self;
+  dn[i] = -dLdd;
+}
+
+// Gershgorin bounds -> ab = (a, b); one block.  On a non-finite or empty
+// interval a is set to NaN (the recursion then reports KPM_EBOUNDS).
+__global__ __launch_bounds__(kBlock) void k_bounds(int Lx, int Ly, const double2* __restrict__ h,
+                                                   double* __restrict__ ab) {
+  const int N = Lx * Ly;
+  double emax = -1e300, emin = 1e300;
+  int finite = 1;
+  for (int i = threadIdx.x; i < N; i += kBlock) {
+    double r0 = 0.0, r1 = 0.0;
+    double2 p = h[(long long)18 * N + i];
+    double ap = hypot(p.x, p.y);
+    r0 += ap;
+    r1 += ap;
+    for (int d = 0; d < 4; ++d) {
+      int j = nbr_of(i, d, -1, Lx, Ly);
+      double2 f0 = h[(long long)(4 * d + 0) * N + i], f1 = h[(long long)(4 * d + 1) * N + i];
+      double2 f2 = h[(long long)(4 * d + 2) * N + i], f3 = h[(long long)(4 * d + 3) * N + i];
+      double2 b0 = h[(long long)(4 * d + 0) * N + j], b1 = h[(long long)(4 * d + 1) * N + j];
+      double2 b2 = h[(long long)(4 * d + 2) * N + j], b3 = h[(long long)(4 * d + 3) * N + j];
+      // row (i,0): (i0,j'b) forward entries 00, 01 and backward conj(B_{b0}(j)): 00, 10
+      r0 += hypot(f0.x, f0.y) + hypot(f1.x, f1.y) + hypot(b0.x, b0.y) + hypot(b2.x, b2.y);
+      // row (i,1): forward 11, 10 and backward conj(B_{b1}(j)): 11, 01 -- summed in the
+      // order that mirrors row (i,0), so a particle-hole symmetric h gets Emin = -Emax exactly
+      r1 += hypot(f3.x, f3.y) + hypot(f2.x, f2.y) + hypot(b3.x, b3.y) + hypot(b1.x, b1.y);
+    }
+    double c0 = h[(long long)16 * N + i].x, c1 = h[(long long)17 * N + i].x;
+    emax = fmax(emax, fmax(c0 + r0, c1 + r1));
+    emin = fmin(emin, fmin(c0 - r0, c1 - r1));
+    if (!(isfinite(c0 + r0) && isfinite(c1 + r1) && isfinite(c0 - r0) && isfinite(c1 - r1))) finite = 0;
+  }
+  __shared__ double smax[kBlock], smin[kBlock];
+  __shared__ int sfin[kBlock];
+  smax[threadIdx.x] = emax;
+  smin[threadIdx.x] = emin;
+  sfin[threadIdx.x] = finite;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      sfin[threadIdx.x] = sfin[threadIdx.x] & sfin[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double a = (smax[0] - smin[0]) / (2.0 - 0.01);
+    double b = (smax[0] + smin[0]) / 2.0;
+    if (!sfin[0] || !(a > 0.0) || !isfinite(a)) a = __builtin_nan("");
+    ab[0] = a;
+    ab[1] = b;
+  }
+}
+
+// Row-form rescaled coefficients H~ = (h - b)/a for the recursion kernels.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_rescale(const InstDev* __restrict__ insts,
+                                                    const int2* __restrict__ cmap) {
+  const int2 cm = cmap[blockIdx.x];
+  const InstDev& I = insts[cm.x];
+  int i = cm.y + threadIdx.x;
+  if (i >= I.N) return;
+  const int N = I.N;
+  const double2* h = I.h;
+  const double a = I.ab[0], b = I.ab[1];
+  const double ia = 1.0 / a;
+  V* out = reinterpret_cast<V*>(I.coef);
+  auto put = [&](int slot, double re, double im) {
+    out[2 * ((long long)slot * N + i) + 0] = (V)re;
+    out[2 * ((long long)slot * N + i) + 1] = (V)im;
+  };
+  double2 p = h[(long long)18 * N + i];
+  put(0, (h[(long long)16 * N + i].x - b) * ia, 0.0);
+  put(1, p.x * ia, p.y * ia);
+  put(18, p.x * ia, -p.y * ia);
+  put(19, (h[(long long)17 * N + i].x - b) * ia, 0.0);
+  for (int d = 0; d < 4; ++d) {
+    int j = nbr_of(i, d, -1, I.Lx, I.Ly);
+    for (int al = 0; al < 2; ++al) {
+      for (int be = 0; be < 2; ++be) {
+        double2 f = h[(long long)(4 * d + 2 * al + be) * N + i];
+        put(18 * al + 2 * (1 + d) + be, f.x * ia, f.y * ia);
+        double2 r = h[(long long)(4 * d + 2 * be + al) * N + j];   // H~_{(i,al),(j,be)} = conj(B_{be al}(j))/a
+        put(18 * al + 2 * (5 + d) + be, r.x * ia, -r.y * ia);
+      }
+    }
+  }
+}
+
+template __global__ void k_rescale<float>(const InstDev*, const int2*);
+template __global__ void k_rescale<double>(const InstDev*, const int2*);
+
+// C_m = (2 - delta_m0) g_m (1/K) sum_k cos(m th_k) f(a cos th_k + b).
+// cos(m th_k) = cospi(j/(2K)) with the exact integer j = m(2k+1) mod 4K.
+__global__ __launch_bounds__(kBlock) void k_coeffs(int M, int K, double T,
+                                                   const double* __restrict__ ab,
+                                                   double* __restrict__ C) {
+  __shared__ double F[kBlock];
+  const int m = blockIdx.x * kBlock + threadIdx.x;
+  const double a = ab[0], b = ab[1];
+  const long long fourK = 4LL * K;
+  const double inv2K = 1.0 / (2.0 * (double)K);
+  double acc = 0.0;
+  long long j = m % fourK;                      // m (2k + 1) for k = 0
+  const long long step = (2LL * m) % fourK;
+  for (int k0 = 0; k0 < K; k0 += kBlock) {
+    int k = k0 + threadIdx.x;
+    if (k < K) {
+      double x = cospi((2.0 * k + 1.0) * inv2K);
+      double e = a * x + b;
+      F[threadIdx.x] = fmin(e, 0.0) - T * log1p(exp(-fabs(e) / T));
+    }
+    __syncthreads();
+    int kmax = min(kBlock, K - k0);
+    for (int kk = 0; kk < kmax; ++kk) {
+      acc += F[kk] * cospi((double)j * inv2K);
+      j += step;
+      if (j >= fourK) j -= fourK;
+    }
+    __syncthreads();
+  }
+  if (m < M) {
+    double c = acc / (double)K;
+    double q = 1.0 / (double)(M + 1);
+    double g = ((double)(M - m + 1) * cospi(m * q) + sinpi(m * q) * cospi(q) / sinpi(q)) * q;
+    C[m] = (m == 0 ? 1.0 : 2.0) * g * c;
+  }
+}
+
+}  // namespace kpm
+
+// ------------------------------------------------------------------ launchers
+namespace kpm {
+
+hipError_t launch_build_h(const ModelDev& md, const double* n, const double* chi,
+                          const double* dlt, double* h, hipStream_t s) {
+  dim3 grid((md.N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_build_h, grid, dim3(kBlock), 0, s, md, n, chi, dlt,
+                     reinterpret_cast<double2*>(h));
+  return hipGetLastError();
+}
+
+hipError_t launch_build_vjp(const ModelDev& md, const double* n, const double* chi,
+                            const double* dlt, const double* rho, double* dn, double* dchi,
+                            double* ddlt, hipStream_t s) {
+  dim3 grid((md.N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_build_vjp, grid, dim3(kBlock), 0, s, md, n, chi, dlt,
+                     reinterpret_cast<const double2*>(rho), dn, reinterpret_cast<double2*>(dchi),
+                     reinterpret_cast<double2*>(ddlt));
+  return hipGetLastError();
+}
+
+hipError_t launch_bounds(int Lx, int Ly, const double* h, double* ab, hipStream_t s) {
+  hipLaunchKernelGGL(k_bounds, dim3(1), dim3(kBlock), 0, s, Lx, Ly,
+                     reinterpret_cast<const double2*>(h), ab);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescale(const InstDev* insts, const int2* cmap, int nchunks, bool fp32,
+                          hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_rescale<float>, dim3(nchunks), dim3(kBlock), 0, s, insts, cmap);
+  else
+    hipLaunchKernelGGL(k_rescale<double>, dim3(nchunks), dim3(kBlock), 0, s, insts, cmap);
+  return hipGetLastError();
+}
+
+hipError_t launch_coeffs(int M, int K, double T, const double* ab, double* C, hipStream_t s) {
+  dim3 grid((M + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_coeffs, grid, dim3(kBlock), 0, s, M, K, T, ab, C);
+  return hipGetLastError();
+}
+
+}  // namespace kpm

@@ -1,0 +1,318 @@
+"""Thin Python binding of the C ABI in include/kpm.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of the method: it checks tensor dtypes/devices/shapes, passes raw
+device pointers and the current HIP stream, and raises ``KpmError`` on a
+nonzero status.  Tensors are torch tensors on the GPU: real arrays float64,
+complex arrays complex128 (interleaved re/im, as the ABI expects).
+
+If libkpm.so is missing, importing this module raises ImportError: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_size_t, c_uint64, c_void_p
+from dataclasses import dataclass
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkpm.so")
+
+KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_EBOUNDS, KPM_ENOTSUP, KPM_EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
+KPM_FP64, KPM_FP32 = 0, 1
+KPM_PROBE_UNIT, KPM_PROBE_DENSE_Z4, KPM_PROBE_COLORED_Z4 = 0, 1, 2
+NENT = 19
+
+EXPORTS = (
+    "kpm_probe_count", "kpm_build_H", "kpm_build_H_vjp", "kpm_bounds", "kpm_coefficients",
+    "kpm_workspace_size", "kpm_moments", "kpm_grand_potential", "kpm_grand_potential_grad",
+    "kpm_density_matrix", "kpm_status_read", "kpm_batch_create", "kpm_batch_energy_grad",
+    "kpm_batch_destroy", "kpm_set_probe_block", "kpm_profile_begin", "kpm_profile_end",
+    "kpm_strerror",
+)
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("Lx", c_int32), ("Ly", c_int32), ("n_vortex", c_int32)]
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("t", c_double), ("tp", c_double), ("J", c_double), ("mu", c_double)]
+
+
+class ProbeGroup(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("count", c_int32), ("px", c_int32), ("py", c_int32),
+                ("split_nambu", c_int32), ("first", c_int32), ("seed", c_uint64),
+                ("weight", c_double)]
+
+
+class Probes(ctypes.Structure):
+    _fields_ = [("groups", POINTER(ProbeGroup)), ("ngroups", c_int32)]
+
+
+class KpmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (build it: python paper_2212_05685_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    sig = {
+        "kpm_probe_count": (c_int32, [POINTER(Lattice), POINTER(Probes)]),
+        "kpm_build_H": (c_int32, [POINTER(Lattice), POINTER(Model), P, P, P, P, P]),
+        "kpm_build_H_vjp": (c_int32, [POINTER(Lattice), POINTER(Model), P, P, P, P, P, P, P, P]),
+        "kpm_bounds": (c_int32, [POINTER(Lattice), P, P, P]),
+        "kpm_coefficients": (c_int32, [c_int32, c_double, P, c_int32, P, P]),
+        "kpm_workspace_size": (c_size_t, [POINTER(Lattice), c_int32, c_int32, c_int32, c_int32]),
+        "kpm_moments": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, c_int32, c_int32,
+                                  P, P, c_size_t, P]),
+        "kpm_grand_potential": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P, c_int32,
+                                          c_int32, P, P, P, c_size_t, P]),
+        "kpm_grand_potential_grad": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P,
+                                               c_int32, c_int32, P, P, P, c_size_t, P]),
+        "kpm_density_matrix": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P, c_int32,
+                                         c_int32, P, P, P, P, P, P, P, P, P, c_size_t, P]),
+        "kpm_status_read": (c_int32, [P, POINTER(c_int32), P]),
+        "kpm_batch_create": (c_int32, [c_int32, POINTER(Lattice), POINTER(Probes), c_int32, c_int32,
+                                       c_int32, POINTER(c_void_p)]),
+        "kpm_batch_energy_grad": (c_int32, [P, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                            P, POINTER(c_void_p), c_int32, P]),
+        "kpm_batch_destroy": (c_int32, [P]),
+        "kpm_set_probe_block": (c_int32, [c_int32]),
+        "kpm_profile_begin": (c_int32, []),
+        "kpm_profile_end": (c_int32, [POINTER(c_double), POINTER(c_int32), POINTER(c_double),
+                                      POINTER(c_int32)]),
+        "kpm_strerror": (ctypes.c_char_p, [c_int32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def strerror(status: int) -> str:
+    return _lib.kpm_strerror(status).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != KPM_OK:
+        raise KpmError(status, where)
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return c_void_p(t.data_ptr())
+
+
+@dataclass(frozen=True)
+class ProbeSpec:
+    """One probe group (see kpm_probe_group in include/kpm.h)."""
+    kind: int
+    count: int
+    seed: int = 0
+    px: int = 1
+    py: int = 1
+    split_nambu: int = 0
+    first: int = 0
+    weight: float = 1.0
+
+
+def _probes(specs: Sequence[ProbeSpec]):
+    arr = (ProbeGroup * len(specs))()
+    for k, s in enumerate(specs):
+        arr[k] = ProbeGroup(s.kind, s.count, s.px, s.py, s.split_nambu, s.first,
+                            s.seed & ((1 << 64) - 1), s.weight)
+    pr = Probes(ctypes.cast(arr, POINTER(ProbeGroup)), len(specs))
+    pr._keep = arr
+    return pr
+
+
+def lattice(Lx: int, Ly: int, n_vortex: int) -> Lattice:
+    return Lattice(Lx, Ly, n_vortex)
+
+
+def model(t: float, tp: float, J: float, mu: float) -> Model:
+    return Model(t, tp, J, mu)
+
+
+# ---------------------------------------------------------------- entry points
+def kpm_probe_count(lat: Lattice, probes: Sequence[ProbeSpec]) -> int:
+    r = _lib.kpm_probe_count(ctypes.byref(lat), ctypes.byref(_probes(probes)))
+    if r < 0:
+        raise KpmError(r, "kpm_probe_count")
+    return r
+
+
+def kpm_build_H(lat, mdl, n, chi, delta, h, stream=None):
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_build_H(ctypes.byref(lat), ctypes.byref(mdl), _ptr(n, torch.float64, N, "n"),
+                            _ptr(chi, torch.complex128, 4 * N, "chi"),
+                            _ptr(delta, torch.complex128, 4 * N, "delta"),
+                            _ptr(h, torch.complex128, NENT * N, "h"), _stream(stream)), "kpm_build_H")
+
+
+def kpm_build_H_vjp(lat, mdl, n, chi, delta, rho, dn, dchi, ddelta, stream=None):
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_build_H_vjp(ctypes.byref(lat), ctypes.byref(mdl), _ptr(n, torch.float64, N, "n"),
+                                _ptr(chi, torch.complex128, 4 * N, "chi"),
+                                _ptr(delta, torch.complex128, 4 * N, "delta"),
+                                _ptr(rho, torch.complex128, NENT * N, "rho"),
+                                _ptr(dn, torch.float64, N, "dn"),
+                                _ptr(dchi, torch.complex128, 4 * N, "dchi"),
+                                _ptr(ddelta, torch.complex128, 4 * N, "ddelta"), _stream(stream)),
+           "kpm_build_H_vjp")
+
+
+def kpm_bounds(lat, h, ab, stream=None):
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_bounds(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"),
+                           _ptr(ab, torch.float64, 2, "ab"), _stream(stream)), "kpm_bounds")
+
+
+def kpm_coefficients(M, T, ab, C, K=0, stream=None):
+    _check(_lib.kpm_coefficients(M, T, _ptr(ab, torch.float64, 2, "ab"), K,
+                                 _ptr(C, torch.float64, M, "C"), _stream(stream)), "kpm_coefficients")
+
+
+def kpm_workspace_size(lat, R, M, ckpt_k, precision) -> int:
+    n = _lib.kpm_workspace_size(ctypes.byref(lat), R, M, ckpt_k, precision)
+    if n == 0:
+        raise KpmError(KPM_EINVAL, "kpm_workspace_size")
+    return int(n)
+
+
+def kpm_moments(lat, h, ab, probes, M, precision, ckpt_k, mu, ws, stream=None):
+    N = lat.Lx * lat.Ly
+    R = kpm_probe_count(lat, probes)
+    _check(_lib.kpm_moments(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"),
+                            _ptr(ab, torch.float64, 2, "ab"), ctypes.byref(_probes(probes)), M,
+                            precision, ckpt_k, _ptr(mu, torch.float64, R * M, "mu"),
+                            _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream)),
+           "kpm_moments")
+
+
+def kpm_grand_potential(lat, h, ab, probes, M, C, precision, ckpt_k, omega, mu, ws, stream=None):
+    N = lat.Lx * lat.Ly
+    R = kpm_probe_count(lat, probes)
+    _check(_lib.kpm_grand_potential(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"),
+                                    _ptr(ab, torch.float64, 2, "ab"), ctypes.byref(_probes(probes)),
+                                    M, _ptr(C, torch.float64, M, "C"), precision, ckpt_k,
+                                    _ptr(omega, torch.float64, 1, "omega"),
+                                    _ptr(mu, torch.float64, R * M, "mu"),
+                                    _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream)),
+           "kpm_grand_potential")
+
+
+def kpm_grand_potential_grad(lat, h, ab, probes, M, C, precision, ckpt_k, omega_bar, rho, ws,
+                             stream=None):
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_grand_potential_grad(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"),
+                                         _ptr(ab, torch.float64, 2, "ab"),
+                                         ctypes.byref(_probes(probes)), M,
+                                         _ptr(C, torch.float64, M, "C"), precision, ckpt_k,
+                                         _ptr(omega_bar, torch.float64, 1, "omega_bar"),
+                                         _ptr(rho, torch.complex128, NENT * N, "rho"),
+                                         _ptr(ws, torch.uint8, None, "ws"), ws.numel(),
+                                         _stream(stream)), "kpm_grand_potential_grad")
+
+
+def kpm_density_matrix(lat, h, ab, probes, M, C, precision, ckpt_k, omega, rho, n_up, n_dn,
+                       chi_up, chi_dn, delta_up, delta_dn, ws, stream=None):
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_density_matrix(
+        ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"), _ptr(ab, torch.float64, 2, "ab"),
+        ctypes.byref(_probes(probes)), M, _ptr(C, torch.float64, M, "C"), precision, ckpt_k,
+        _ptr(omega, torch.float64, 1, "omega"), _ptr(rho, torch.complex128, NENT * N, "rho"),
+        _ptr(n_up, torch.float64, N, "n_up"), _ptr(n_dn, torch.float64, N, "n_dn"),
+        _ptr(chi_up, torch.complex128, 4 * N, "chi_up"), _ptr(chi_dn, torch.complex128, 4 * N, "chi_dn"),
+        _ptr(delta_up, torch.complex128, 4 * N, "delta_up"),
+        _ptr(delta_dn, torch.complex128, 4 * N, "delta_dn"),
+        _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream)), "kpm_density_matrix")
+
+
+def kpm_status_read(ws, stream=None) -> int:
+    out = c_int32(0)
+    _check(_lib.kpm_status_read(_ptr(ws, torch.uint8, None, "ws"), ctypes.byref(out), _stream(stream)),
+           "kpm_status_read")
+    return out.value
+
+
+def kpm_set_probe_block(probes_per_thread: int) -> int:
+    return int(_lib.kpm_set_probe_block(probes_per_thread))
+
+
+def kpm_profile_begin() -> None:
+    _check(_lib.kpm_profile_begin(), "kpm_profile_begin")
+
+
+def kpm_profile_end():
+    """(forward ms, forward launches, adjoint ms, adjoint launches) since begin."""
+    f, a = c_double(0), c_double(0)
+    nf, na = c_int32(0), c_int32(0)
+    _check(_lib.kpm_profile_end(ctypes.byref(f), ctypes.byref(nf), ctypes.byref(a), ctypes.byref(na)),
+           "kpm_profile_end")
+    return f.value, nf.value, a.value, na.value
+
+
+def kpm_strerror(status: int) -> str:
+    return strerror(status)
+
+
+def kpm_batch_create(lats: Sequence[Lattice], probes: Sequence[Sequence[ProbeSpec]], M, precision,
+                     ckpt_k) -> c_void_p:
+    n = len(lats)
+    L = (Lattice * n)(*lats)
+    prs = [_probes(p) for p in probes]
+    P = (Probes * n)(*prs)
+    plan = c_void_p()
+    _check(_lib.kpm_batch_create(n, L, P, M, precision, ckpt_k, ctypes.byref(plan)), "kpm_batch_create")
+    return plan
+
+
+def kpm_batch_energy_grad(plan, h, ab, C, omega, rho, use_graph=True, stream=None):
+    n = len(h)
+    arr = lambda ts, dt, nm: (c_void_p * n)(*[_ptr(t, dt, None, nm).value for t in ts])
+    _check(_lib.kpm_batch_energy_grad(plan, arr(h, torch.complex128, "h"), arr(ab, torch.float64, "ab"),
+                                      arr(C, torch.float64, "C"), _ptr(omega, torch.float64, n, "omega"),
+                                      arr(rho, torch.complex128, "rho"), 1 if use_graph else 0,
+                                      _stream(stream)), "kpm_batch_energy_grad")
+
+
+def kpm_batch_destroy(plan) -> None:
+    _check(_lib.kpm_batch_destroy(plan), "kpm_batch_destroy")
+
+
+# ---------------------------------------------------------------- helpers
+def workspace(lat, R, M, ckpt_k, precision, device="cuda") -> torch.Tensor:
+    """A device byte tensor of kpm_workspace_size bytes, 256-byte aligned."""
+    n = kpm_workspace_size(lat, R, M, ckpt_k, precision)
+    ws = torch.empty(n + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + n]

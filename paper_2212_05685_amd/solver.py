@@ -1,0 +1,102 @@
+"""Convenience layer over the C ABI: allocates torch device buffers and calls
+the library entry points in the order of the method (App. B): build h, rescale
+bounds, expansion coefficients, forward recursion (Omega), adjoint (rho), and
+the builder VJP.  No arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import torch
+
+from . import kpm
+
+
+@dataclass
+class KPMProblem:
+    Lx: int
+    Ly: int
+    n_vortex: int
+    t: float
+    tp: float
+    J: float
+    mu: float
+    T: float
+    M: int
+    probes: Sequence[kpm.ProbeSpec]
+    precision: int = kpm.KPM_FP64
+    ckpt_k: int = 64
+    device: str = "cuda"
+    _ws: torch.Tensor = field(default=None, repr=False)
+
+    def __post_init__(self):
+        self.lat = kpm.lattice(self.Lx, self.Ly, self.n_vortex)
+        self.mdl = kpm.model(self.t, self.tp, self.J, self.mu)
+        self.N = self.Lx * self.Ly
+        self.R = kpm.kpm_probe_count(self.lat, self.probes)
+
+    # -- buffers
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            self._ws = kpm.workspace(self.lat, self.R, self.M, self.ckpt_k, self.precision, self.device)
+        return self._ws
+
+    def zeros(self, *shape, dtype=torch.complex128):
+        return torch.zeros(*shape, dtype=dtype, device=self.device)
+
+    # -- steps
+    def build_H(self, n, chi, delta):
+        h = self.zeros(kpm.NENT, self.N)
+        kpm.kpm_build_H(self.lat, self.mdl, n, chi, delta, h)
+        return h
+
+    def build_H_vjp(self, n, chi, delta, rho):
+        dn = self.zeros(self.N, dtype=torch.float64)
+        dchi = self.zeros(4, self.N)
+        ddelta = self.zeros(4, self.N)
+        kpm.kpm_build_H_vjp(self.lat, self.mdl, n, chi, delta, rho, dn, dchi, ddelta)
+        return dn, dchi, ddelta
+
+    def bounds(self, h):
+        ab = self.zeros(2, dtype=torch.float64)
+        kpm.kpm_bounds(self.lat, h, ab)
+        return ab
+
+    def coefficients(self, ab, K=0):
+        C = self.zeros(self.M, dtype=torch.float64)
+        kpm.kpm_coefficients(self.M, self.T, ab, C, K)
+        return C
+
+    def moments(self, h, ab):
+        mu = self.zeros(self.R, self.M, dtype=torch.float64)
+        kpm.kpm_moments(self.lat, h, ab, self.probes, self.M, self.precision, self.ckpt_k, mu,
+                        self.workspace())
+        return mu
+
+    def grand_potential(self, h, ab, C, want_mu=False):
+        omega = self.zeros(1, dtype=torch.float64)
+        mu = self.zeros(self.R, self.M, dtype=torch.float64) if want_mu else None
+        kpm.kpm_grand_potential(self.lat, h, ab, self.probes, self.M, C, self.precision, self.ckpt_k,
+                                omega, mu, self.workspace())
+        return (omega, mu) if want_mu else omega
+
+    def grand_potential_grad(self, h, ab, C, omega_bar=None):
+        rho = self.zeros(kpm.NENT, self.N)
+        kpm.kpm_grand_potential_grad(self.lat, h, ab, self.probes, self.M, C, self.precision,
+                                     self.ckpt_k, omega_bar, rho, self.workspace())
+        return rho
+
+    def density_matrix(self, h, ab, C):
+        out = {"omega": self.zeros(1, dtype=torch.float64), "rho": self.zeros(kpm.NENT, self.N),
+               "n_up": self.zeros(self.N, dtype=torch.float64),
+               "n_dn": self.zeros(self.N, dtype=torch.float64),
+               "chi_up": self.zeros(4, self.N), "chi_dn": self.zeros(4, self.N),
+               "delta_up": self.zeros(4, self.N), "delta_dn": self.zeros(4, self.N)}
+        kpm.kpm_density_matrix(self.lat, h, ab, self.probes, self.M, C, self.precision, self.ckpt_k,
+                               out["omega"], out["rho"], out["n_up"], out["n_dn"], out["chi_up"],
+                               out["chi_dn"], out["delta_up"], out["delta_dn"], self.workspace())
+        return out
+
+    def status(self) -> int:
+        return kpm.kpm_status_read(self.workspace())
