@@ -94,7 +94,7 @@ def timed(prob, th, steps, warmup, profile):
         log(f"{'fp32' if prob.precision else 'fp64'} warmup {w + 1}/{warmup} done")
     torch.cuda.synchronize()
     if profile:
-        kpm.kpm_profile_begin()
+        kpm.kpm_profile_begin(16)
     t0 = time.perf_counter()
     for s in range(steps):
         out, grads = energy_grad(prob, th)
@@ -144,6 +144,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time the steps without per-kernel events (roofline fields omitted)")
+    ap.add_argument("--moments", type=int, default=0,
+                    help="profiling runs only: override M (same launch shape, fewer steps)")
+    ap.add_argument("--probe-block", type=int, default=0,
+                    help="probes per wave of the recursion kernels (0 = library default)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="run one plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: this build runs on a single GPU only "
@@ -155,13 +163,28 @@ def main():
 
     import workloads as wl
 
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}))
+        return
+
+    if args.probe_block:
+        from paper_2212_05685_amd import kpm
+        kpm.kpm_set_probe_block(args.probe_block)
     cfg = wl.C5("fp32")
+    if args.moments:
+        cfg = wl.scaled(cfg, M=args.moments)
     prob, th = make_problem(cfg, "fp32")
     R, M, N = prob.R, cfg.M, cfg.N
     log(f"workload 100x100 M={M} R={R}; building and warming up")
-    dt, out32, grads32, prof = timed(prob, th, args.steps, args.warmup, profile=True)
+    dt, out32, grads32, prof = timed(prob, th, args.steps, args.warmup, profile=not args.no_kernel_timing)
     vsteps = R * (M - 1) + 2 * R * (M - 2)
-    fwd_ms, n_fwd, adj_ms, n_adj = prof
+    fwd_ms, n_fwd, adj_ms, n_adj = prof if prof else (float("nan"), 0, float("nan"), 0)
     rec = 16                                    # FP32 complex record of one site (2 components)
     coef_bytes = 36 * 8 * N                     # row-form H~ coefficients, FP32 complex
     adj_bytes = 6 * rec * R * N + coef_bytes     # read a_{m+1}, g_{m+1}, a_{m+2}, g_{m+2}; write a_m, g_m
@@ -210,7 +233,7 @@ def main():
             "avg_launch_us": fwd_avg_s * 1e6, "achieved_GBs": fwd_bytes / fwd_avg_s / 1e9,
             "launches_timed": n_fwd,
         },
-        "hbm_GBs_algorithmic_whole_step": (n_fwd * fwd_bytes + n_adj * adj_bytes) / args.steps / dt / 1e9,
+        "hbm_GBs_algorithmic_whole_step": ((M - 1) * fwd_bytes + (M - 2) * adj_bytes) / dt / 1e9,
     }
 
     if not args.no_fp64_form:

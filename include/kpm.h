@@ -231,12 +231,13 @@ int kpm_batch_destroy(void* plan);
 int32_t kpm_set_probe_block(int32_t probes_per_thread);
 
 /* ---- measurement ----------------------------------------------------------
- * Between kpm_profile_begin and kpm_profile_end every forward-step and
- * adjoint-step kernel launched by this library (not inside a graph capture)
- * carries start/stop events recorded by its own dispatch on its own stream.
- * kpm_profile_end synchronises those events and returns the summed kernel
- * durations (milliseconds, host memory) and launch counts of both kinds. */
-int kpm_profile_begin(void);
+ * Between kpm_profile_begin and kpm_profile_end, one in `sample_every`
+ * forward-step and adjoint-step kernel launches of this library (not inside a
+ * graph capture) carries start/stop events recorded by its own dispatch on its
+ * own stream.  kpm_profile_end synchronises those events and returns the
+ * summed durations (milliseconds, host memory) and counts of the sampled
+ * launches of both kinds. */
+int kpm_profile_begin(int32_t sample_every);
 int kpm_profile_end(double* fwd_ms, int32_t* n_fwd, double* adj_ms, int32_t* n_adj);
 
 const char* kpm_strerror(int status);

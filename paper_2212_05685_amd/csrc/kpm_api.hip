@@ -22,14 +22,14 @@ hipError_t launch_build_vjp(const ModelDev&, const double*, const double*, const
 hipError_t launch_bounds(int, int, const double*, double*, hipStream_t);
 hipError_t launch_rescale(const InstDev*, const int2*, int, bool, hipStream_t);
 hipError_t launch_coeffs(int, int, double, const double*, double*, hipStream_t);
-hipError_t launch_cheb(bool, int, int, const InstDev*, const int2*, int, int, int, int, int, int,
+hipError_t launch_cheb(bool, int, int, const InstDev*, const int4*, int, int, int, int, int, int,
                        hipStream_t);
 hipError_t launch_mom_reduce(const InstDev*, int, int, int, double*, hipStream_t);
 hipError_t launch_omega(const InstDev*, int, int, hipStream_t);
 hipError_t launch_rho(const InstDev*, const int2*, int, hipStream_t);
 hipError_t launch_map(int, const double*, double*, double*, double*, double*, double*, double*,
                       hipStream_t);
-hipError_t profile_begin();
+hipError_t profile_begin(int);
 hipError_t profile_end(double*, int*, double*, int*);
 
 // Sets every instance's status word (a kernel, not a memset, so that the
@@ -115,13 +115,14 @@ int build_groups(const kpm_lattice* L, const kpm_probes* pr, GroupDev* out, int*
 
 bool valid_P(int P) { return P == 1 || P == 2 || P == 4 || P == 8 || P == 16 || P == 32; }
 
-// Enough threads to give every SIMD of the 256 CUs several waves, then the
-// largest block that keeps the per-thread register footprint reasonable.
-int auto_probe_block(long long sites_total, int Rmax, bool fp32, bool adjoint) {
-  const long long want = 256LL * 4 * 4 * 64;
-  const int pmax = adjoint ? (fp32 ? 8 : 4) : (fp32 ? 16 : 8);
+constexpr int kTX = 8, kTY = 4, kWaves = kBlock / 64;   // recursion tile and waves per block
+
+// Probes per wave: the largest power of two (<= 8) that still gives every
+// SIMD of the 256 CUs about 8 waves in one launch.
+int auto_probe_block(long long tiles_total, int Rmax) {
+  const long long want = 256LL * 4 * 8;
   int P = 1;
-  while (P < pmax && sites_total * ((Rmax + 2 * P - 1) / (2 * P)) >= want) P *= 2;
+  while (P < 8 && tiles_total * ((Rmax + 2 * P - 1) / (2 * P)) >= want) P *= 2;
   return P;
 }
 
@@ -130,7 +131,7 @@ int g_probe_block = 0;   // 0 = automatic
 
 // ------------------------------------------------------------ instance layout
 struct Sizes {
-  int N, R, nchunk;
+  int N, R, M, nchunk, ntile;
   size_t rec, coef, vec, ckpt, mom, musum, gpart;
   long long nslots;
 };
@@ -139,20 +140,23 @@ Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32) {
   Sizes z{};
   z.N = L->Lx * L->Ly;
   z.R = R;
+  z.M = M;
   z.nchunk = (z.N + kBlock - 1) / kBlock;
+  z.ntile = ((L->Lx + kTX - 1) / kTX) * ((L->Ly + kTY - 1) / kTY);
   z.rec = fp32 ? 16 : 32;
   z.coef = align_up((size_t)kNcoef * z.N * 2 * (fp32 ? 4 : 8));
   z.vec = align_up((size_t)R * z.N * z.rec);
   z.nslots = 2LL * ((M - 1) / k + 1);
   z.ckpt = align_up((size_t)R * z.N * z.rec * (size_t)z.nslots);
-  z.mom = align_up(sizeof(double) * (size_t)M * R * z.nchunk);
+  z.mom = align_up(sizeof(double) * (size_t)M * R * z.ntile);
   z.musum = align_up(sizeof(double) * (size_t)M * R);
   z.gpart = align_up(sizeof(double) * 2 * kNent * (size_t)z.N * R);   // sized for P = 1
   return z;
 }
 
 size_t inst_bytes(const Sizes& z) {
-  return align_up(sizeof(int)) + z.coef + 4 * z.vec + z.ckpt + z.mom + z.musum + z.gpart;
+  return align_up(sizeof(int)) + z.coef + 4 * z.vec + z.ckpt + z.mom + z.musum + z.gpart +
+         align_up(sizeof(double) * ((z.M + kBlock - 1) / kBlock));
 }
 
 // Carve one instance's buffers out of `base` (which must hold inst_bytes).
@@ -167,38 +171,48 @@ void carve(InstDev& I, const Sizes& z, char* base) {
   I.ckpt = o;                             o += z.ckpt;
   I.mom = reinterpret_cast<double*>(o);   o += z.mom;
   I.musum = reinterpret_cast<double*>(o); o += z.musum;
-  I.gpart = reinterpret_cast<double2*>(o);
+  I.gpart = reinterpret_cast<double2*>(o); o += z.gpart;
+  I.opart = reinterpret_cast<double*>(o);
 }
 
 // ------------------------------------------------------------ run context
 struct Ctx {
   std::vector<InstDev> inst;
-  std::vector<int2> cmap;
+  std::vector<int2> cmap;     // 256-site chunks (element-wise kernels)
+  std::vector<int4> tmap;     // (instance, X0, Y0, tile index) recursion tiles
   InstDev* d_inst = nullptr;
   int2* d_cmap = nullptr;
+  int4* d_tmap = nullptr;
+  double* d_opart = nullptr;  // Omega partial sums [ninst][ceil(M/256)]
   int M = 0, k = 0;
   bool fp32 = false;
-  int Pf = 1, Pa = 1;
+  int Pf = 1, Pa = 1;         // probes per wave, forward and adjoint kernels
   int Rmax = 0;
   long long sites = 0;
-  int npbf() const { return (Rmax + Pf - 1) / Pf; }
-  int npba() const { return (Rmax + Pa - 1) / Pa; }
+  int nrf() const { return (Rmax + kWaves * Pf - 1) / (kWaves * Pf); }
+  int nra() const { return (Rmax + kWaves * Pa - 1) / (kWaves * Pa); }
   int nch() const { return (int)cmap.size(); }
+  int ntl() const { return (int)tmap.size(); }
 };
 
 void finish_ctx(Ctx& c) {
   c.cmap.clear();
+  c.tmap.clear();
   c.Rmax = 0;
   c.sites = 0;
   for (size_t q = 0; q < c.inst.size(); ++q) {
-    for (int ch = 0; ch < c.inst[q].nchunk; ++ch) c.cmap.push_back(make_int2((int)q, ch * kBlock));
-    c.Rmax = std::max(c.Rmax, c.inst[q].R);
-    c.sites += c.inst[q].N;
+    const InstDev& I = c.inst[q];
+    for (int ch = 0; ch * kBlock < I.N; ++ch) c.cmap.push_back(make_int2((int)q, ch * kBlock));
+    const int tx = (I.Lx + kTX - 1) / kTX, ty = (I.Ly + kTY - 1) / kTY;
+    for (int t = 0; t < tx * ty; ++t) c.tmap.push_back(make_int4((int)q, (t % tx) * kTX, (t / tx) * kTY, t));
+    c.Rmax = std::max(c.Rmax, I.R);
+    c.sites += I.N;
   }
 }
 
+// number of probe ranges of each instance in the adjoint (partial dOmega/dH~ buffers)
 void set_npb(Ctx& c) {
-  for (auto& I : c.inst) I.npb = (I.R + c.Pa - 1) / c.Pa;
+  for (auto& I : c.inst) I.npb = (I.R + kWaves * c.Pa - 1) / (kWaves * c.Pa);
 }
 
 // Host copies of the tables uploaded for single-lattice calls, kept alive per
@@ -206,21 +220,27 @@ void set_npb(Ctx& c) {
 struct HostTables {
   std::vector<InstDev> inst;
   std::vector<int2> cmap;
+  std::vector<int4> tmap;
 };
 std::map<const void*, HostTables> g_tables;
 std::mutex g_tables_mu;
 
-int upload_from(const std::vector<InstDev>& inst, const std::vector<int2>& cmap, InstDev* d_inst,
-                int2* d_cmap, hipStream_t s) {
+int upload_from(const std::vector<InstDev>& inst, const std::vector<int2>& cmap,
+                const std::vector<int4>& tmap, InstDev* d_inst, int2* d_cmap, int4* d_tmap,
+                hipStream_t s) {
   KPM_HIP(hipMemcpyAsync(d_inst, inst.data(), sizeof(InstDev) * inst.size(),
                          hipMemcpyHostToDevice, s));
   KPM_HIP(hipMemcpyAsync(d_cmap, cmap.data(), sizeof(int2) * cmap.size(), hipMemcpyHostToDevice,
+                         s));
+  KPM_HIP(hipMemcpyAsync(d_tmap, tmap.data(), sizeof(int4) * tmap.size(), hipMemcpyHostToDevice,
                          s));
   return KPM_OK;
 }
 
 // Plans own their tables (Ctx lives as long as the plan).
-int upload(Ctx& c, hipStream_t s) { return upload_from(c.inst, c.cmap, c.d_inst, c.d_cmap, s); }
+int upload(Ctx& c, hipStream_t s) {
+  return upload_from(c.inst, c.cmap, c.tmap, c.d_inst, c.d_cmap, c.d_tmap, s);
+}
 
 // Single-lattice calls: copy the tables into the per-workspace host store first.
 int upload_single(Ctx& c, const void* ws, hipStream_t s) {
@@ -230,7 +250,8 @@ int upload_single(Ctx& c, const void* ws, hipStream_t s) {
   // the previous upload from this store no longer reads it
   t.inst = c.inst;
   t.cmap = c.cmap;
-  return upload_from(t.inst, t.cmap, c.d_inst, c.d_cmap, s);
+  t.tmap = c.tmap;
+  return upload_from(t.inst, t.cmap, t.tmap, c.d_inst, c.d_cmap, c.d_tmap, s);
 }
 
 int run_forward(const Ctx& c, bool ckpt, int nsteps, hipStream_t s) {
@@ -238,10 +259,10 @@ int run_forward(const Ctx& c, bool ckpt, int nsteps, hipStream_t s) {
   hipLaunchKernelGGL(k_set_status, dim3((ninst + 63) / 64), dim3(64), 0, s, c.d_inst, ninst, 0);
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_cmap, c.nch(), c.fp32, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_cmap, c.nch(), c.npbf(), 0, c.M, c.k,
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), 0, c.M, c.k,
                       ckpt ? 1 : 0, s));
   for (int m = 0; m + 1 < nsteps; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_cmap, c.nch(), c.npbf(), m, c.M, c.k,
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, c.M, c.k,
                         ckpt ? 1 : 0, s));
   return KPM_OK;
 }
@@ -255,10 +276,10 @@ int run_moments(const Ctx& c, double* mu_user, hipStream_t s) {
 
 int run_adjoint(const Ctx& c, hipStream_t s) {
   const int M = c.M;
-  KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_cmap, c.nch(), c.npba(), 0, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_tmap, c.ntl(), c.nra(), 0, M, c.k, 0, s));
   for (int m = M - 3; m >= 0; --m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_cmap, c.nch(), c.npba(), m, M, c.k, 0, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_cmap, c.nch(), c.npba(), 0, M, c.k, 1, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.nra(), m, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.nra(), 0, M, c.k, 1, s));
   KPM_HIP(launch_rho(c.d_inst, c.d_cmap, c.nch(), s));
   return KPM_OK;
 }
@@ -266,7 +287,7 @@ int run_adjoint(const Ctx& c, hipStream_t s) {
 // ------------------------------------------------------------ single lattice
 // Workspace = [InstDev][cmap][instance buffers].
 struct WsLayout {
-  size_t off_inst, off_cmap, off_buf, total;
+  size_t off_inst, off_cmap, off_tmap, off_buf, total;
 };
 
 WsLayout ws_layout(const Sizes& z) {
@@ -274,6 +295,7 @@ WsLayout ws_layout(const Sizes& z) {
   size_t o = 0;
   w.off_inst = o; o = align_up(o + sizeof(InstDev));
   w.off_cmap = o; o = align_up(o + sizeof(int2) * z.nchunk);
+  w.off_tmap = o; o = align_up(o + sizeof(int4) * z.ntile);
   w.off_buf = o;  o += inst_bytes(z);
   w.total = o;
   return w;
@@ -308,7 +330,7 @@ int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* 
   I.Ly = L->Ly;
   I.N = z.N;
   I.R = R;
-  I.nchunk = z.nchunk;
+  I.nchunk = z.ntile;
   I.ngroups = ng;
   I.h = reinterpret_cast<const double2*>(h);
   I.ab = ab;
@@ -317,6 +339,7 @@ int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* 
   c.inst.assign(1, I);
   c.d_inst = reinterpret_cast<InstDev*>(base + w.off_inst);
   c.d_cmap = reinterpret_cast<int2*>(base + w.off_cmap);
+  c.d_tmap = reinterpret_cast<int4*>(base + w.off_tmap);
   c.M = M;
   c.k = k;
   finish_ctx(c);
@@ -325,8 +348,8 @@ int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* 
     std::lock_guard<std::mutex> lk(g_mu);
     P = g_probe_block;
   }
-  c.Pf = P ? P : auto_probe_block(c.sites, c.Rmax, c.fp32, false);
-  c.Pa = P ? P : auto_probe_block(c.sites, c.Rmax, c.fp32, true);
+  c.Pf = P ? P : auto_probe_block(c.ntl(), c.Rmax);
+  c.Pa = P ? P : auto_probe_block(c.ntl(), c.Rmax);
   set_npb(c);
   return KPM_OK;
 }
@@ -375,9 +398,9 @@ int autotune(KpmBatchPlan* pl, hipStream_t s) {
   const int steps = std::min(c.M, 8);
   float best_f = 1e30f, best_a = 1e30f;
   int Pf = 1, Pa = 1;
-  for (int P : {2, 4, 8, 16}) {
+  for (int P : {1, 2, 4, 8, 16}) {
     c.Pf = P;
-    c.Pa = std::min(P, 8);
+    c.Pa = P;
     set_npb(c);
     int st = upload(c, s);
     if (st != KPM_OK) return st;
@@ -395,12 +418,12 @@ int autotune(KpmBatchPlan* pl, hipStream_t s) {
       best_f = tf;
       Pf = P;
     }
-    if (P <= 8 && c.M >= 3) {
+    if (c.M >= 3) {
       // adjoint steps on whatever the buffers hold (timing only; m = M-3 >= 0)
       KPM_HIP(hipEventRecord(e0, s));
-      KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_cmap, c.nch(), c.npba(), 0, c.M, c.k, 0, s));
+      KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_tmap, c.ntl(), c.nra(), 0, c.M, c.k, 0, s));
       for (int q = 0; q < steps; ++q)
-        KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_cmap, c.nch(), c.npba(), c.M - 3, c.M,
+        KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.nra(), c.M - 3, c.M,
                             c.M + 1, 0, s));
       KPM_HIP(hipEventRecord(e1, s));
       KPM_HIP(hipEventSynchronize(e1));
@@ -592,7 +615,7 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
   std::vector<Sizes> zs(n_inst);
   std::vector<InstDev> insts(n_inst);
   size_t total = align_up(sizeof(InstDev) * n_inst);
-  size_t nch = 0;
+  size_t nch = 0, ntl = 0;
   for (int q = 0; q < n_inst; ++q) {
     if (!valid_lattice(&lats[q])) return KPM_EINVAL;
     std::memset(&insts[q], 0, sizeof(InstDev));
@@ -604,12 +627,13 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
     insts[q].Ly = lats[q].Ly;
     insts[q].N = zs[q].N;
     insts[q].R = R;
-    insts[q].nchunk = zs[q].nchunk;
+    insts[q].nchunk = zs[q].ntile;
     insts[q].ngroups = ng;
     nch += zs[q].nchunk;
+    ntl += zs[q].ntile;
     total += inst_bytes(zs[q]);
   }
-  total += align_up(sizeof(int2) * nch);
+  total += align_up(sizeof(int2) * nch) + align_up(sizeof(int4) * ntl);
   auto* pl = new (std::nothrow) KpmBatchPlan();
   if (!pl) return KPM_ENOMEM;
   if (hipMalloc(&pl->mem, total) != hipSuccess) {
@@ -621,6 +645,8 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
   char* o = base + align_up(sizeof(InstDev) * n_inst);
   pl->c.d_cmap = reinterpret_cast<int2*>(o);
   o += align_up(sizeof(int2) * nch);
+  pl->c.d_tmap = reinterpret_cast<int4*>(o);
+  o += align_up(sizeof(int4) * ntl);
   for (int q = 0; q < n_inst; ++q) {
     carve(insts[q], zs[q], o);
     o += inst_bytes(zs[q]);
@@ -635,8 +661,8 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
     std::lock_guard<std::mutex> lk(g_mu);
     P = g_probe_block;
   }
-  pl->c.Pf = P ? P : auto_probe_block(pl->c.sites, pl->c.Rmax, fp32, false);
-  pl->c.Pa = P ? P : auto_probe_block(pl->c.sites, pl->c.Rmax, fp32, true);
+  pl->c.Pf = P ? P : auto_probe_block(pl->c.ntl(), pl->c.Rmax);
+  pl->c.Pa = P ? P : auto_probe_block(pl->c.ntl(), pl->c.Rmax);
   pl->tuned = P != 0;
   set_npb(pl->c);
   *plan = pl;
@@ -713,8 +739,9 @@ int kpm_batch_destroy(void* plan) {
   return KPM_OK;
 }
 
-int kpm_profile_begin(void) {
-  KPM_HIP(profile_begin());
+int kpm_profile_begin(int32_t sample_every) {
+  if (sample_every < 1) return KPM_EINVAL;
+  KPM_HIP(profile_begin(sample_every));
   return KPM_OK;
 }
 

@@ -9,8 +9,8 @@
 //                            rec = two complex values (Nambu 0, 1) of one site
 //                            (float4 = 16 B in FP32, 2 x double2 = 32 B in FP64)
 //   ckpt   [S][R][N] rec     checkpoint alpha_j for j % k in {0, 1}, slot 2(j/k)+j%k
-//   mom    [M][R][nchunk]    per-(step, probe, 256-site chunk) moment partials
-//   gpart  [npb][19][N] double2  per-probe-block partial dOmega/dH~ (FP64)
+//   mom    [M][R][ntile]     per-(step, probe, 8x4 tile) moment partials
+//   gpart  [nrange][19][N] double2  per-probe-range partial dOmega/dH~ (FP64)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,9 +46,10 @@ struct InstDev {
   void* A[2];
   void* G[2];
   void* ckpt;
-  double* mom;        // [M][R][nchunk]
+  double* mom;        // [M][R][nchunk] moment partials (nchunk = recursion tiles)
   double* musum;      // [R][M] reduced moments
-  double2* gpart;     // [npb][19][N]
+  double2* gpart;     // [npb][19][N] partial dOmega/dH~ per probe range
+  double* opart;      // [ceil(M/256)] partial sums of Omega
   double2* rho;       // [19][N] output
   const double* omega_bar;
   double* omega;

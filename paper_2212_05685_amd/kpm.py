@@ -87,7 +87,7 @@ def _load():
                                             P, POINTER(c_void_p), c_int32, P]),
         "kpm_batch_destroy": (c_int32, [P]),
         "kpm_set_probe_block": (c_int32, [c_int32]),
-        "kpm_profile_begin": (c_int32, []),
+        "kpm_profile_begin": (c_int32, [c_int32]),
         "kpm_profile_end": (c_int32, [POINTER(c_double), POINTER(c_int32), POINTER(c_double),
                                       POINTER(c_int32)]),
         "kpm_strerror": (ctypes.c_char_p, [c_int32]),
@@ -268,8 +268,8 @@ def kpm_set_probe_block(probes_per_thread: int) -> int:
     return int(_lib.kpm_set_probe_block(probes_per_thread))
 
 
-def kpm_profile_begin() -> None:
-    _check(_lib.kpm_profile_begin(), "kpm_profile_begin")
+def kpm_profile_begin(sample_every: int = 1) -> None:
+    _check(_lib.kpm_profile_begin(sample_every), "kpm_profile_begin")
 
 
 def kpm_profile_end():
