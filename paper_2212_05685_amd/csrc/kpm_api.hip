@@ -132,7 +132,7 @@ int g_probe_block = 0;   // 0 = automatic
 // ------------------------------------------------------------ instance layout
 struct Sizes {
   int N, R, M, nchunk, ntile;
-  size_t rec, coef, vec, ckpt, mom, musum, gpart;
+  size_t rec, coef, vec, ckpt, mom, musum, gpart, pcode, pw;
   long long nslots;
 };
 
@@ -151,12 +151,14 @@ Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32) {
   z.mom = align_up(sizeof(double) * (size_t)M * R * z.ntile);
   z.musum = align_up(sizeof(double) * (size_t)M * R);
   z.gpart = align_up(sizeof(double) * 2 * kNent * (size_t)z.N * R);   // sized for P = 1
+  z.pcode = align_up((size_t)R * z.N);
+  z.pw = align_up(sizeof(double) * (size_t)R);
   return z;
 }
 
 size_t inst_bytes(const Sizes& z) {
   return align_up(sizeof(int)) + z.coef + 4 * z.vec + z.ckpt + z.mom + z.musum + z.gpart +
-         align_up(sizeof(double) * ((z.M + kBlock - 1) / kBlock));
+         align_up(sizeof(double) * ((z.M + kBlock - 1) / kBlock)) + z.pcode + z.pw;
 }
 
 // Carve one instance's buffers out of `base` (which must hold inst_bytes).
@@ -172,7 +174,9 @@ void carve(InstDev& I, const Sizes& z, char* base) {
   I.mom = reinterpret_cast<double*>(o);   o += z.mom;
   I.musum = reinterpret_cast<double*>(o); o += z.musum;
   I.gpart = reinterpret_cast<double2*>(o); o += z.gpart;
-  I.opart = reinterpret_cast<double*>(o);
+  I.opart = reinterpret_cast<double*>(o);  o += align_up(sizeof(double) * ((z.M + kBlock - 1) / kBlock));
+  I.pcode = reinterpret_cast<unsigned char*>(o); o += z.pcode;
+  I.pw = reinterpret_cast<double*>(o);
 }
 
 // ------------------------------------------------------------ run context

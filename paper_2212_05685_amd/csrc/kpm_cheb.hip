@@ -123,7 +123,8 @@ __device__ __forceinline__ void load_row(RowCoef<V>& K, const InstDev& I, const 
 }
 
 // ------------------------------------------------------------- probes
-// Per-lane probe context precomputed once: colour of the site in each group.
+// Per-lane probe context: colour of the site in each group (used once per call
+// by k_init, which evaluates the probes and writes the code table).
 struct ProbeLane {
   int col[kMaxGroups];
 };
@@ -140,14 +141,11 @@ __device__ __forceinline__ ProbeLane probe_lane(const InstDev& I, const Lane& L)
 }
 
 // Code k (entry = i^k) of probe p at the lane's (site, row); -1 for zero.
-// p is wave-uniform, so the group lookup and the draw/colour split are scalar.
 __device__ __forceinline__ int probe_code(const InstDev& I, const ProbeLane& P, const Lane& L,
                                           int p, double& w) {
   int k = -1;
   w = 0.0;
-#pragma unroll
-  for (int gi = 0; gi < kMaxGroups; ++gi) {
-    if (gi >= I.ngroups) break;
+  for (int gi = 0; gi < I.ngroups; ++gi) {
     const GroupDev& g = I.g[gi];
     const int q = p - g.base;
     if (q < 0 || q >= g.nprobes) continue;
@@ -173,6 +171,16 @@ __device__ __forceinline__ int probe_code(const InstDev& I, const ProbeLane& P, 
   return k;
 }
 
+// Entry code of the lane's Nambu component from the probe's code byte.
+__device__ __forceinline__ int lane_code(unsigned byte, int a) {
+  const unsigned nib = (byte >> (4 * a)) & 0xFu;
+  return (nib & 8u) ? (int)(nib & 3u) : -1;
+}
+
+__device__ __forceinline__ unsigned ldg_code(const InstDev& I, unsigned idx) {
+  return ((GPtr<unsigned char>)(I.pcode))[idx];
+}
+
 template <typename V>
 __device__ __forceinline__ Cx<V> phase_times(int k, V s) {
   Cx<V> r{V(0), V(0)};
@@ -183,11 +191,44 @@ __device__ __forceinline__ Cx<V> phase_times(int k, V s) {
   return r;
 }
 
-// 64-lane FP64 sum (every lane gets the total).
+// Re(conj(i^k) z) in FP64 (0 for k < 0)
+template <typename V>
+__device__ __forceinline__ double re_conj_phase(int k, const Cx<V>& z) {
+  double v = 0.0;
+  if (k == 0) v = (double)z.x;
+  else if (k == 1) v = (double)z.y;
+  else if (k == 2) v = -(double)z.x;
+  else if (k == 3) v = -(double)z.y;
+  return v;
+}
+
+// 64-lane FP64 sum (every lane gets the total), fixed butterfly order.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
   return v;
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Wave sum of v over the lanes flagged nz: lanes read directly when at most
+// two are set (coloured and unit probes: one site of a tile), else a butterfly.
+// Wave-uniform result; deterministic for given data.
+__device__ __forceinline__ double wave_moment(double v, bool nz) {
+  unsigned long long mask = __ballot(nz);
+  if (mask == 0ull) return 0.0;
+  if (__popcll(mask) <= 2) {
+    double s = read_lane(v, __ffsll((long long)mask) - 1);
+    mask &= mask - 1ull;
+    if (mask) s += read_lane(v, __ffsll((long long)mask) - 1);
+    return s;
+  }
+  return wave_sum(nz ? v : 0.0);
 }
 
 // ------------------------------------------------------------- LDS staging
@@ -207,8 +248,12 @@ __device__ __forceinline__ void row_apply(Cx<V>& acc, const RowCoef<V>& K,
   }
 }
 
+// wave index as a scalar (it is uniform across the wave)
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // ------------------------------------------------------------- init
-// alpha_0 = r (and its checkpoint) for every probe; mu_0 partials per tile.
+// Evaluates every probe once: alpha_0 = r (and its checkpoint), the code
+// table pcode, the weight table pw and the mu_0 partials per tile.
 template <typename V, int PW>
 __global__ __launch_bounds__(kBlock) void k_init(const InstDev* __restrict__ insts,
                                                  const int4* __restrict__ tmap, int nranges,
@@ -216,30 +261,39 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDev* __restrict__ ins
   const int4 tm = tmap[blockIdx.x / nranges];
   const int range = blockIdx.x % nranges;
   const InstDev& I = insts[tm.x];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
   if (pbase >= I.R) return;                              // wave-uniform, no barriers below
   const Lane L = lane_geometry(I, tm.y, tm.z, lane);
   const ProbeLane PL = probe_lane(I, L);
-  for (int u = 0; u < PW; ++u) {
-    const int p = pbase + u;
-    if (p >= I.R) break;
+  const int pend = min(pbase + PW, I.R);
+  for (int p = pbase; p < pend; ++p) {
     double w;
     const int k = probe_code(I, PL, L, p, w);
     const Cx<V> r = phase_times<V>(k, V(1));
     const unsigned rec = (unsigned)(p * I.N) + L.site;
+    const unsigned nib = k >= 0 ? (8u | (unsigned)k) : 0u;
+    const unsigned other = (unsigned)__shfl_xor((int)nib, 1, 64);
     if (L.valid) {
       stg_comp<V>(I.A[0], rec, L.a, r);
       if (store_ckpt)
         stg_comp<V>((char*)I.ckpt + ckpt_slot(0, k_ckpt) * (long long)I.R * I.N * sizeof(typename RecT<V>::T),
                     rec, L.a, r);
+      if (L.a == 0) I.pcode[rec] = (unsigned char)(nib | (other << 4));
     }
-    const double s = wave_sum((L.valid && k >= 0) ? 1.0 : 0.0);
+    if (tm.w == 0 && lane == 0) I.pw[p] = w;
+    const double s = wave_moment(1.0, L.valid && k >= 0);
     if (lane == 0) I.mom[((long long)0 * I.R + p) * I.nchunk + tm.w] = s;
   }
 }
 
 // ------------------------------------------------------------- forward step
+// Loads of a probe are issued PD (forward) / PDA (adjoint) probes ahead of
+// its use: a ring of staged halo records, own-site values and code bytes held
+// in registers.
+constexpr int PD = 2;
+constexpr int PDA = 1;
+
 // alpha_{m+1} into A[(m+1)&1] (holding alpha_{m-1}) from alpha_m in A[m&1];
 // m == 0: alpha_1 = H~ alpha_0.  Moment partial of alpha_{m+1} per (probe, tile).
 template <typename V, int PW>
@@ -251,12 +305,11 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   const int4 tm = tmap[blockIdx.x / nranges];
   const int range = blockIdx.x % nranges;
   const InstDev& I = insts[tm.x];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
   if (pbase >= I.R) return;                              // wave-uniform; waves never sync
   const int N = I.N;
   const Lane L = lane_geometry(I, tm.y, tm.z, lane);
-  const ProbeLane PL = probe_lane(I, L);
   RowCoef<V> K;
   load_row<V>(K, I, L);
   const void* cur = I.A[m & 1];
@@ -265,47 +318,53 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   const bool ck = store_ckpt && ((mo % k_ckpt) <= 1);
   void* ckbuf = ck ? (void*)((char*)I.ckpt + ckpt_slot(mo, k_ckpt) * (long long)I.R * N * sizeof(R4))
                    : nullptr;
+  double* mom = I.mom + (long long)mo * I.R * I.nchunk + tm.w;
   const int pend = min(pbase + PW, I.R);
-  // software pipeline, distance one probe: the halo record and alpha_{m-1} of
-  // probe p+1 are in flight while probe p is computed
-  R4 stage = ldg_rec<V>(cur, (unsigned)(pbase * N) + L.halo);
-  Cx<V> prev_next{V(0), V(0)};
-  if (m > 0) prev_next = ldg_comp<V>(nxt, (unsigned)(pbase * N) + L.site, L.a);
-  for (int p = pbase; p < pend; ++p) {
-    const int buf = (p - pbase) & 1;
-    R4* lds = S.r[wave][buf][0];
-    if (lane < HREC) lds[lane] = stage;
-    __builtin_amdgcn_wave_barrier();
-    const unsigned rec = (unsigned)(p * N) + L.site;
-    const Cx<V> prev = prev_next;
-    if (p + 1 < pend) {
-      stage = ldg_rec<V>(cur, (unsigned)((p + 1) * N) + L.halo);
-      if (m > 0) prev_next = ldg_comp<V>(nxt, rec + (unsigned)N, L.a);
+  R4 st[PD];
+  Cx<V> pq[PD];
+  unsigned cq[PD];
+#pragma unroll
+  for (int u = 0; u < PD; ++u) {
+    pq[u] = Cx<V>{V(0), V(0)};
+    cq[u] = 0u;
+    const int p = pbase + u;
+    if (p < pend) {
+      st[u] = ldg_rec<V>(cur, (unsigned)(p * N) + L.halo);
+      if (m > 0) pq[u] = ldg_comp<V>(nxt, (unsigned)(p * N) + L.site, L.a);
+      cq[u] = ldg_code(I, (unsigned)(p * N) + L.site);
     }
-    Cx<V> o{V(0), V(0)};
-    row_apply<V>(o, K, lds, L);
-    if (m > 0) {
-      o.x = fma(V(2), o.x, -prev.x);
-      o.y = fma(V(2), o.y, -prev.y);
+  }
+  for (int p0 = pbase; p0 < pend; p0 += PD) {
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      const int p = p0 + u;
+      if (p >= pend) break;
+      R4* lds = S.r[wave][u & 1][0];
+      if (lane < HREC) lds[lane] = st[u];
+      __builtin_amdgcn_wave_barrier();
+      const unsigned rec = (unsigned)(p * N) + L.site;
+      const Cx<V> prev = pq[u];
+      const unsigned code = cq[u];
+      if (p + PD < pend) {
+        st[u] = ldg_rec<V>(cur, (unsigned)((p + PD) * N) + L.halo);
+        if (m > 0) pq[u] = ldg_comp<V>(nxt, rec + (unsigned)(PD * N), L.a);
+        cq[u] = ldg_code(I, rec + (unsigned)(PD * N));
+      }
+      Cx<V> o{V(0), V(0)};
+      row_apply<V>(o, K, lds, L);
+      if (m > 0) {
+        o.x = fma(V(2), o.x, -prev.x);
+        o.y = fma(V(2), o.y, -prev.y);
+      }
+      if (L.valid) {
+        stg_comp<V>(nxt, rec, L.a, o);
+        if (ck) stg_comp<V>(ckbuf, rec, L.a, o);
+      }
+      const int k = L.valid ? lane_code(code, L.a) : -1;
+      const double v = wave_moment(re_conj_phase<V>(k, o), k >= 0);
+      if (lane == 0) mom[(long long)p * I.nchunk] = v;
+      __builtin_amdgcn_wave_barrier();
     }
-    if (L.valid) {
-      stg_comp<V>(nxt, rec, L.a, o);
-      if (ck) stg_comp<V>(ckbuf, rec, L.a, o);
-    }
-    double w;
-    const int k = L.valid ? probe_code(I, PL, L, p, w) : -1;
-    if (__ballot(k >= 0)) {
-      double v = 0.0;
-      if (k == 0) v = (double)o.x;
-      else if (k == 1) v = (double)o.y;
-      else if (k == 2) v = -(double)o.x;
-      else if (k == 3) v = -(double)o.y;
-      v = wave_sum(v);
-      if (lane == 0) I.mom[((long long)mo * I.R + p) * I.nchunk + tm.w] = v;
-    } else if (lane == 0) {
-      I.mom[((long long)mo * I.R + p) * I.nchunk + tm.w] = 0.0;
-    }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -318,26 +377,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(const InstDev* __restrict__
   const int4 tm = tmap[blockIdx.x / nranges];
   const int range = blockIdx.x % nranges;
   const InstDev& I = insts[tm.x];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
   const Lane L = lane_geometry(I, tm.y, tm.z, lane);
   if (range * WAVES * PW >= I.R) return;
-  // clear this (tile, range)'s partial sums: each wave clears entries of its own lanes
+  // clear this (tile, range)'s partial sums: the two lanes of a site split the entries
   if (L.valid && wave == 0) {
     double2* gp = I.gpart + (long long)range * kNent * I.N;
     for (int e = L.a; e < kNent; e += 2) gp[(long long)e * I.N + L.site] = make_double2(0.0, 0.0);
   }
   if (pbase >= I.R) return;
-  const ProbeLane PL = probe_lane(I, L);
   const double cM = I.C[M - 1];
-  for (int u = 0; u < PW; ++u) {
-    const int p = pbase + u;
-    if (p >= I.R) break;
-    double w;
-    const int k = probe_code(I, PL, L, p, w);
+  const int pend = min(pbase + PW, I.R);
+  for (int p = pbase; p < pend; ++p) {
     const unsigned rec = (unsigned)(p * I.N) + L.site;
     if (L.valid) {
-      stg_comp<V>(I.G[(M - 2) & 1], rec, L.a, phase_times<V>(k, (V)(w * cM)));
+      const int k = lane_code(ldg_code(I, rec), L.a);
+      stg_comp<V>(I.G[(M - 2) & 1], rec, L.a, phase_times<V>(k, (V)(I.pw[p] * cM)));
       stg_comp<V>(I.G[(M - 1) & 1], rec, L.a, Cx<V>{V(0), V(0)});
     }
   }
@@ -361,12 +417,11 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   const int range = blockIdx.x % nranges;
   const InstDev& I = insts[tm.x];
   if (range * WAVES * PW >= I.R) return;                 // block-uniform
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
   const int pend = min(pbase + PW, I.R);
   const int N = I.N;
   const Lane L = lane_geometry(I, tm.y, tm.z, lane);
-  const ProbeLane PL = probe_lane(I, L);
   RowCoef<V> K;
   if (!tail) load_row<V>(K, I, L);
   const int src = tail ? m : m + 1;
@@ -374,7 +429,7 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   const void* Gx = I.G[src & 1];
   void* Ay = I.A[m & 1];
   void* Gy = I.G[m & 1];
-  const V Cm1 = tail ? V(0) : (V)I.C[m + 1];
+  const double Cm1 = tail ? 0.0 : I.C[m + 1];
   const bool anchor = !tail && ((m % k_ckpt) <= 1);
   const void* ckbuf = anchor ? (const void*)((const char*)I.ckpt +
                                              ckpt_slot(m, k_ckpt) * (long long)I.R * N * sizeof(R4))
@@ -382,75 +437,88 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   Cx<V> G[10];
 #pragma unroll
   for (int e = 0; e < 10; ++e) G[e] = Cx<V>{V(0), V(0)};
-  // software pipeline, distance one probe (halo records of alpha_{m+1},
-  // gamma_{m+1} and the own-site m+2 values of probe p+1 in flight)
-  R4 sa, sg;
-  Cx<V> a2n{V(0), V(0)}, g2n{V(0), V(0)};
+  // software pipeline, distance PDA probes (halo records of alpha_{m+1},
+  // gamma_{m+1}, the own-site m+2 values and the probe code)
   const void* Asrc = anchor ? ckbuf : (const void*)Ay;
-  if (pbase < pend) {
-    sa = ldg_rec<V>(Ax, (unsigned)(pbase * N) + L.halo);
-    sg = ldg_rec<V>(Gx, (unsigned)(pbase * N) + L.halo);
-    if (!tail) {
-      g2n = ldg_comp<V>(Gy, (unsigned)(pbase * N) + L.site, L.a);
-      a2n = ldg_comp<V>(Asrc, (unsigned)(pbase * N) + L.site, L.a);
+  R4 sa[PDA], sg[PDA];
+  Cx<V> aq[PDA], gq[PDA];
+  unsigned cq[PDA];
+#pragma unroll
+  for (int u = 0; u < PDA; ++u) {
+    aq[u] = Cx<V>{V(0), V(0)};
+    gq[u] = Cx<V>{V(0), V(0)};
+    cq[u] = 0u;
+    const int p = pbase + u;
+    if (p < pend) {
+      sa[u] = ldg_rec<V>(Ax, (unsigned)(p * N) + L.halo);
+      sg[u] = ldg_rec<V>(Gx, (unsigned)(p * N) + L.halo);
+      if (!tail) {
+        gq[u] = ldg_comp<V>(Gy, (unsigned)(p * N) + L.site, L.a);
+        aq[u] = ldg_comp<V>(Asrc, (unsigned)(p * N) + L.site, L.a);
+        cq[u] = ldg_code(I, (unsigned)(p * N) + L.site);
+      }
     }
   }
-  for (int p = pbase; p < pend; ++p) {
-    const int buf = (p - pbase) & 1;
-    R4* la = S.st.r[wave][buf][0];
-    R4* lg = S.st.r[wave][buf][1];
-    if (lane < HREC) {
-      la[lane] = sa;
-      lg[lane] = sg;
-    }
-    __builtin_amdgcn_wave_barrier();
-    const unsigned rec = (unsigned)(p * N) + L.site;
-    const Cx<V> a2 = a2n, g2 = g2n;
-    if (p + 1 < pend) {
-      sa = ldg_rec<V>(Ax, (unsigned)((p + 1) * N) + L.halo);
-      sg = ldg_rec<V>(Gx, (unsigned)((p + 1) * N) + L.halo);
-      if (!tail) {
-        g2n = ldg_comp<V>(Gy, rec + (unsigned)N, L.a);
-        a2n = ldg_comp<V>(Asrc, rec + (unsigned)N, L.a);
-      }
-    }
-    // dOmega/dH~ contribution of index src: conj(gamma_(i,a)) alpha_(j,b)
-    const Cx<V> gi = comp_of<V>(lg[L.hoff[0]], L.a);
+  for (int p0 = pbase; p0 < pend; p0 += PDA) {
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const R4 v = la[L.hoff[1 + d]];
-      cfma_conj(G[2 * d + 0], gi, comp_of<V>(v, 0));
-      cfma_conj(G[2 * d + 1], gi, comp_of<V>(v, 1));
-    }
-    {
-      const R4 v = la[L.hoff[0]];
-      // a = 0: entries 16 (b = 0) and 18 (b = 1); a = 1: entry 17 (b = 1)
-      cfma_conj(G[8], gi, comp_of<V>(v, L.a));
-      cfma_conj(G[9], gi, comp_of<V>(v, 1));
-    }
-    if (!tail) {
-      // gamma_m row a
-      Cx<V> gn{V(0), V(0)};
-      row_apply<V>(gn, K, lg, L);
-      double w;
-      const int k = probe_code(I, PL, L, p, w);
-      const Cx<V> s = phase_times<V>(k, (V)w * Cm1);
-      gn.x = fma(V(2), gn.x, s.x - g2.x);
-      gn.y = fma(V(2), gn.y, s.y - g2.y);
-      // alpha_m row a: checkpoint or reversed recursion
-      Cx<V> an = a2;
-      if (!anchor) {
-        Cx<V> t{V(0), V(0)};
-        row_apply<V>(t, K, la, L);
-        an.x = fma(V(2), t.x, -a2.x);
-        an.y = fma(V(2), t.y, -a2.y);
+    for (int u = 0; u < PDA; ++u) {
+      const int p = p0 + u;
+      if (p >= pend) break;
+      R4* la = S.st.r[wave][u & 1][0];
+      R4* lg = S.st.r[wave][u & 1][1];
+      if (lane < HREC) {
+        la[lane] = sa[u];
+        lg[lane] = sg[u];
       }
-      if (L.valid) {
-        stg_comp<V>(Gy, rec, L.a, gn);
-        stg_comp<V>(Ay, rec, L.a, an);
+      __builtin_amdgcn_wave_barrier();
+      const unsigned rec = (unsigned)(p * N) + L.site;
+      const Cx<V> a2 = aq[u], g2 = gq[u];
+      const unsigned code = cq[u];
+      if (p + PDA < pend) {
+        sa[u] = ldg_rec<V>(Ax, (unsigned)((p + PDA) * N) + L.halo);
+        sg[u] = ldg_rec<V>(Gx, (unsigned)((p + PDA) * N) + L.halo);
+        if (!tail) {
+          gq[u] = ldg_comp<V>(Gy, rec + (unsigned)(PDA * N), L.a);
+          aq[u] = ldg_comp<V>(Asrc, rec + (unsigned)(PDA * N), L.a);
+          cq[u] = ldg_code(I, rec + (unsigned)(PDA * N));
+        }
       }
+      // dOmega/dH~ contribution of index src: conj(gamma_(i,a)) alpha_(j,b)
+      const Cx<V> gi = comp_of<V>(lg[L.hoff[0]], L.a);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const R4 v = la[L.hoff[1 + d]];
+        cfma_conj(G[2 * d + 0], gi, comp_of<V>(v, 0));
+        cfma_conj(G[2 * d + 1], gi, comp_of<V>(v, 1));
+      }
+      {
+        const R4 v = la[L.hoff[0]];
+        // a = 0: entries 16 (b = 0) and 18 (b = 1); a = 1: entry 17 (b = 1)
+        cfma_conj(G[8], gi, comp_of<V>(v, L.a));
+        cfma_conj(G[9], gi, comp_of<V>(v, 1));
+      }
+      if (!tail) {
+        // gamma_m row a
+        Cx<V> gn{V(0), V(0)};
+        row_apply<V>(gn, K, lg, L);
+        const Cx<V> sr = phase_times<V>(lane_code(code, L.a), (V)(I.pw[p] * Cm1));
+        gn.x = fma(V(2), gn.x, sr.x - g2.x);
+        gn.y = fma(V(2), gn.y, sr.y - g2.y);
+        // alpha_m row a: checkpoint or reversed recursion
+        Cx<V> an = a2;
+        if (!anchor) {
+          Cx<V> t{V(0), V(0)};
+          row_apply<V>(t, K, la, L);
+          an.x = fma(V(2), t.x, -a2.x);
+          an.y = fma(V(2), t.y, -a2.y);
+        }
+        if (L.valid) {
+          stg_comp<V>(Gy, rec, L.a, gn);
+          stg_comp<V>(Ay, rec, L.a, an);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
   }
   // sum the 4 waves' partials in LDS, then one read-modify-write per (site, entry)
   __syncthreads();

@@ -11,6 +11,7 @@
 //   ckpt   [S][R][N] rec     checkpoint alpha_j for j % k in {0, 1}, slot 2(j/k)+j%k
 //   mom    [M][R][ntile]     per-(step, probe, 8x4 tile) moment partials
 //   gpart  [nrange][19][N] double2  per-probe-range partial dOmega/dH~ (FP64)
+//   pcode  [R][N] bytes      probe entries (written once per call by the alpha_0 kernel)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,6 +51,9 @@ struct InstDev {
   double* musum;      // [R][M] reduced moments
   double2* gpart;     // [npb][19][N] partial dOmega/dH~ per probe range
   double* opart;      // [ceil(M/256)] partial sums of Omega
+  unsigned char* pcode;  // [R][N] probe entries: nibble a (bits 4a..4a+3) of site i is
+                         // 8 | k for entry i^k of Nambu component a, 0 for a zero entry
+  double* pw;            // [R] probe weights
   double2* rho;       // [19][N] output
   const double* omega_bar;
   double* omega;
