@@ -31,6 +31,7 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
+PMC_ARGS = "--moments 256 --steps 1 --warmup 0 --no-cpu-baseline --no-fp64-form --no-kernel-timing"
 METRIC = "Chebyshev vector-steps/s + HBM GB/s; s per KPM energy+gradient at 100x100"
 
 
@@ -53,6 +54,65 @@ def traffic_record(kernel: str):
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def _pmc_rows(d, counter):
+    """Per-dispatch values of one counter from a rocprofv3 --pmc CSV directory,
+    keyed by kernel name."""
+    import csv
+    import glob
+    vals = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} rows under {d}")
+    return vals
+
+
+def traffic_summary(base: str, copy_bytes: int) -> None:
+    """Turn the four rocprofv3 --pmc runs under ``base`` (fetch/, write/: the
+    workload; copyf/, copyw/: one plain copy of ``copy_bytes``) into the
+    traffic record of the recursion kernels (written under profiles/)."""
+    fetch, write = _pmc_rows(os.path.join(base, "fetch"), "FETCH_SIZE"), _pmc_rows(os.path.join(base, "write"), "WRITE_SIZE")
+    cf, cw = _pmc_rows(os.path.join(base, "copyf"), "FETCH_SIZE"), _pmc_rows(os.path.join(base, "copyw"), "WRITE_SIZE")
+    kib_f = max(max(v) for v in cf.values())      # the copy is the largest dispatch of its run
+    kib_w = max(max(v) for v in cw.values())
+    f_fetch, f_write = copy_bytes / (kib_f * 1024.0), copy_bytes / (kib_w * 1024.0)
+    out = {}
+    for short, tags in (("k_adj", (">::adj(", "k_adj<")), ("k_fwd", (">::fwd(", "k_fwd<"))):
+        fr = [v for k, vs in fetch.items() if any(t in k for t in tags) for v in vs]
+        wr = [v for k, vs in write.items() if any(t in k for t in tags) for v in vs]
+        if not fr or not wr:
+            raise SystemExit(f"no dispatches of {short} in the counter runs")
+        fk, wk = sum(fr) / len(fr), sum(wr) / len(wr)
+        out[short] = {
+            "kernel_source_sha256_16": kernel_source_hash(),
+            "dispatches": len(fr),
+            "FETCH_SIZE_KiB_per_dispatch": fk,
+            "WRITE_SIZE_KiB_per_dispatch": wk,
+            "copy_calibration": {"bytes": copy_bytes, "FETCH_SIZE_KiB": kib_f, "WRITE_SIZE_KiB": kib_w,
+                                 "fetch_factor": f_fetch, "write_factor": f_write},
+            "hbm_bytes_per_launch": fk * 1024.0 * f_fetch + wk * 1024.0 * f_write,
+            "note": "bytes leaving L2 for the memory fabric (Infinity Cache hits included), "
+                    "scaled by what the same counters read for a plain copy of known size",
+            "commands": [
+                "cd /tmp && export TMPDIR=/tmp",
+                f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {base}/fetch -o fetch -- python3 bench.py {PMC_ARGS}",
+                f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {base}/write -o write -- python3 bench.py {PMC_ARGS}",
+                f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {base}/copyf -o copyf -- python3 bench.py "
+                f"--copy-calibration {copy_bytes}",
+                f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {base}/copyw -o copyw -- python3 bench.py "
+                f"--copy-calibration {copy_bytes}",
+                f"python3 bench.py --traffic-summary {base}",
+            ],
+        }
+    for short, rec in out.items():
+        path = os.path.join(ROOT, "profiles", f"{short}_c5_fp32_traffic.json")
+        with open(path, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(f"{path}: {rec['hbm_bytes_per_launch'] / 1e6:.1f} MB per launch")
 
 
 def make_problem(cfg, precision):
@@ -152,7 +212,13 @@ def main():
                     help="probes per wave of the recursion kernels (0 = library default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES (counter calibration) and exit")
+    ap.add_argument("--traffic-summary", default="", metavar="DIR",
+                    help="summarise rocprofv3 FETCH_SIZE/WRITE_SIZE runs under DIR (fetch/ write/ copyf/ "
+                         "copyw/) into profiles/k_*_c5_fp32_traffic.json and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary, args.copy_calibration or (1 << 30))
+        return
     if args.gpus != 1:
         print("bench.py measures one MI355X: this build runs on a single GPU only "
               "(multi-GPU probe sharding is described in DESIGN.md, not built).", file=sys.stderr)
