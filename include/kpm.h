@@ -155,7 +155,8 @@ size_t kpm_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int32_t 
  * alpha_{m-1} (App. B eq. alpha).  Vectors in `precision`, sums in FP64.
  * mu: [R][M] doubles (real parts; the imaginary parts vanish for Hermitian h).
  * ws: workspace of at least kpm_workspace_size(lat, R, M, ckpt_k, precision)
- * bytes, 256-byte aligned. */
+ * bytes, 256-byte aligned.  R * Lx * Ly must be below 2^31 (else KPM_EINVAL;
+ * the same holds for every instance of a batch plan). */
 int kpm_moments(const kpm_lattice* lat, const double* h, const double* ab,
                 const kpm_probes* probes, int32_t M, int32_t precision, int32_t ckpt_k,
                 double* mu, void* ws, size_t ws_bytes, void* stream);

@@ -70,6 +70,11 @@ long long group_nprobes(const kpm_probe_group& g) {
   return g.count;
 }
 
+// Probe-vector records are addressed with 32-bit indices p * N + site.
+bool records_fit(const kpm_lattice* L, int R) {
+  return (long long)R * L->Lx * L->Ly < (1LL << 31);
+}
+
 // Fills the device group table; returns R or < 0.
 int build_groups(const kpm_lattice* L, const kpm_probes* pr, GroupDev* out, int* ng) {
   if (!pr || !pr->groups || pr->ngroups < 1 || pr->ngroups > KPM_MAX_PROBE_GROUPS) return -1;
@@ -324,7 +329,7 @@ int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* 
   std::memset(&I, 0, sizeof(I));
   int ng = 0;
   const int R = build_groups(L, pr, I.g, &ng);
-  if (R < 1) return KPM_EINVAL;
+  if (R < 1 || !records_fit(L, R)) return KPM_EINVAL;
   c.fp32 = prec == KPM_FP32;
   const Sizes z = sizes(L, R, M, k, c.fp32);
   const WsLayout w = ws_layout(z);
@@ -625,7 +630,7 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
     std::memset(&insts[q], 0, sizeof(InstDev));
     int ng = 0;
     const int R = build_groups(&lats[q], &probes[q], insts[q].g, &ng);
-    if (R < 1) return KPM_EINVAL;
+    if (R < 1 || !records_fit(&lats[q], R)) return KPM_EINVAL;
     zs[q] = sizes(&lats[q], R, M, ckpt_k, fp32);
     insts[q].Lx = lats[q].Lx;
     insts[q].Ly = lats[q].Ly;

@@ -198,14 +198,18 @@ __global__ __launch_bounds__(kBlock) void k_build_vjp(ModelDev md, const double*
   dn[i] = -dLdd;
 }
 
-// Gershgorin bounds -> ab = (a, b); one block.  On a non-finite or empty
-// interval a is set to NaN (the recursion then reports KPM_EBOUNDS).
-__global__ __launch_bounds__(kBlock) void k_bounds(int Lx, int Ly, const double2* __restrict__ h,
+// Gershgorin bounds -> ab = (a, b); one block of kBoundsBlock threads (the
+// max / min are order-independent, so the result is deterministic).  On a
+// non-finite or empty interval a is set to NaN (the recursion then reports
+// KPM_EBOUNDS).
+constexpr int kBoundsBlock = 1024;
+
+__global__ __launch_bounds__(kBoundsBlock) void k_bounds(int Lx, int Ly, const double2* __restrict__ h,
                                                    double* __restrict__ ab) {
   const int N = Lx * Ly;
   double emax = -1e300, emin = 1e300;
   int finite = 1;
-  for (int i = threadIdx.x; i < N; i += kBlock) {
+  for (int i = threadIdx.x; i < N; i += kBoundsBlock) {
     double r0 = 0.0, r1 = 0.0;
     double2 p = h[(long long)18 * N + i];
     double ap = hypot(p.x, p.y);
@@ -228,13 +232,13 @@ __global__ __launch_bounds__(kBlock) void k_bounds(int Lx, int Ly, const double2
     emin = fmin(emin, fmin(c0 - r0, c1 - r1));
     if (!(isfinite(c0 + r0) && isfinite(c1 + r1) && isfinite(c0 - r0) && isfinite(c1 - r1))) finite = 0;
   }
-  __shared__ double smax[kBlock], smin[kBlock];
-  __shared__ int sfin[kBlock];
+  __shared__ double smax[kBoundsBlock], smin[kBoundsBlock];
+  __shared__ int sfin[kBoundsBlock];
   smax[threadIdx.x] = emax;
   smin[threadIdx.x] = emin;
   sfin[threadIdx.x] = finite;
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
+  for (int s = kBoundsBlock / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
       smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
@@ -291,37 +295,46 @@ template __global__ void k_rescale<double>(const InstDev*, const int2*);
 
 // C_m = (2 - delta_m0) g_m (1/K) sum_k cos(m th_k) f(a cos th_k + b).
 // cos(m th_k) = cospi(j/(2K)) with the exact integer j = m(2k+1) mod 4K.
+// A block handles kCoefM consecutive m: 16 lanes per m run over k (lane l
+// takes k = l, l + 16, ...), f(x_k) is evaluated once per block in LDS, and
+// the 16 lane sums of each m are added in a fixed butterfly order.
+constexpr int kCoefM = kBlock / 16;
+
 __global__ __launch_bounds__(kBlock) void k_coeffs(int M, int K, double T,
                                                    const double* __restrict__ ab,
                                                    double* __restrict__ C) {
   __shared__ double F[kBlock];
-  const int m = blockIdx.x * kBlock + threadIdx.x;
+  const int lane16 = threadIdx.x & 15;
+  const int m = blockIdx.x * kCoefM + (threadIdx.x >> 4);
   const double a = ab[0], b = ab[1];
   const long long fourK = 4LL * K;
   const double inv2K = 1.0 / (2.0 * (double)K);
+  const long long mm = m < M ? m : 0;
+  long long j = (mm * (2LL * lane16 + 1)) % fourK;     // k = lane16
+  const long long step = (32LL * mm) % fourK;           // k -> k + 16
   double acc = 0.0;
-  long long j = m % fourK;                      // m (2k + 1) for k = 0
-  const long long step = (2LL * m) % fourK;
   for (int k0 = 0; k0 < K; k0 += kBlock) {
-    int k = k0 + threadIdx.x;
+    const int k = k0 + threadIdx.x;
     if (k < K) {
-      double x = cospi((2.0 * k + 1.0) * inv2K);
-      double e = a * x + b;
+      const double x = cospi((2.0 * k + 1.0) * inv2K);
+      const double e = a * x + b;
       F[threadIdx.x] = fmin(e, 0.0) - T * log1p(exp(-fabs(e) / T));
     }
     __syncthreads();
-    int kmax = min(kBlock, K - k0);
-    for (int kk = 0; kk < kmax; ++kk) {
+    const int kmax = min(kBlock, K - k0);
+    for (int kk = lane16; kk < kmax; kk += 16) {
       acc += F[kk] * cospi((double)j * inv2K);
       j += step;
       if (j >= fourK) j -= fourK;
     }
     __syncthreads();
   }
-  if (m < M) {
-    double c = acc / (double)K;
-    double q = 1.0 / (double)(M + 1);
-    double g = ((double)(M - m + 1) * cospi(m * q) + sinpi(m * q) * cospi(q) / sinpi(q)) * q;
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 16);
+  if (m < M && lane16 == 0) {
+    const double c = acc / (double)K;
+    const double q = 1.0 / (double)(M + 1);
+    const double g = ((double)(M - m + 1) * cospi(m * q) + sinpi(m * q) * cospi(q) / sinpi(q)) * q;
     C[m] = (m == 0 ? 1.0 : 2.0) * g * c;
   }
 }
@@ -350,7 +363,7 @@ hipError_t launch_build_vjp(const ModelDev& md, const double* n, const double* c
 }
 
 hipError_t launch_bounds(int Lx, int Ly, const double* h, double* ab, hipStream_t s) {
-  hipLaunchKernelGGL(k_bounds, dim3(1), dim3(kBlock), 0, s, Lx, Ly,
+  hipLaunchKernelGGL(k_bounds, dim3(1), dim3(kBoundsBlock), 0, s, Lx, Ly,
                      reinterpret_cast<const double2*>(h), ab);
   return hipGetLastError();
 }
@@ -365,7 +378,7 @@ hipError_t launch_rescale(const InstDev* insts, const int2* cmap, int nchunks, b
 }
 
 hipError_t launch_coeffs(int M, int K, double T, const double* ab, double* C, hipStream_t s) {
-  dim3 grid((M + kBlock - 1) / kBlock);
+  dim3 grid((M + kCoefM - 1) / kCoefM);
   hipLaunchKernelGGL(k_coeffs, grid, dim3(kBlock), 0, s, M, K, T, ab, C);
   return hipGetLastError();
 }

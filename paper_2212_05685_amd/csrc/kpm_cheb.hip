@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDev* __restrict__ ins
     }
     if (tm.w == 0 && lane == 0) I.pw[p] = w;
     const double s = wave_moment(1.0, L.valid && k >= 0);
-    if (lane == 0) I.mom[((long long)0 * I.R + p) * I.nchunk + tm.w] = s;
+    if (lane == 0) I.mom[(long long)tm.w * I.R + p] = s;
   }
 }
 
@@ -318,7 +318,7 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   const bool ck = store_ckpt && ((mo % k_ckpt) <= 1);
   void* ckbuf = ck ? (void*)((char*)I.ckpt + ckpt_slot(mo, k_ckpt) * (long long)I.R * N * sizeof(R4))
                    : nullptr;
-  double* mom = I.mom + (long long)mo * I.R * I.nchunk + tm.w;
+  double* mom = I.mom + ((long long)mo * I.nchunk + tm.w) * I.R;
   const int pend = min(pbase + PW, I.R);
   R4 st[PD];
   Cx<V> pq[PD];
@@ -362,7 +362,7 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
       }
       const int k = L.valid ? lane_code(code, L.a) : -1;
       const double v = wave_moment(re_conj_phase<V>(k, o), k >= 0);
-      if (lane == 0) mom[(long long)p * I.nchunk] = v;
+      if (lane == 0) mom[p] = v;
       __builtin_amdgcn_wave_barrier();
     }
   }
@@ -585,16 +585,18 @@ template <int PW> struct StepKernels<double, PW> {
 };
 
 // ------------------------------------------------------------- finishing
-// mu[p][m] = sum over tiles (fixed order); also the [R][M] user copy.
+// mu[p][m] = sum over tiles (fixed order); also the [R][M] user copy.  Threads
+// run over (m, p) with p fastest, so each pass of the tile loop reads
+// consecutive probes' partials.
 __global__ __launch_bounds__(kBlock) void k_mom_reduce(const InstDev* __restrict__ insts, int M,
                                                        double* __restrict__ mu_user) {
   const InstDev& I = insts[blockIdx.y];
   const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (t >= (long long)I.R * M) return;
-  const int p = (int)(t / M), m = (int)(t - (long long)p * M);
-  const double* src = I.mom + ((long long)m * I.R + p) * I.nchunk;
+  const int m = (int)(t / I.R), p = (int)(t - (long long)m * I.R);
+  const double* src = I.mom + (long long)m * I.nchunk * I.R + p;
   double s = 0.0;
-  for (int c = 0; c < I.nchunk; ++c) s += src[c];
+  for (int c = 0; c < I.nchunk; ++c) s += src[(long long)c * I.R];
   I.musum[(long long)p * M + m] = s;
   if (mu_user) mu_user[(long long)p * M + m] = s;
 }

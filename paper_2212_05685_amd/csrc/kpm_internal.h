@@ -9,7 +9,7 @@
 //                            rec = two complex values (Nambu 0, 1) of one site
 //                            (float4 = 16 B in FP32, 2 x double2 = 32 B in FP64)
 //   ckpt   [S][R][N] rec     checkpoint alpha_j for j % k in {0, 1}, slot 2(j/k)+j%k
-//   mom    [M][R][ntile]     per-(step, probe, 8x4 tile) moment partials
+//   mom    [M][ntile][R]     per-(step, 8x4 tile, probe) moment partials
 //   gpart  [nrange][19][N] double2  per-probe-range partial dOmega/dH~ (FP64)
 //   pcode  [R][N] bytes      probe entries (written once per call by the alpha_0 kernel)
 #pragma once
@@ -47,7 +47,7 @@ struct InstDev {
   void* A[2];
   void* G[2];
   void* ckpt;
-  double* mom;        // [M][R][nchunk] moment partials (nchunk = recursion tiles)
+  double* mom;        // [M][nchunk][R] moment partials (nchunk = recursion tiles)
   double* musum;      // [R][M] reduced moments
   double2* gpart;     // [npb][19][N] partial dOmega/dH~ per probe range
   double* opart;      // [ceil(M/256)] partial sums of Omega

@@ -36,6 +36,13 @@ def coefficients(cfg: wl.Config, a, b, M=None):
     return chebyshev.kpm_coefficients(cfg.M if M is None else M, cfg.T, a, b)
 
 
+def oracle_inputs(cfg: wl.Config, M=None):
+    """Stencil, rescaling (a, b) and coefficients, all computed by the oracle."""
+    st = stencil(cfg)
+    a, b = bounds(cfg, st)
+    return st, a, b, coefficients(cfg, a, b, M)
+
+
 def probe_matrix(cfg: wl.Config):
     return probes.probe_set(oracle_groups(cfg), cfg.Lx, cfg.Ly)
 
