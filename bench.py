@@ -167,6 +167,80 @@ def timed(prob, th, steps, warmup, profile):
     return (t1 - t0) / steps, out, grads, prof
 
 
+def batched_form(steps: int):
+    """48 uneven lattices (24..64 sites on a side, doping 0.05-0.25, 2 or 4
+    vortices, M = 1024, 64 colored probes each): one batched FP32 energy +
+    gradient replayed as a hipGraph, against the plain FP64 single-lattice
+    form run lattice by lattice on the same inputs."""
+    import numpy as np
+    import torch
+    from paper_2212_05685_amd import kpm
+    import workloads as wl
+
+    cfgs = wl.C4_instances(48)
+    probs, hs, abs_, Cs = [], [], [], []
+    for cfg in cfgs:
+        q, th = make_problem(cfg, "fp32")
+        h = q.build_H(*th)
+        ab = q.bounds(h)
+        probs.append(q)
+        hs.append(h)
+        abs_.append(ab)
+        Cs.append(q.coefficients(ab))
+    M, k = cfgs[0].M, cfgs[0].ckpt_k
+    plan = kpm.kpm_batch_create([q.lat for q in probs], [q.probes for q in probs], M, kpm.KPM_FP32, k)
+    try:
+        omega = torch.zeros(len(cfgs), dtype=torch.float64, device="cuda")
+        rhos = [torch.zeros_like(h) for h in hs]
+        kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=True)   # tune + capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=True)
+        torch.cuda.synchronize()
+        dt32 = (time.perf_counter() - t0) / steps
+        om32 = omega.cpu().numpy()
+        r32 = [r.cpu().numpy() for r in rhos]
+    finally:
+        kpm.kpm_batch_destroy(plan)
+    log(f"batched FP32: {dt32 * 1e3:.1f} ms per energy + gradient of 48 lattices")
+    p64 = []
+    for cfg in cfgs:
+        q, _ = make_problem(cfg, "fp64")
+        p64.append(q)
+
+    def fp64_pass():
+        out = []
+        for q, h, ab, C in zip(p64, hs, abs_, Cs):
+            om = q.grand_potential(h, ab, C)
+            out.append((om, q.grand_potential_grad(h, ab, C)))
+        return out
+
+    fp64_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out64 = fp64_pass()
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t0
+    om64 = np.array([float(o.item()) for o, _ in out64])
+    e_om = float(np.max(np.abs(om32 - om64) / np.abs(om64)))
+    e_rho = max(float(np.max(np.abs(r32[q] - out64[q][1].cpu().numpy())) /
+                      np.max(np.abs(out64[q][1].cpu().numpy()))) for q in range(len(cfgs)))
+    vsteps = sum(q.R for q in probs) * (3 * M - 5)
+    log(f"FP64 lattice by lattice: {dt64 * 1e3:.1f} ms")
+    return {
+        "workload": "48 lattices L in {24..64}, doping U(0.05, 0.25), 2 or 4 vortices, M=1024, "
+                    "64 colored Z4 probes (8x8) each, checkpoints every 64",
+        "sites_total": int(sum(c.N for c in cfgs)),
+        "ms_per_step_fp32_batched_graph": dt32 * 1e3,
+        "ms_per_step_fp64_lattice_by_lattice": dt64 * 1e3,
+        "speedup_fp32_batched_over_fp64": dt64 / dt32,
+        "vector_steps_per_s_fp32_batched": vsteps / dt32,
+        "fp32_vs_fp64_max_rel_err_omega": e_om,
+        "fp32_vs_fp64_max_rel_err_rho": e_rho,
+    }
+
+
 def cpu_baseline(cfg):
     """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
     probe of the same workload, single thread."""
@@ -204,6 +278,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
+    ap.add_argument("--no-batched-form", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without per-kernel events (roofline fields omitted)")
     ap.add_argument("--moments", type=int, default=0,
@@ -319,6 +394,10 @@ def main():
             "fp32_vs_fp64_rel_err_dchi": float(np.max(np.abs(g32 - g64)) / np.max(np.abs(g64))),
         }
         del prob64
+        torch.cuda.empty_cache()
+
+    if not args.no_batched_form and not args.moments:
+        result["batched_form"] = batched_form(3)
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:

@@ -181,17 +181,16 @@ __device__ __forceinline__ unsigned ldg_code(const InstDev& I, unsigned idx) {
   return ((GPtr<unsigned char>)(I.pcode))[idx];
 }
 
+// i^k s (0 for k < 0), without branches
 template <typename V>
 __device__ __forceinline__ Cx<V> phase_times(int k, V s) {
-  Cx<V> r{V(0), V(0)};
-  if (k == 0) r.x = s;
-  else if (k == 1) r.y = s;
-  else if (k == 2) r.x = -s;
-  else if (k == 3) r.y = -s;
-  return r;
+  const V sv = (k & 2) ? -s : s;
+  const bool on = k >= 0;
+  return Cx<V>{(on && !(k & 1)) ? sv : V(0), (on && (k & 1)) ? sv : V(0)};
 }
 
-// Re(conj(i^k) z) in FP64 (0 for k < 0)
+// Re(conj(i^k) z) in FP64 (0 for k < 0).  Branches: for coloured and unit
+// probes only one lane of a tile has k >= 0, and the others skip the work.
 template <typename V>
 __device__ __forceinline__ double re_conj_phase(int k, const Cx<V>& z) {
   double v = 0.0;
@@ -237,16 +236,6 @@ template <typename V> struct Stage {
   typename RecT<V>::T r[WAVES][2][2][HREC];
 };
 
-template <typename V>
-__device__ __forceinline__ void row_apply(Cx<V>& acc, const RowCoef<V>& K,
-                                          const typename RecT<V>::T* lds, const Lane& L) {
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const typename RecT<V>::T v = lds[L.hoff[k]];
-    cfma(acc, K.c[2 * k + 0], comp_of<V>(v, 0));
-    cfma(acc, K.c[2 * k + 1], comp_of<V>(v, 1));
-  }
-}
 
 // wave index as a scalar (it is uniform across the wave)
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
@@ -284,6 +273,102 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDev* __restrict__ ins
     if (tm.w == 0 && lane == 0) I.pw[p] = w;
     const double s = wave_moment(1.0, L.valid && k >= 0);
     if (lane == 0) I.mom[(long long)tm.w * I.R + p] = s;
+  }
+}
+
+// ------------------------------------------------------------- addressing
+// Probe vectors are addressed as a wave-uniform base (buffer + p N records, in
+// scalar registers) plus a per-lane 32-bit byte offset, so that each load or
+// store is a single instruction with no per-lane 64-bit address arithmetic.
+template <typename V> using C2 = V __attribute__((ext_vector_type(2)));
+
+struct Off {
+  unsigned halo;   // byte offset of the record this lane stages
+  unsigned own;    // byte offset of the lane's own component (site, row a)
+};
+
+template <typename V>
+__device__ __forceinline__ Off lane_offsets(const Lane& L) {
+  constexpr unsigned RB = sizeof(typename RecT<V>::T), CB = RB / 2;
+  return Off{L.halo * RB, L.site * RB + (unsigned)L.a * CB};
+}
+
+template <typename V>
+__device__ __forceinline__ const char* probe_base(const void* buf, int p, int N) {
+  return (const char*)buf + (size_t)p * (size_t)N * sizeof(typename RecT<V>::T);
+}
+template <typename V>
+__device__ __forceinline__ typename RecT<V>::T ld_rec(const char* base, unsigned off) {
+  return *(GPtr<typename RecT<V>::T>)(base + off);
+}
+template <typename V>
+__device__ __forceinline__ Cx<V> ld_cx(const char* base, unsigned off) {
+  const C2<V> v = *(GPtr<C2<V>>)(base + off);
+  return Cx<V>{v.x, v.y};
+}
+template <typename V>
+__device__ __forceinline__ void st_cx(const char* base, unsigned off, const Cx<V>& v) {
+  C2<V> t;
+  t.x = v.x;
+  t.y = v.y;
+  *(GPtrW<C2<V>>)(const_cast<char*>(base) + off) = t;
+}
+__device__ __forceinline__ unsigned ld_code(const InstDev& I, int p, const Lane& L) {
+  return ((GPtr<unsigned char>)(I.pcode + (size_t)p * (size_t)I.N))[L.site];
+}
+// the lane's own Nambu component of a staged record (a half-record LDS read)
+template <typename V>
+__device__ __forceinline__ Cx<V> lds_own(const typename RecT<V>::T* rec, int a) {
+  const C2<V> h = ((const C2<V>*)rec)[a];
+  return Cx<V>{h.x, h.y};
+}
+
+// ------------------------------------------------------------- sparse rows
+// In the model's Hamiltonian the on-site Nambu block and the next-nearest-
+// neighbour blocks have no anomalous (pairing) entries: pairing lives on
+// nearest-neighbour bonds only (App. A).  For records k = 0 (site), 3, 4
+// (forward diagonal bonds) and 7, 8 (backward diagonal bonds) row a then only
+// couples to component a.  In the adjoint step (two row products per probe) a
+// wave whose lanes all see exact zeros there runs the 13-term rows instead of
+// the 18-term ones; any other stencil keeps the full rows.  (The forward step
+// keeps the full rows: measured on gfx950 the short rows did not pay there.)
+__device__ __forceinline__ constexpr bool nambu_diag(int k) {
+  return k == 0 || k == 3 || k == 4 || k == 7 || k == 8;
+}
+
+template <typename V>
+__device__ __forceinline__ bool wave_sparse(const RowCoef<V>& K, int a) {
+  bool z = true;
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    if (nambu_diag(k)) {
+      const Cx<V> c = a ? K.c[2 * k] : K.c[2 * k + 1];
+      z = z && c.x == V(0) && c.y == V(0);
+    }
+  return __all(z);
+}
+
+// Moves the coefficient (row a, component a) of those records to slot 2k.
+template <typename V>
+__device__ __forceinline__ void compact_row(RowCoef<V>& K, int a) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    if (nambu_diag(k)) K.c[2 * k] = a ? K.c[2 * k + 1] : K.c[2 * k];
+}
+
+// acc += row a of H~ times the staged vector (SP: compacted sparse row).
+template <typename V, bool SP>
+__device__ __forceinline__ void row_apply(Cx<V>& acc, const RowCoef<V>& K,
+                                          const typename RecT<V>::T* lds, const Lane& L) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (SP && nambu_diag(k)) {
+      cfma(acc, K.c[2 * k], lds_own<V>(lds + L.hoff[k], L.a));
+    } else {
+      const typename RecT<V>::T v = lds[L.hoff[k]];
+      cfma(acc, K.c[2 * k + 0], comp_of<V>(v, 0));
+      cfma(acc, K.c[2 * k + 1], comp_of<V>(v, 1));
+    }
   }
 }
 
@@ -351,7 +436,7 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
         cq[u] = ldg_code(I, rec + (unsigned)(PD * N));
       }
       Cx<V> o{V(0), V(0)};
-      row_apply<V>(o, K, lds, L);
+      row_apply<V, false>(o, K, lds, L);
       if (m > 0) {
         o.x = fma(V(2), o.x, -prev.x);
         o.y = fma(V(2), o.y, -prev.y);
@@ -399,6 +484,97 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(const InstDev* __restrict__
   }
 }
 
+// One wave's probes of adjoint step m (see adj_body).
+template <typename V, bool SP>
+__device__ __forceinline__ void adj_loop(const InstDev& I, const Lane& L, const RowCoef<V>& K,
+                                         typename RecT<V>::T (*stage)[2][HREC], int pbase,
+                                         int pend, int tail, bool anchor, double Cm1,
+                                         const void* Ax, const void* Gx, const void* Ay,
+                                         const void* Gy, const void* Asrc, Cx<V> (&G)[10],
+                                         int lane) {
+  using R4 = typename RecT<V>::T;
+  const int N = I.N;
+  const Off O = lane_offsets<V>(L);
+  // software pipeline, distance PDA probes (halo records of alpha_{m+1},
+  // gamma_{m+1}, the own-site m+2 values and the probe code)
+  R4 sa[PDA], sg[PDA];
+  Cx<V> aq[PDA], gq[PDA];
+  unsigned cq[PDA];
+#pragma unroll
+  for (int u = 0; u < PDA; ++u) {
+    aq[u] = Cx<V>{V(0), V(0)};
+    gq[u] = Cx<V>{V(0), V(0)};
+    cq[u] = 0u;
+    const int p = pbase + u;
+    if (p < pend) {
+      sa[u] = ld_rec<V>(probe_base<V>(Ax, p, N), O.halo);
+      sg[u] = ld_rec<V>(probe_base<V>(Gx, p, N), O.halo);
+      if (!tail) {
+        gq[u] = ld_cx<V>(probe_base<V>(Gy, p, N), O.own);
+        aq[u] = ld_cx<V>(probe_base<V>(Asrc, p, N), O.own);
+        cq[u] = ld_code(I, p, L);
+      }
+    }
+  }
+  for (int p0 = pbase; p0 < pend; p0 += PDA) {
+#pragma unroll
+    for (int u = 0; u < PDA; ++u) {
+      const int p = p0 + u;
+      if (p >= pend) break;
+      R4* la = stage[u & 1][0];
+      R4* lg = stage[u & 1][1];
+      if (lane < HREC) {
+        la[lane] = sa[u];
+        lg[lane] = sg[u];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const Cx<V> a2 = aq[u], g2 = gq[u];
+      const unsigned code = cq[u];
+      if (p + PDA < pend) {
+        sa[u] = ld_rec<V>(probe_base<V>(Ax, p + PDA, N), O.halo);
+        sg[u] = ld_rec<V>(probe_base<V>(Gx, p + PDA, N), O.halo);
+        if (!tail) {
+          gq[u] = ld_cx<V>(probe_base<V>(Gy, p + PDA, N), O.own);
+          aq[u] = ld_cx<V>(probe_base<V>(Asrc, p + PDA, N), O.own);
+          cq[u] = ld_code(I, p + PDA, L);
+        }
+      }
+      // dOmega/dH~ contribution of index src: conj(gamma_(i,a)) alpha_(j,b)
+      const Cx<V> gi = lds_own<V>(lg + L.hoff[0], L.a);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const R4 v = la[L.hoff[1 + d]];
+        cfma_conj(G[2 * d + 0], gi, comp_of<V>(v, 0));
+        cfma_conj(G[2 * d + 1], gi, comp_of<V>(v, 1));
+      }
+      // a = 0: entries 16 (b = 0) and 18 (b = 1); a = 1: entry 17 (b = 1)
+      cfma_conj(G[8], gi, lds_own<V>(la + L.hoff[0], L.a));
+      cfma_conj(G[9], gi, lds_own<V>(la + L.hoff[0], 1));
+      if (!tail) {
+        // gamma_m row a
+        Cx<V> gn{V(0), V(0)};
+        row_apply<V, SP>(gn, K, lg, L);
+        const Cx<V> sr = phase_times<V>(lane_code(code, L.a), (V)(I.pw[p] * Cm1));
+        gn.x = fma(V(2), gn.x, sr.x - g2.x);
+        gn.y = fma(V(2), gn.y, sr.y - g2.y);
+        // alpha_m row a: checkpoint or reversed recursion
+        Cx<V> an = a2;
+        if (!anchor) {
+          Cx<V> t{V(0), V(0)};
+          row_apply<V, SP>(t, K, la, L);
+          an.x = fma(V(2), t.x, -a2.x);
+          an.y = fma(V(2), t.y, -a2.y);
+        }
+        if (L.valid) {
+          st_cx<V>(probe_base<V>(Gy, p, N), O.own, gn);
+          st_cx<V>(probe_base<V>(Ay, p, N), O.own, an);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
 // Step m (0 <= m <= M-3): alpha_m, gamma_m from the m+1, m+2 vectors (the m+2
 // buffers are overwritten), plus 2 conj(gamma_{m+1}) x alpha_{m+1} into the
 // partial dOmega/dH~.  tail != 0: only conj(gamma_0) x alpha_0 (weight 1).
@@ -427,98 +603,31 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   const int src = tail ? m : m + 1;
   const void* Ax = I.A[src & 1];
   const void* Gx = I.G[src & 1];
-  void* Ay = I.A[m & 1];
-  void* Gy = I.G[m & 1];
+  const void* Ay = I.A[m & 1];
+  const void* Gy = I.G[m & 1];
   const double Cm1 = tail ? 0.0 : I.C[m + 1];
   const bool anchor = !tail && ((m % k_ckpt) <= 1);
   const void* ckbuf = anchor ? (const void*)((const char*)I.ckpt +
                                              ckpt_slot(m, k_ckpt) * (long long)I.R * N * sizeof(R4))
                              : nullptr;
+  const void* Asrc = anchor ? ckbuf : Ay;
   Cx<V> G[10];
 #pragma unroll
   for (int e = 0; e < 10; ++e) G[e] = Cx<V>{V(0), V(0)};
-  // software pipeline, distance PDA probes (halo records of alpha_{m+1},
-  // gamma_{m+1}, the own-site m+2 values and the probe code)
-  const void* Asrc = anchor ? ckbuf : (const void*)Ay;
-  R4 sa[PDA], sg[PDA];
-  Cx<V> aq[PDA], gq[PDA];
-  unsigned cq[PDA];
-#pragma unroll
-  for (int u = 0; u < PDA; ++u) {
-    aq[u] = Cx<V>{V(0), V(0)};
-    gq[u] = Cx<V>{V(0), V(0)};
-    cq[u] = 0u;
-    const int p = pbase + u;
-    if (p < pend) {
-      sa[u] = ldg_rec<V>(Ax, (unsigned)(p * N) + L.halo);
-      sg[u] = ldg_rec<V>(Gx, (unsigned)(p * N) + L.halo);
-      if (!tail) {
-        gq[u] = ldg_comp<V>(Gy, (unsigned)(p * N) + L.site, L.a);
-        aq[u] = ldg_comp<V>(Asrc, (unsigned)(p * N) + L.site, L.a);
-        cq[u] = ldg_code(I, (unsigned)(p * N) + L.site);
-      }
+  // (FP64: full rows only; a second loop body would push the kernel past
+  // 256 VGPRs into scratch)
+  if constexpr (sizeof(V) == 4) {
+    if (!tail && wave_sparse<V>(K, L.a)) {
+      compact_row<V>(K, L.a);
+      adj_loop<V, true>(I, L, K, S.st.r[wave], pbase, pend, tail, anchor, Cm1, Ax, Gx, Ay, Gy,
+                        Asrc, G, lane);
+    } else {
+      adj_loop<V, false>(I, L, K, S.st.r[wave], pbase, pend, tail, anchor, Cm1, Ax, Gx, Ay, Gy,
+                         Asrc, G, lane);
     }
-  }
-  for (int p0 = pbase; p0 < pend; p0 += PDA) {
-#pragma unroll
-    for (int u = 0; u < PDA; ++u) {
-      const int p = p0 + u;
-      if (p >= pend) break;
-      R4* la = S.st.r[wave][u & 1][0];
-      R4* lg = S.st.r[wave][u & 1][1];
-      if (lane < HREC) {
-        la[lane] = sa[u];
-        lg[lane] = sg[u];
-      }
-      __builtin_amdgcn_wave_barrier();
-      const unsigned rec = (unsigned)(p * N) + L.site;
-      const Cx<V> a2 = aq[u], g2 = gq[u];
-      const unsigned code = cq[u];
-      if (p + PDA < pend) {
-        sa[u] = ldg_rec<V>(Ax, (unsigned)((p + PDA) * N) + L.halo);
-        sg[u] = ldg_rec<V>(Gx, (unsigned)((p + PDA) * N) + L.halo);
-        if (!tail) {
-          gq[u] = ldg_comp<V>(Gy, rec + (unsigned)(PDA * N), L.a);
-          aq[u] = ldg_comp<V>(Asrc, rec + (unsigned)(PDA * N), L.a);
-          cq[u] = ldg_code(I, rec + (unsigned)(PDA * N));
-        }
-      }
-      // dOmega/dH~ contribution of index src: conj(gamma_(i,a)) alpha_(j,b)
-      const Cx<V> gi = comp_of<V>(lg[L.hoff[0]], L.a);
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const R4 v = la[L.hoff[1 + d]];
-        cfma_conj(G[2 * d + 0], gi, comp_of<V>(v, 0));
-        cfma_conj(G[2 * d + 1], gi, comp_of<V>(v, 1));
-      }
-      {
-        const R4 v = la[L.hoff[0]];
-        // a = 0: entries 16 (b = 0) and 18 (b = 1); a = 1: entry 17 (b = 1)
-        cfma_conj(G[8], gi, comp_of<V>(v, L.a));
-        cfma_conj(G[9], gi, comp_of<V>(v, 1));
-      }
-      if (!tail) {
-        // gamma_m row a
-        Cx<V> gn{V(0), V(0)};
-        row_apply<V>(gn, K, lg, L);
-        const Cx<V> sr = phase_times<V>(lane_code(code, L.a), (V)(I.pw[p] * Cm1));
-        gn.x = fma(V(2), gn.x, sr.x - g2.x);
-        gn.y = fma(V(2), gn.y, sr.y - g2.y);
-        // alpha_m row a: checkpoint or reversed recursion
-        Cx<V> an = a2;
-        if (!anchor) {
-          Cx<V> t{V(0), V(0)};
-          row_apply<V>(t, K, la, L);
-          an.x = fma(V(2), t.x, -a2.x);
-          an.y = fma(V(2), t.y, -a2.y);
-        }
-        if (L.valid) {
-          stg_comp<V>(Gy, rec, L.a, gn);
-          stg_comp<V>(Ay, rec, L.a, an);
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-    }
+  } else {
+    adj_loop<V, false>(I, L, K, S.st.r[wave], pbase, pend, tail, anchor, Cm1, Ax, Gx, Ay, Gy, Asrc,
+                       G, lane);
   }
   // sum the 4 waves' partials in LDS, then one read-modify-write per (site, entry)
   __syncthreads();

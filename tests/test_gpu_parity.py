@@ -109,6 +109,53 @@ def test_energy_grad_fp64(M, k, P):
     assert p.status() == 0
 
 
+def _stencil_run(cfg, st, P=0):
+    """Energy, moments and gradient of an arbitrary stencil on the GPU and in the
+    oracle (each side computes its own bounds and coefficients)."""
+    from paper_2212_05685_amd import kpm
+    kpm.kpm_set_probe_block(P)
+    p = problem(cfg)
+    h = dev(st)
+    ab = p.bounds(h)
+    C = p.coefficients(ab)
+    omega, mu = p.grand_potential(h, ab, C, want_mu=True)
+    rho = host(p.grand_potential_grad(h, ab, C))
+    a, b = H.bounds(cfg, st)
+    ref = H.plain(cfg, st, a, b, H.coefficients(cfg, a, b))
+    assert abs(host(omega)[0] - ref["omega"]) < TOL * abs(ref["omega"])
+    assert np.max(np.abs(host(mu) - ref["mu"])) < TOL * np.max(np.abs(ref["mu"]))
+    assert H.rel_err(rho, ref["rho"]) < TOL
+    assert p.status() == 0
+
+
+def _random_stencil(cfg, seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    st = scale * (rng.normal(size=(19, cfg.N)) + 1j * rng.normal(size=(19, cfg.N)))
+    st[16:18] = st[16:18].real
+    return st
+
+
+@pytest.mark.parametrize("P", [2, 8])
+def test_general_stencil_full_rows(P):
+    """Every one of the 19 stencil entries nonzero: on-site and next-nearest-
+    neighbour anomalous entries included (the full-row kernels)."""
+    cfg = _cfg(M=40, ckpt_k=6)
+    _stencil_run(cfg, _random_stencil(cfg, 11), P)
+
+
+def test_mixed_sparse_and_full_rows():
+    """The model's stencil with anomalous next-nearest-neighbour and on-site
+    entries added on a few sites only: some waves of a launch take the sparse
+    rows, the others the full rows."""
+    cfg = _cfg(M=40, ckpt_k=6)
+    st = H.stencil(cfg).copy()
+    rnd = _random_stencil(cfg, 12, 0.05)
+    for i in (0, 37, 200, cfg.N - 1):
+        for e in (9, 10, 13, 14, 18):           # nnn (i a, j b != a) and on-site (i0, i1)
+            st[e, i] = rnd[e, i]
+    _stencil_run(cfg, st)
+
+
 def test_c1_exact_trace_against_dense():
     cfg = wl.C1()
     p, h, ab, C = _run_forward(cfg)
