@@ -277,9 +277,10 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDev* __restrict__ ins
 }
 
 // ------------------------------------------------------------- addressing
-// Probe vectors are addressed as a wave-uniform base (buffer + p N records, in
-// scalar registers) plus a per-lane 32-bit byte offset, so that each load or
-// store is a single instruction with no per-lane 64-bit address arithmetic.
+// In the adjoint, probe vectors are addressed as a wave-uniform base (buffer +
+// p N records, computed in scalar registers) plus a per-lane 32-bit byte
+// offset fixed for the whole launch, so a load or store costs one 64-bit add
+// per lane instead of an index multiply-add.
 template <typename V> using C2 = V __attribute__((ext_vector_type(2)));
 
 struct Off {
