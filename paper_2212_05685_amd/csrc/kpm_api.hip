@@ -20,7 +20,7 @@ hipError_t launch_build_h(const ModelDev&, const double*, const double*, const d
 hipError_t launch_build_vjp(const ModelDev&, const double*, const double*, const double*,
                             const double*, double*, double*, double*, hipStream_t);
 hipError_t launch_bounds(int, int, const double*, double*, hipStream_t);
-hipError_t launch_rescale(const InstDev*, const int2*, int, bool, hipStream_t);
+hipError_t launch_rescale(const InstDev*, const int4*, int, bool, hipStream_t);
 hipError_t launch_coeffs(int, int, double, const double*, double*, hipStream_t);
 hipError_t launch_cheb(bool, int, int, const InstDev*, const int4*, int, int, int, int, int, int,
                        hipStream_t);
@@ -149,7 +149,7 @@ Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32) {
   z.nchunk = (z.N + kBlock - 1) / kBlock;
   z.ntile = ((L->Lx + kTX - 1) / kTX) * ((L->Ly + kTY - 1) / kTY);
   z.rec = fp32 ? 16 : 32;
-  z.coef = align_up((size_t)kNcoef * z.N * 2 * (fp32 ? 4 : 8));
+  z.coef = align_up((size_t)z.ntile * 9 * 64 * 4 * (fp32 ? 4 : 8));
   z.vec = align_up((size_t)R * z.N * z.rec);
   z.nslots = 2LL * ((M - 1) / k + 1);
   z.ckpt = align_up((size_t)R * z.N * z.rec * (size_t)z.nslots);
@@ -267,7 +267,7 @@ int run_forward(const Ctx& c, bool ckpt, int nsteps, hipStream_t s) {
   const int ninst = (int)c.inst.size();
   hipLaunchKernelGGL(k_set_status, dim3((ninst + 63) / 64), dim3(64), 0, s, c.d_inst, ninst, 0);
   KPM_HIP(hipGetLastError());
-  KPM_HIP(launch_rescale(c.d_inst, c.d_cmap, c.nch(), c.fp32, s));
+  KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
   KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), 0, c.M, c.k,
                       ckpt ? 1 : 0, s));
   for (int m = 0; m + 1 < nsteps; ++m)

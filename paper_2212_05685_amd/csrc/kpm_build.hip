@@ -255,43 +255,65 @@ __global__ __launch_bounds__(kBoundsBlock) void k_bounds(int Lx, int Ly, const d
   }
 }
 
-// Row-form rescaled coefficients H~ = (h - b)/a for the recursion kernels.
+// Row-form rescaled coefficients H~ = (h - b)/a for the recursion kernels,
+// laid out in the order the recursion waves read them: for tile t of an
+// instance, pair k (record k = 0 site, 1..4 forward, 5..8 backward
+// neighbours) and lane l (site l >> 1 of the 8 x 4 tile, Nambu row a = l & 1),
+// the 4-vector (re, im) of H~_{(i,a),(nb_k(i),0)} followed by (re, im) of
+// H~_{(i,a),(nb_k(i),1)} sits at [(t * 9 + k) * 64 + l].  A wave thus loads
+// its whole row block with 9 contiguous 64-lane loads.  Lanes outside the
+// lattice get zeros.  One 64-thread block per tile.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_rescale(const InstDev* __restrict__ insts,
-                                                    const int2* __restrict__ cmap) {
-  const int2 cm = cmap[blockIdx.x];
-  const InstDev& I = insts[cm.x];
-  int i = cm.y + threadIdx.x;
-  if (i >= I.N) return;
-  const int N = I.N;
-  const double2* h = I.h;
-  const double a = I.ab[0], b = I.ab[1];
-  const double ia = 1.0 / a;
-  V* out = reinterpret_cast<V*>(I.coef);
-  auto put = [&](int slot, double re, double im) {
-    out[2 * ((long long)slot * N + i) + 0] = (V)re;
-    out[2 * ((long long)slot * N + i) + 1] = (V)im;
-  };
-  double2 p = h[(long long)18 * N + i];
-  put(0, (h[(long long)16 * N + i].x - b) * ia, 0.0);
-  put(1, p.x * ia, p.y * ia);
-  put(18, p.x * ia, -p.y * ia);
-  put(19, (h[(long long)17 * N + i].x - b) * ia, 0.0);
-  for (int d = 0; d < 4; ++d) {
-    int j = nbr_of(i, d, -1, I.Lx, I.Ly);
-    for (int al = 0; al < 2; ++al) {
+__global__ __launch_bounds__(64) void k_rescale(const InstDev* __restrict__ insts,
+                                                const int4* __restrict__ tmap) {
+  using R4 = typename RecT4<V>::T;
+  const int4 tm = tmap[blockIdx.x];
+  const InstDev& I = insts[tm.x];
+  const int l = threadIdx.x, al = l & 1, s = l >> 1;
+  const int x = tm.y + (s & 7), y = tm.z + (s >> 3);
+  R4* out = reinterpret_cast<R4*>(I.coef) + (size_t)tm.w * 9 * 64 + l;
+  double c[18][2];
+#pragma unroll
+  for (int q = 0; q < 18; ++q) c[q][0] = c[q][1] = 0.0;
+  if (x < I.Lx && y < I.Ly) {
+    const int N = I.N, i = y * I.Lx + x;
+    const double2* h = I.h;
+    const double ia = 1.0 / I.ab[0], b = I.ab[1];
+    const double2 p = h[(long long)18 * N + i];
+    if (al == 0) {
+      c[0][0] = (h[(long long)16 * N + i].x - b) * ia;
+      c[1][0] = p.x * ia;
+      c[1][1] = p.y * ia;
+    } else {
+      c[0][0] = p.x * ia;
+      c[0][1] = -p.y * ia;
+      c[1][0] = (h[(long long)17 * N + i].x - b) * ia;
+    }
+    for (int d = 0; d < 4; ++d) {
+      const int j = nbr_of(i, d, -1, I.Lx, I.Ly);
       for (int be = 0; be < 2; ++be) {
-        double2 f = h[(long long)(4 * d + 2 * al + be) * N + i];
-        put(18 * al + 2 * (1 + d) + be, f.x * ia, f.y * ia);
-        double2 r = h[(long long)(4 * d + 2 * be + al) * N + j];   // H~_{(i,al),(j,be)} = conj(B_{be al}(j))/a
-        put(18 * al + 2 * (5 + d) + be, r.x * ia, -r.y * ia);
+        const double2 f = h[(long long)(4 * d + 2 * al + be) * N + i];
+        c[2 * (1 + d) + be][0] = f.x * ia;
+        c[2 * (1 + d) + be][1] = f.y * ia;
+        const double2 r = h[(long long)(4 * d + 2 * be + al) * N + j];   // conj(B_{be al}(j))/a
+        c[2 * (5 + d) + be][0] = r.x * ia;
+        c[2 * (5 + d) + be][1] = -r.y * ia;
       }
     }
   }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    R4 v;
+    v.x = (V)c[2 * k][0];
+    v.y = (V)c[2 * k][1];
+    v.z = (V)c[2 * k + 1][0];
+    v.w = (V)c[2 * k + 1][1];
+    out[k * 64] = v;
+  }
 }
 
-template __global__ void k_rescale<float>(const InstDev*, const int2*);
-template __global__ void k_rescale<double>(const InstDev*, const int2*);
+template __global__ void k_rescale<float>(const InstDev*, const int4*);
+template __global__ void k_rescale<double>(const InstDev*, const int4*);
 
 // C_m = (2 - delta_m0) g_m (1/K) sum_k cos(m th_k) f(a cos th_k + b).
 // cos(m th_k) = cospi(j/(2K)) with the exact integer j = m(2k+1) mod 4K.
@@ -368,12 +390,12 @@ hipError_t launch_bounds(int Lx, int Ly, const double* h, double* ab, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_rescale(const InstDev* insts, const int2* cmap, int nchunks, bool fp32,
+hipError_t launch_rescale(const InstDev* insts, const int4* tmap, int ntiles, bool fp32,
                           hipStream_t s) {
   if (fp32)
-    hipLaunchKernelGGL(k_rescale<float>, dim3(nchunks), dim3(kBlock), 0, s, insts, cmap);
+    hipLaunchKernelGGL(k_rescale<float>, dim3(ntiles), dim3(64), 0, s, insts, tmap);
   else
-    hipLaunchKernelGGL(k_rescale<double>, dim3(nchunks), dim3(kBlock), 0, s, insts, cmap);
+    hipLaunchKernelGGL(k_rescale<double>, dim3(ntiles), dim3(64), 0, s, insts, tmap);
   return hipGetLastError();
 }
 

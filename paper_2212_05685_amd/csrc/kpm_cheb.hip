@@ -112,13 +112,17 @@ __device__ __forceinline__ Lane lane_geometry(const InstDev& I, int X0, int Y0, 
 // Row a of the site's 18 row coefficients of H~ (slot 2k + b, k = stencil slot).
 template <typename V> struct RowCoef { Cx<V> c[18]; };
 
+// 9 contiguous 64-lane loads from the lane-ordered coefficient table (the
+// other waves of the block, on the same tile, find the lines in L1).
 template <typename V>
-__device__ __forceinline__ void load_row(RowCoef<V>& K, const InstDev& I, const Lane& L) {
-  GPtr<V> base = (GPtr<V>)(I.coef);
+__device__ __forceinline__ void load_row(RowCoef<V>& K, const InstDev& I, int tile, int lane) {
+  using R4 = typename RecT<V>::T;
+  GPtr<R4> base = (GPtr<R4>)(I.coef) + (size_t)tile * 9 * 64 + lane;
 #pragma unroll
-  for (int j = 0; j < 18; ++j) {
-    const unsigned idx = (unsigned)((18 * L.a + j) * I.N) + L.site;
-    K.c[j] = Cx<V>{base[2u * idx], base[2u * idx + 1u]};
+  for (int k = 0; k < 9; ++k) {
+    const R4 v = base[k * 64];
+    K.c[2 * k] = Cx<V>{v.x, v.y};
+    K.c[2 * k + 1] = Cx<V>{v.z, v.w};
   }
 }
 
@@ -397,7 +401,7 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   const int N = I.N;
   const Lane L = lane_geometry(I, tm.y, tm.z, lane);
   RowCoef<V> K;
-  load_row<V>(K, I, L);
+  load_row<V>(K, I, tm.w, lane);
   const void* cur = I.A[m & 1];
   void* nxt = I.A[(m + 1) & 1];
   const int mo = m + 1;
@@ -600,7 +604,7 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   const int N = I.N;
   const Lane L = lane_geometry(I, tm.y, tm.z, lane);
   RowCoef<V> K;
-  if (!tail) load_row<V>(K, I, L);
+  if (!tail) load_row<V>(K, I, tm.w, lane);
   const int src = tail ? m : m + 1;
   const void* Ax = I.A[src & 1];
   const void* Gx = I.G[src & 1];

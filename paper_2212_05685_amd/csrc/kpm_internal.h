@@ -2,9 +2,11 @@
 //
 // Data layout in HBM (per lattice instance, N = Lx*Ly sites, R probes):
 //   h      [19][N] double2   stencil of h (ABI layout)
-//   coef   [36][N] complex   rescaled rows of H~ = (h - b)/a, slot
-//                            18*a + 2*k + b' = H~_{(i,a),(nb_k(i),b')} with
-//                            nb_0 = i, nb_{1+d} = i + d, nb_{5+d} = i - d
+//   coef   [tile][9][64] 4-vectors  rescaled rows of H~ = (h - b)/a in lane
+//                            order: pair k of lane l (site l >> 1 of the tile,
+//                            row a = l & 1) holds H~_{(i,a),(nb_k(i),0)} and
+//                            H~_{(i,a),(nb_k(i),1)}, nb_0 = i, nb_{1+d} = i + d,
+//                            nb_{5+d} = i - d
 //   A[2], G[2]  [R][N] rec   alpha_j lives in A[j & 1], gamma_j in G[j & 1];
 //                            rec = two complex values (Nambu 0, 1) of one site
 //                            (float4 = 16 B in FP32, 2 x double2 = 32 B in FP64)
@@ -59,6 +61,14 @@ struct InstDev {
   double* omega;
   int* status;
 };
+
+// Four values of one precision moved as one vector (a site record of both
+// Nambu components, or a coefficient pair).
+typedef float KF4 __attribute__((ext_vector_type(4)));
+typedef double KD4 __attribute__((ext_vector_type(4)));
+template <typename V> struct RecT4;
+template <> struct RecT4<float> { using T = KF4; };
+template <> struct RecT4<double> { using T = KD4; };
 
 // ---------------------------------------------------------------- complex
 template <typename V> struct Cx { V x, y; };
