@@ -241,6 +241,14 @@ template <typename V> struct Stage {
 };
 
 
+// Probe weight w_p, read through the constant address space: p is wave-uniform,
+// so this is a scalar load, where a generic pointer would give a FLAT load that
+// the compiler answers with full memory waits.  The table is written by an
+// earlier kernel.
+__device__ __forceinline__ double probe_weight(const InstDev& I, int p) {
+  return ((const __attribute__((address_space(4))) double*)(I.pw))[p];
+}
+
 // wave index as a scalar (it is uniform across the wave)
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
@@ -408,7 +416,8 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   const bool ck = store_ckpt && ((mo % k_ckpt) <= 1);
   void* ckbuf = ck ? (void*)((char*)I.ckpt + ckpt_slot(mo, k_ckpt) * (long long)I.R * N * sizeof(R4))
                    : nullptr;
-  double* mom = I.mom + ((long long)mo * I.nchunk + tm.w) * I.R;
+  // global (not generic) pointer: a generic store would be a FLAT access
+  GPtrW<double> mom = (GPtrW<double>)(I.mom) + ((long long)mo * I.nchunk + tm.w) * I.R;
   const int pend = min(pbase + PW, I.R);
   R4 st[PD];
   Cx<V> pq[PD];
@@ -559,7 +568,7 @@ __device__ __forceinline__ void adj_loop(const InstDev& I, const Lane& L, const 
         // gamma_m row a
         Cx<V> gn{V(0), V(0)};
         row_apply<V, SP>(gn, K, lg, L);
-        const Cx<V> sr = phase_times<V>(lane_code(code, L.a), (V)(I.pw[p] * Cm1));
+        const Cx<V> sr = phase_times<V>(lane_code(code, L.a), (V)(probe_weight(I, p) * Cm1));
         gn.x = fma(V(2), gn.x, sr.x - g2.x);
         gn.y = fma(V(2), gn.y, sr.y - g2.y);
         // alpha_m row a: checkpoint or reversed recursion
