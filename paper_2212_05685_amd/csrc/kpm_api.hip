@@ -122,13 +122,30 @@ bool valid_P(int P) { return P == 1 || P == 2 || P == 4 || P == 8 || P == 16 || 
 
 constexpr int kTX = 8, kTY = 4, kWaves = kBlock / 64;   // recursion tile and waves per block
 
-// Probes per wave: the largest power of two (<= 8) that still gives every
-// SIMD of the 256 CUs about 8 waves in one launch.
-int auto_probe_block(long long tiles_total, int Rmax) {
-  const long long want = 256LL * 4 * 8;
-  int P = 1;
-  while (P < 8 && tiles_total * ((Rmax + 2 * P - 1) / (2 * P)) >= want) P *= 2;
+// Probes per wave (P), from the measured behaviour of the 100x100 workload:
+// the forward step wants many short waves (the largest P <= 8 that still gives
+// ~16 waves per SIMD of the 256 CUs in one launch), the adjoint step wants few
+// probe ranges (each range adds a read-modify-write of the FP64 partial sums and
+// a pass over the coefficient table) as long as every SIMD still gets ~2 waves,
+// and a range count that divides 8 or is a multiple of 8, so that every XCD
+// keeps to its own probe ranges (block_work).
+int waves_for(long long tiles_total, int Rmax, int P) {
+  return (int)std::min<long long>(tiles_total * ((Rmax + kWaves * P - 1) / (kWaves * P)) * kWaves,
+                                  1LL << 30);
+}
+
+int auto_probe_fwd(long long tiles_total, int Rmax) {
+  int P = 8;
+  while (P > 1 && waves_for(tiles_total, Rmax, P) < 256 * 4 * 16) P /= 2;
   return P;
+}
+
+int auto_probe_adj(long long tiles_total, int Rmax) {
+  for (int P = 32; P > 1; P /= 2) {
+    const int nr = (Rmax + kWaves * P - 1) / (kWaves * P);
+    if ((8 % nr == 0 || nr % 8 == 0) && waves_for(tiles_total, Rmax, P) >= 256 * 4 * 2) return P;
+  }
+  return 1;
 }
 
 std::mutex g_mu;
@@ -357,8 +374,8 @@ int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* 
     std::lock_guard<std::mutex> lk(g_mu);
     P = g_probe_block;
   }
-  c.Pf = P ? P : auto_probe_block(c.ntl(), c.Rmax);
-  c.Pa = P ? P : auto_probe_block(c.ntl(), c.Rmax);
+  c.Pf = P ? P : auto_probe_fwd(c.ntl(), c.Rmax);
+  c.Pa = P ? P : auto_probe_adj(c.ntl(), c.Rmax);
   set_npb(c);
   return KPM_OK;
 }
@@ -407,7 +424,7 @@ int autotune(KpmBatchPlan* pl, hipStream_t s) {
   const int steps = std::min(c.M, 8);
   float best_f = 1e30f, best_a = 1e30f;
   int Pf = 1, Pa = 1;
-  for (int P : {1, 2, 4, 8, 16}) {
+  for (int P : {1, 2, 4, 8, 16, 32}) {
     c.Pf = P;
     c.Pa = P;
     set_npb(c);
@@ -670,8 +687,8 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
     std::lock_guard<std::mutex> lk(g_mu);
     P = g_probe_block;
   }
-  pl->c.Pf = P ? P : auto_probe_block(pl->c.ntl(), pl->c.Rmax);
-  pl->c.Pa = P ? P : auto_probe_block(pl->c.ntl(), pl->c.Rmax);
+  pl->c.Pf = P ? P : auto_probe_fwd(pl->c.ntl(), pl->c.Rmax);
+  pl->c.Pa = P ? P : auto_probe_adj(pl->c.ntl(), pl->c.Rmax);
   pl->tuned = P != 0;
   set_npb(pl->c);
   *plan = pl;

@@ -16,9 +16,11 @@
 //  * The 4 waves of a block share the tile and take different probe subgroups
 //    (PW probes each), so the adjoint's dOmega/dH~ contributions of 4 PW probes
 //    are summed in LDS and written once per (site, probe range) per step.
-//  * Blocks are numbered tile-major with the probe range fastest, so with 8
-//    probe ranges each XCD (blocks dispatched round-robin over the 8 XCDs)
-//    sweeps one probe range over all tiles and the halo rows stay in its L2.
+//  * Blocks are dispatched round-robin over the 8 XCDs.  When the number of
+//    probe ranges divides 8, XCD x takes one probe range on one contiguous
+//    strip of tiles (block_work), so the halo rows it shares stay in its L2
+//    and each tile's coefficients and partial sums are touched by as many
+//    XCDs as there are ranges.
 #include <hip/hip_ext.h>
 
 #include <mutex>
@@ -249,6 +251,26 @@ __device__ __forceinline__ double probe_weight(const InstDev& I, int p) {
   return ((const __attribute__((address_space(4))) double*)(I.pw))[p];
 }
 
+// Block -> (tile, probe range).  When the number of probe ranges divides 8,
+// XCD x = blockIdx % 8 (blocks go to the 8 XCDs round-robin) takes range
+// x % nranges on the (x / nranges)-th contiguous strip of `chunk` tiles: each
+// XCD sweeps a spatially coherent part of the lattice with one probe range,
+// so the halo rows it shares stay in its L2, and a tile's coefficients and
+// partial sums are touched by nranges XCDs only.  Otherwise tile-major.
+struct Sched { int nranges, chunk, ntiles; };
+__device__ __forceinline__ bool block_work(const Sched& sc, int& tile, int& range) {
+  const int b = blockIdx.x;
+  if (sc.chunk > 0) {
+    const int x = b & 7;
+    range = x % sc.nranges;
+    tile = (x / sc.nranges) * sc.chunk + (b >> 3);
+    return tile < sc.ntiles;
+  }
+  tile = b / sc.nranges;
+  range = b % sc.nranges;
+  return true;
+}
+
 // wave index as a scalar (it is uniform across the wave)
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
@@ -257,10 +279,11 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // table pcode, the weight table pw and the mu_0 partials per tile.
 template <typename V, int PW>
 __global__ __launch_bounds__(kBlock) void k_init(const InstDev* __restrict__ insts,
-                                                 const int4* __restrict__ tmap, int nranges,
+                                                 const int4* __restrict__ tmap, Sched sc,
                                                  int k_ckpt, int store_ckpt) {
-  const int4 tm = tmap[blockIdx.x / nranges];
-  const int range = blockIdx.x % nranges;
+  int tile, range;
+  if (!block_work(sc, tile, range)) return;               // block-uniform
+  const int4 tm = tmap[tile];
   const InstDev& I = insts[tm.x];
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
@@ -396,12 +419,13 @@ constexpr int PDA = 1;
 // m == 0: alpha_1 = H~ alpha_0.  Moment partial of alpha_{m+1} per (probe, tile).
 template <typename V, int PW>
 __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
-                                         const int4* __restrict__ tmap, int nranges, int m,
+                                         const int4* __restrict__ tmap, Sched sc, int m,
                                          int k_ckpt, int store_ckpt) {
   using R4 = typename RecT<V>::T;
   __shared__ Stage<V> S;
-  const int4 tm = tmap[blockIdx.x / nranges];
-  const int range = blockIdx.x % nranges;
+  int tile, range;
+  if (!block_work(sc, tile, range)) return;               // block-uniform
+  const int4 tm = tmap[tile];
   const InstDev& I = insts[tm.x];
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
@@ -471,10 +495,11 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
 // gamma_{M-1} = 0, gamma_{M-2} = w C_{M-1} r; clears the dOmega/dH~ partials.
 template <typename V, int PW>
 __global__ __launch_bounds__(kBlock) void k_adj_init(const InstDev* __restrict__ insts,
-                                                     const int4* __restrict__ tmap, int nranges,
+                                                     const int4* __restrict__ tmap, Sched sc,
                                                      int M) {
-  const int4 tm = tmap[blockIdx.x / nranges];
-  const int range = blockIdx.x % nranges;
+  int tile, range;
+  if (!block_work(sc, tile, range)) return;               // block-uniform
+  const int4 tm = tmap[tile];
   const InstDev& I = insts[tm.x];
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
@@ -596,15 +621,16 @@ __device__ __forceinline__ void adj_loop(const InstDev& I, const Lane& L, const 
 // b < 2) and the onsite ones (a = 0: 16, 18; a = 1: 17).
 template <typename V, int PW>
 __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
-                                         const int4* __restrict__ tmap, int nranges, int m,
+                                         const int4* __restrict__ tmap, Sched sc, int m,
                                          int k_ckpt, int tail) {
   using R4 = typename RecT<V>::T;
   __shared__ union {
     Stage<V> st;
     Cx<V> red[WAVES][kNent][TX * TY];     // per-wave partial sums, precision of V
   } S;
-  const int4 tm = tmap[blockIdx.x / nranges];
-  const int range = blockIdx.x % nranges;
+  int tile, range;
+  if (!block_work(sc, tile, range)) return;               // block-uniform
+  const int4 tm = tmap[tile];
   const InstDev& I = insts[tm.x];
   if (range * WAVES * PW >= I.R) return;                 // block-uniform
   const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -684,26 +710,26 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
 template <typename V, int PW> struct StepKernels;
 template <int PW> struct StepKernels<float, PW> {
   static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
-  void fwd(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, int nranges, int m,
+  void fwd(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
            int k_ckpt, int store_ckpt) {
-    fwd_body<float, PW>(insts, tmap, nranges, m, k_ckpt, store_ckpt);
+    fwd_body<float, PW>(insts, tmap, sc, m, k_ckpt, store_ckpt);
   }
   static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
-  void adj(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, int nranges, int m,
+  void adj(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
            int k_ckpt, int tail) {
-    adj_body<float, PW>(insts, tmap, nranges, m, k_ckpt, tail);
+    adj_body<float, PW>(insts, tmap, sc, m, k_ckpt, tail);
   }
 };
 template <int PW> struct StepKernels<double, PW> {
   static __global__ __launch_bounds__(kBlock)
-  void fwd(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, int nranges, int m,
+  void fwd(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
            int k_ckpt, int store_ckpt) {
-    fwd_body<double, PW>(insts, tmap, nranges, m, k_ckpt, store_ckpt);
+    fwd_body<double, PW>(insts, tmap, sc, m, k_ckpt, store_ckpt);
   }
   static __global__ __launch_bounds__(kBlock)
-  void adj(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, int nranges, int m,
+  void adj(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
            int k_ckpt, int tail) {
-    adj_body<double, PW>(insts, tmap, nranges, m, k_ckpt, tail);
+    adj_body<double, PW>(insts, tmap, sc, m, k_ckpt, tail);
   }
 };
 
@@ -882,29 +908,35 @@ hipError_t profile_end(double* fwd_ms, int* nfwd, double* adj_ms, int* nadj) {
 template <typename V, int PW>
 static hipError_t launch_all(int which, const InstDev* insts, const int4* tmap, int ntiles,
                              int nranges, int m, int M, int k_ckpt, int flag, hipStream_t s) {
-  dim3 grid(ntiles * nranges), block(kBlock);
+  Sched sc{nranges, 0, ntiles};
+  int nblocks = ntiles * nranges;
+  if (8 % nranges == 0) {
+    sc.chunk = (ntiles + 8 / nranges - 1) / (8 / nranges);
+    nblocks = 8 * sc.chunk;
+  }
+  dim3 grid(nblocks), block(kBlock);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = (which == 1 || (which == 3 && flag == 0)) && prof::next(which, e0, e1);
   switch (which) {
     case 0:
-      hipLaunchKernelGGL((k_init<V, PW>), grid, block, 0, s, insts, tmap, nranges, k_ckpt, flag);
+      hipLaunchKernelGGL((k_init<V, PW>), grid, block, 0, s, insts, tmap, sc, k_ckpt, flag);
       break;
     case 1:
       if (timed)
-        hipExtLaunchKernelGGL((StepKernels<V, PW>::fwd), grid, block, 0, s, e0, e1, 0, insts, tmap, nranges, m,
+        hipExtLaunchKernelGGL((StepKernels<V, PW>::fwd), grid, block, 0, s, e0, e1, 0, insts, tmap, sc, m,
                               k_ckpt, flag);
       else
-        hipLaunchKernelGGL((StepKernels<V, PW>::fwd), grid, block, 0, s, insts, tmap, nranges, m, k_ckpt, flag);
+        hipLaunchKernelGGL((StepKernels<V, PW>::fwd), grid, block, 0, s, insts, tmap, sc, m, k_ckpt, flag);
       break;
     case 2:
-      hipLaunchKernelGGL((k_adj_init<V, PW>), grid, block, 0, s, insts, tmap, nranges, M);
+      hipLaunchKernelGGL((k_adj_init<V, PW>), grid, block, 0, s, insts, tmap, sc, M);
       break;
     case 3:
       if (timed)
-        hipExtLaunchKernelGGL((StepKernels<V, PW>::adj), grid, block, 0, s, e0, e1, 0, insts, tmap, nranges, m,
+        hipExtLaunchKernelGGL((StepKernels<V, PW>::adj), grid, block, 0, s, e0, e1, 0, insts, tmap, sc, m,
                               k_ckpt, flag);
       else
-        hipLaunchKernelGGL((StepKernels<V, PW>::adj), grid, block, 0, s, insts, tmap, nranges, m, k_ckpt, flag);
+        hipLaunchKernelGGL((StepKernels<V, PW>::adj), grid, block, 0, s, insts, tmap, sc, m, k_ckpt, flag);
       break;
     default:
       return hipErrorInvalidValue;
