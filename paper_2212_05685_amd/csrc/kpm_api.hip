@@ -124,7 +124,7 @@ constexpr int kTX = 8, kTY = 4, kWaves = kBlock / 64;   // recursion tile and wa
 
 // Probes per wave (P), from the measured behaviour of the 100x100 workload:
 // the forward step wants many short waves (the largest P <= 8 that still gives
-// ~16 waves per SIMD of the 256 CUs in one launch), the adjoint step wants few
+// ~8 waves per SIMD of the 256 CUs in one launch), the adjoint step wants few
 // probe ranges (each range adds a read-modify-write of the FP64 partial sums and
 // a pass over the coefficient table) as long as every SIMD still gets ~2 waves,
 // and a range count that divides 8 or is a multiple of 8, so that every XCD
@@ -136,7 +136,7 @@ int waves_for(long long tiles_total, int Rmax, int P) {
 
 int auto_probe_fwd(long long tiles_total, int Rmax) {
   int P = 8;
-  while (P > 1 && waves_for(tiles_total, Rmax, P) < 256 * 4 * 16) P /= 2;
+  while (P > 1 && waves_for(tiles_total, Rmax, P) < 256 * 4 * 8) P /= 2;
   return P;
 }
 
@@ -154,7 +154,7 @@ int g_probe_block = 0;   // 0 = automatic
 // ------------------------------------------------------------ instance layout
 struct Sizes {
   int N, R, M, nchunk, ntile;
-  size_t rec, coef, vec, ckpt, mom, musum, gpart, pcode, pw;
+  size_t rec, coef, vec, ckpt, mom, musum, gpart, pcode, pw, sink;
   long long nslots;
 };
 
@@ -175,12 +175,13 @@ Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32) {
   z.gpart = align_up(sizeof(double) * 2 * kNent * (size_t)z.N * R);   // sized for P = 1
   z.pcode = align_up((size_t)R * z.N);
   z.pw = align_up(sizeof(double) * (size_t)R);
+  z.sink = align_up(4096);
   return z;
 }
 
 size_t inst_bytes(const Sizes& z) {
   return align_up(sizeof(int)) + z.coef + 4 * z.vec + z.ckpt + z.mom + z.musum + z.gpart +
-         align_up(sizeof(double) * ((z.M + kBlock - 1) / kBlock)) + z.pcode + z.pw;
+         align_up(sizeof(double) * ((z.M + kBlock - 1) / kBlock)) + z.pcode + z.pw + z.sink;
 }
 
 // Carve one instance's buffers out of `base` (which must hold inst_bytes).
@@ -199,6 +200,8 @@ void carve(InstDev& I, const Sizes& z, char* base) {
   I.opart = reinterpret_cast<double*>(o);  o += align_up(sizeof(double) * ((z.M + kBlock - 1) / kBlock));
   I.pcode = reinterpret_cast<unsigned char*>(o); o += z.pcode;
   I.pw = reinterpret_cast<double*>(o);
+  o += z.pw;
+  I.sink = o;
 }
 
 // ------------------------------------------------------------ run context

@@ -409,18 +409,17 @@ __device__ __forceinline__ void row_apply(Cx<V>& acc, const RowCoef<V>& K,
 }
 
 // ------------------------------------------------------------- forward step
-// Loads of a probe are issued PD (forward) / PDA (adjoint) probes ahead of
-// its use: a ring of staged halo records, own-site values and code bytes held
-// in registers.
-constexpr int PD = 2;
-constexpr int PDA = 1;
+// The forward step keeps the loads of FPD probes in flight: a register ring of
+// staged halo records, own-site values and code bytes.
+constexpr int FPD = 2;
 
 // alpha_{m+1} into A[(m+1)&1] (holding alpha_{m-1}) from alpha_m in A[m&1];
 // m == 0: alpha_1 = H~ alpha_0.  Moment partial of alpha_{m+1} per (probe, tile).
-template <typename V, int PW>
+// CK: this step's alpha_{m+1} is also a checkpoint.
+template <typename V, int PW, bool CK>
 __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
                                          const int4* __restrict__ tmap, Sched sc, int m,
-                                         int k_ckpt, int store_ckpt) {
+                                         int k_ckpt) {
   using R4 = typename RecT<V>::T;
   __shared__ Stage<V> S;
   int tile, range;
@@ -437,58 +436,58 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   const void* cur = I.A[m & 1];
   void* nxt = I.A[(m + 1) & 1];
   const int mo = m + 1;
-  const bool ck = store_ckpt && ((mo % k_ckpt) <= 1);
-  void* ckbuf = ck ? (void*)((char*)I.ckpt + ckpt_slot(mo, k_ckpt) * (long long)I.R * N * sizeof(R4))
+  void* ckbuf = CK ? (void*)((char*)I.ckpt + ckpt_slot(mo, k_ckpt) * (long long)I.R * N * sizeof(R4))
                    : nullptr;
   // global (not generic) pointer: a generic store would be a FLAT access
   GPtrW<double> mom = (GPtrW<double>)(I.mom) + ((long long)mo * I.nchunk + tm.w) * I.R;
   const int pend = min(pbase + PW, I.R);
-  R4 st[PD];
-  Cx<V> pq[PD];
-  unsigned cq[PD];
+  // Every load and store of the probe loop is issued unconditionally (loads
+  // past the wave's last probe re-read that probe; lanes outside the lattice
+  // store to the sink), so the compiler's memory-wait counts are exact and a
+  // wave waits for the loads it needs, not for its earlier stores.
+  double momv = 0.0;                     // moment of probe pbase + lane, stored after the loop
+  // Ring of FPD probes in flight.  A slot is refilled only after its values
+  // have been consumed, so each load lands in the register it is read from
+  // later (no copies, which would force an early wait for the load).
+  R4 st[FPD];
+  Cx<V> pq[FPD];
+  unsigned cq[FPD];
 #pragma unroll
-  for (int u = 0; u < PD; ++u) {
-    pq[u] = Cx<V>{V(0), V(0)};
-    cq[u] = 0u;
-    const int p = pbase + u;
-    if (p < pend) {
-      st[u] = ldg_rec<V>(cur, (unsigned)(p * N) + L.halo);
-      if (m > 0) pq[u] = ldg_comp<V>(nxt, (unsigned)(p * N) + L.site, L.a);
-      cq[u] = ldg_code(I, (unsigned)(p * N) + L.site);
-    }
+  for (int u = 0; u < FPD; ++u) {
+    const int p = min(pbase + u, pend - 1);
+    st[u] = ldg_rec<V>(cur, (unsigned)(p * N) + L.halo);
+    pq[u] = ldg_comp<V>(nxt, (unsigned)(p * N) + L.site, L.a);
+    cq[u] = ldg_code(I, (unsigned)(p * N) + L.site);
   }
-  for (int p0 = pbase; p0 < pend; p0 += PD) {
+  // Straight-line steps (a step past the wave's last probe recomputes the
+  // last probe and stores to the sink), so that the wait counts are static.
+  for (int p0 = pbase; p0 < pend; p0 += FPD) {
 #pragma unroll
-    for (int u = 0; u < PD; ++u) {
+    for (int u = 0; u < FPD; ++u) {
       const int p = p0 + u;
-      if (p >= pend) break;
+      const bool live = L.valid && p < pend;
       R4* lds = S.r[wave][u & 1][0];
       if (lane < HREC) lds[lane] = st[u];
       __builtin_amdgcn_wave_barrier();
-      const unsigned rec = (unsigned)(p * N) + L.site;
-      const Cx<V> prev = pq[u];
-      const unsigned code = cq[u];
-      if (p + PD < pend) {
-        st[u] = ldg_rec<V>(cur, (unsigned)((p + PD) * N) + L.halo);
-        if (m > 0) pq[u] = ldg_comp<V>(nxt, rec + (unsigned)(PD * N), L.a);
-        cq[u] = ldg_code(I, rec + (unsigned)(PD * N));
-      }
+      const int pn = min(p + FPD, pend - 1);
+      st[u] = ldg_rec<V>(cur, (unsigned)(pn * N) + L.halo);
       Cx<V> o{V(0), V(0)};
       row_apply<V, false>(o, K, lds, L);
-      if (m > 0) {
-        o.x = fma(V(2), o.x, -prev.x);
-        o.y = fma(V(2), o.y, -prev.y);
-      }
-      if (L.valid) {
-        stg_comp<V>(nxt, rec, L.a, o);
-        if (ck) stg_comp<V>(ckbuf, rec, L.a, o);
-      }
-      const int k = L.valid ? lane_code(code, L.a) : -1;
+      // m == 0: alpha_1 = H~ alpha_0 (prev is not read then: it may be any bits)
+      const Cx<V> o2{fma(V(2), o.x, -pq[u].x), fma(V(2), o.y, -pq[u].y)};
+      if (m > 0) o = o2;
+      const int k = live ? lane_code(cq[u], L.a) : -1;
+      pq[u] = ldg_comp<V>(nxt, (unsigned)(pn * N) + L.site, L.a);
+      cq[u] = ldg_code(I, (unsigned)(pn * N) + L.site);
+      const unsigned sidx = live ? (unsigned)(p * N) + L.site : (unsigned)L.s;
+      stg_comp<V>(live ? nxt : I.sink, sidx, L.a, o);
+      if (CK) stg_comp<V>(live ? ckbuf : I.sink, sidx, L.a, o);
       const double v = wave_moment(re_conj_phase<V>(k, o), k >= 0);
-      if (lane == 0) mom[p] = v;
+      if (lane == p - pbase) momv = v;
       __builtin_amdgcn_wave_barrier();
     }
   }
+  if (lane < pend - pbase) mom[pbase + lane] = momv;
 }
 
 // ------------------------------------------------------------- adjoint
@@ -523,106 +522,99 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(const InstDev* __restrict__
   }
 }
 
-// One wave's probes of adjoint step m (see adj_body).
-template <typename V, bool SP>
+// Address of a store that every lane issues: its own element, or the sink for
+// lanes outside the lattice.  The empty asm hides the choice from the
+// compiler, which would otherwise split the store into two conditional ones.
+__device__ __forceinline__ const char* store_addr(bool valid, const char* own, const char* sink) {
+  const char* a = valid ? own : sink;
+  asm volatile("" : "+v"(a));
+  return a;
+}
+
+// One wave's probes of adjoint step m (see adj_body).  One probe is in
+// flight: the halo records of the next probe are loaded right after this
+// probe's are staged, its own-site values right after this probe's have been
+// used, so every load lands in the register it is read from.  Every load and
+// store is issued (clamped probe index; lanes outside the lattice store to the
+// sink), so the wait counts are static and a wave waits for the loads it
+// needs, not for its earlier stores.
+template <typename V, bool SP, bool TAIL>
 __device__ __forceinline__ void adj_loop(const InstDev& I, const Lane& L, const RowCoef<V>& K,
                                          typename RecT<V>::T (*stage)[2][HREC], int pbase,
-                                         int pend, int tail, bool anchor, double Cm1,
-                                         const void* Ax, const void* Gx, const void* Ay,
-                                         const void* Gy, const void* Asrc, Cx<V> (&G)[10],
-                                         int lane) {
+                                         int pend, bool anchor, double Cm1, const void* Ax,
+                                         const void* Gx, const void* Ay, const void* Gy,
+                                         const void* Asrc, Cx<V> (&G)[10], int lane) {
   using R4 = typename RecT<V>::T;
   const int N = I.N;
   const Off O = lane_offsets<V>(L);
-  // software pipeline, distance PDA probes (halo records of alpha_{m+1},
-  // gamma_{m+1}, the own-site m+2 values and the probe code)
-  R4 sa[PDA], sg[PDA];
-  Cx<V> aq[PDA], gq[PDA];
-  unsigned cq[PDA];
-#pragma unroll
-  for (int u = 0; u < PDA; ++u) {
-    aq[u] = Cx<V>{V(0), V(0)};
-    gq[u] = Cx<V>{V(0), V(0)};
-    cq[u] = 0u;
-    const int p = pbase + u;
-    if (p < pend) {
-      sa[u] = ld_rec<V>(probe_base<V>(Ax, p, N), O.halo);
-      sg[u] = ld_rec<V>(probe_base<V>(Gx, p, N), O.halo);
-      if (!tail) {
-        gq[u] = ld_cx<V>(probe_base<V>(Gy, p, N), O.own);
-        aq[u] = ld_cx<V>(probe_base<V>(Asrc, p, N), O.own);
-        cq[u] = ld_code(I, p, L);
-      }
-    }
+  const unsigned sown = (unsigned)lane * (unsigned)sizeof(Cx<V>);
+  const char* sink = (const char*)I.sink;
+  R4 sa = ld_rec<V>(probe_base<V>(Ax, pbase, N), O.halo);
+  R4 sg = ld_rec<V>(probe_base<V>(Gx, pbase, N), O.halo);
+  Cx<V> aq{V(0), V(0)}, gq{V(0), V(0)};
+  unsigned cq = 0u;
+  if (!TAIL) {
+    gq = ld_cx<V>(probe_base<V>(Gy, pbase, N), O.own);
+    aq = ld_cx<V>(probe_base<V>(Asrc, pbase, N), O.own);
+    cq = ld_code(I, pbase, L);
   }
-  for (int p0 = pbase; p0 < pend; p0 += PDA) {
-#pragma unroll
-    for (int u = 0; u < PDA; ++u) {
-      const int p = p0 + u;
-      if (p >= pend) break;
-      R4* la = stage[u & 1][0];
-      R4* lg = stage[u & 1][1];
-      if (lane < HREC) {
-        la[lane] = sa[u];
-        lg[lane] = sg[u];
-      }
-      __builtin_amdgcn_wave_barrier();
-      const Cx<V> a2 = aq[u], g2 = gq[u];
-      const unsigned code = cq[u];
-      if (p + PDA < pend) {
-        sa[u] = ld_rec<V>(probe_base<V>(Ax, p + PDA, N), O.halo);
-        sg[u] = ld_rec<V>(probe_base<V>(Gx, p + PDA, N), O.halo);
-        if (!tail) {
-          gq[u] = ld_cx<V>(probe_base<V>(Gy, p + PDA, N), O.own);
-          aq[u] = ld_cx<V>(probe_base<V>(Asrc, p + PDA, N), O.own);
-          cq[u] = ld_code(I, p + PDA, L);
-        }
-      }
-      // dOmega/dH~ contribution of index src: conj(gamma_(i,a)) alpha_(j,b)
-      const Cx<V> gi = lds_own<V>(lg + L.hoff[0], L.a);
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const R4 v = la[L.hoff[1 + d]];
-        cfma_conj(G[2 * d + 0], gi, comp_of<V>(v, 0));
-        cfma_conj(G[2 * d + 1], gi, comp_of<V>(v, 1));
-      }
-      // a = 0: entries 16 (b = 0) and 18 (b = 1); a = 1: entry 17 (b = 1)
-      cfma_conj(G[8], gi, lds_own<V>(la + L.hoff[0], L.a));
-      cfma_conj(G[9], gi, lds_own<V>(la + L.hoff[0], 1));
-      if (!tail) {
-        // gamma_m row a
-        Cx<V> gn{V(0), V(0)};
-        row_apply<V, SP>(gn, K, lg, L);
-        const Cx<V> sr = phase_times<V>(lane_code(code, L.a), (V)(probe_weight(I, p) * Cm1));
-        gn.x = fma(V(2), gn.x, sr.x - g2.x);
-        gn.y = fma(V(2), gn.y, sr.y - g2.y);
-        // alpha_m row a: checkpoint or reversed recursion
-        Cx<V> an = a2;
-        if (!anchor) {
-          Cx<V> t{V(0), V(0)};
-          row_apply<V, SP>(t, K, la, L);
-          an.x = fma(V(2), t.x, -a2.x);
-          an.y = fma(V(2), t.y, -a2.y);
-        }
-        if (L.valid) {
-          st_cx<V>(probe_base<V>(Gy, p, N), O.own, gn);
-          st_cx<V>(probe_base<V>(Ay, p, N), O.own, an);
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
+  int buf = 0;
+  for (int p = pbase; p < pend; ++p, buf ^= 1) {
+    const int pn = min(p + 1, pend - 1);
+    R4* la = stage[buf][0];
+    R4* lg = stage[buf][1];
+    if (lane < HREC) {
+      la[lane] = sa;
+      lg[lane] = sg;
     }
+    __builtin_amdgcn_wave_barrier();
+    sa = ld_rec<V>(probe_base<V>(Ax, pn, N), O.halo);
+    sg = ld_rec<V>(probe_base<V>(Gx, pn, N), O.halo);
+    // dOmega/dH~ contribution of index src: conj(gamma_(i,a)) alpha_(j,b)
+    const Cx<V> gi = lds_own<V>(lg + L.hoff[0], L.a);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const R4 v = la[L.hoff[1 + d]];
+      cfma_conj(G[2 * d + 0], gi, comp_of<V>(v, 0));
+      cfma_conj(G[2 * d + 1], gi, comp_of<V>(v, 1));
+    }
+    // a = 0: entries 16 (b = 0) and 18 (b = 1); a = 1: entry 17 (b = 1)
+    cfma_conj(G[8], gi, lds_own<V>(la + L.hoff[0], L.a));
+    cfma_conj(G[9], gi, lds_own<V>(la + L.hoff[0], 1));
+    if (!TAIL) {
+      // gamma_m row a
+      Cx<V> gn{V(0), V(0)};
+      row_apply<V, SP>(gn, K, lg, L);
+      const Cx<V> sr = phase_times<V>(lane_code(cq, L.a), (V)(probe_weight(I, p) * Cm1));
+      gn.x = fma(V(2), gn.x, sr.x - gq.x);
+      gn.y = fma(V(2), gn.y, sr.y - gq.y);
+      // alpha_m row a: checkpoint or reversed recursion
+      Cx<V> an = aq;
+      if (!anchor) {
+        Cx<V> t{V(0), V(0)};
+        row_apply<V, SP>(t, K, la, L);
+        an.x = fma(V(2), t.x, -aq.x);
+        an.y = fma(V(2), t.y, -aq.y);
+      }
+      gq = ld_cx<V>(probe_base<V>(Gy, pn, N), O.own);
+      aq = ld_cx<V>(probe_base<V>(Asrc, pn, N), O.own);
+      cq = ld_code(I, pn, L);
+      st_cx<V>(store_addr(L.valid, probe_base<V>(Gy, p, N) + O.own, sink + sown), 0u, gn);
+      st_cx<V>(store_addr(L.valid, probe_base<V>(Ay, p, N) + O.own, sink + sown + 2048u), 0u, an);
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
 // Step m (0 <= m <= M-3): alpha_m, gamma_m from the m+1, m+2 vectors (the m+2
 // buffers are overwritten), plus 2 conj(gamma_{m+1}) x alpha_{m+1} into the
-// partial dOmega/dH~.  tail != 0: only conj(gamma_0) x alpha_0 (weight 1).
+// partial dOmega/dH~.  TAIL: only conj(gamma_0) x alpha_0 (weight 1).
 // Lane (site, row a) accumulates the entries of row a: 4d + 2a + b (d < 4,
 // b < 2) and the onsite ones (a = 0: 16, 18; a = 1: 17).
-template <typename V, int PW>
+template <typename V, int PW, bool TAIL>
 __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
                                          const int4* __restrict__ tmap, Sched sc, int m,
-                                         int k_ckpt, int tail) {
+                                         int k_ckpt) {
   using R4 = typename RecT<V>::T;
   __shared__ union {
     Stage<V> st;
@@ -639,14 +631,14 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   const int N = I.N;
   const Lane L = lane_geometry(I, tm.y, tm.z, lane);
   RowCoef<V> K;
-  if (!tail) load_row<V>(K, I, tm.w, lane);
-  const int src = tail ? m : m + 1;
+  if (!TAIL) load_row<V>(K, I, tm.w, lane);
+  const int src = TAIL ? m : m + 1;
   const void* Ax = I.A[src & 1];
   const void* Gx = I.G[src & 1];
   const void* Ay = I.A[m & 1];
   const void* Gy = I.G[m & 1];
-  const double Cm1 = tail ? 0.0 : I.C[m + 1];
-  const bool anchor = !tail && ((m % k_ckpt) <= 1);
+  const double Cm1 = TAIL ? 0.0 : I.C[m + 1];
+  const bool anchor = !TAIL && ((m % k_ckpt) <= 1);
   const void* ckbuf = anchor ? (const void*)((const char*)I.ckpt +
                                              ckpt_slot(m, k_ckpt) * (long long)I.R * N * sizeof(R4))
                              : nullptr;
@@ -657,17 +649,17 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   // (FP64: full rows only; a second loop body would push the kernel past
   // 256 VGPRs into scratch)
   if constexpr (sizeof(V) == 4) {
-    if (!tail && wave_sparse<V>(K, L.a)) {
+    if (!TAIL && wave_sparse<V>(K, L.a)) {
       compact_row<V>(K, L.a);
-      adj_loop<V, true>(I, L, K, S.st.r[wave], pbase, pend, tail, anchor, Cm1, Ax, Gx, Ay, Gy,
-                        Asrc, G, lane);
+      adj_loop<V, true, TAIL>(I, L, K, S.st.r[wave], pbase, pend, anchor, Cm1, Ax, Gx, Ay, Gy,
+                              Asrc, G, lane);
     } else {
-      adj_loop<V, false>(I, L, K, S.st.r[wave], pbase, pend, tail, anchor, Cm1, Ax, Gx, Ay, Gy,
-                         Asrc, G, lane);
+      adj_loop<V, false, TAIL>(I, L, K, S.st.r[wave], pbase, pend, anchor, Cm1, Ax, Gx, Ay, Gy,
+                               Asrc, G, lane);
     }
   } else {
-    adj_loop<V, false>(I, L, K, S.st.r[wave], pbase, pend, tail, anchor, Cm1, Ax, Gx, Ay, Gy, Asrc,
-                       G, lane);
+    adj_loop<V, false, TAIL>(I, L, K, S.st.r[wave], pbase, pend, anchor, Cm1, Ax, Gx, Ay, Gy,
+                             Asrc, G, lane);
   }
   // sum the 4 waves' partials in LDS, then one read-modify-write per (site, entry)
   __syncthreads();
@@ -684,7 +676,7 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
     S.red[wave][17][s] = G[8];
   }
   __syncthreads();
-  const double wgt = tail ? 1.0 : 2.0;
+  const double wgt = TAIL ? 1.0 : 2.0;
   double2* gp = I.gpart + (long long)range * kNent * N;
   for (int q = threadIdx.x; q < kNent * TX * TY; q += kBlock) {
     const int e = q / (TX * TY), ss = q % (TX * TY);
@@ -704,32 +696,36 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   }
 }
 
-// Kernel entry points.  The FP32 kernels are held to 5 (forward) and 3
-// (adjoint) waves per SIMD, i.e. at most 96 and 168 VGPRs: the recursion is
-// latency-bound and those occupancies keep enough loads in flight.
+// Kernel entry points.  The FP32 kernels are held to 4 (forward) and 3
+// (adjoint) waves per SIMD, i.e. at most 128 and 168 VGPRs, which leaves the
+// register rings of loads in flight without spills.
 template <typename V, int PW> struct StepKernels;
 template <int PW> struct StepKernels<float, PW> {
-  static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
+  template <bool CK>
+  static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
   void fwd(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
-           int k_ckpt, int store_ckpt) {
-    fwd_body<float, PW>(insts, tmap, sc, m, k_ckpt, store_ckpt);
+           int k_ckpt) {
+    fwd_body<float, PW, CK>(insts, tmap, sc, m, k_ckpt);
   }
+  template <bool TAIL>
   static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
   void adj(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
-           int k_ckpt, int tail) {
-    adj_body<float, PW>(insts, tmap, sc, m, k_ckpt, tail);
+           int k_ckpt) {
+    adj_body<float, PW, TAIL>(insts, tmap, sc, m, k_ckpt);
   }
 };
 template <int PW> struct StepKernels<double, PW> {
+  template <bool CK>
   static __global__ __launch_bounds__(kBlock)
   void fwd(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
-           int k_ckpt, int store_ckpt) {
-    fwd_body<double, PW>(insts, tmap, sc, m, k_ckpt, store_ckpt);
+           int k_ckpt) {
+    fwd_body<double, PW, CK>(insts, tmap, sc, m, k_ckpt);
   }
+  template <bool TAIL>
   static __global__ __launch_bounds__(kBlock)
   void adj(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
-           int k_ckpt, int tail) {
-    adj_body<double, PW>(insts, tmap, sc, m, k_ckpt, tail);
+           int k_ckpt) {
+    adj_body<double, PW, TAIL>(insts, tmap, sc, m, k_ckpt);
   }
 };
 
@@ -921,23 +917,27 @@ static hipError_t launch_all(int which, const InstDev* insts, const int4* tmap, 
     case 0:
       hipLaunchKernelGGL((k_init<V, PW>), grid, block, 0, s, insts, tmap, sc, k_ckpt, flag);
       break;
-    case 1:
+    case 1: {
+      // this step stores alpha_{m+1} as a checkpoint
+      const bool ck = flag && ((m + 1) % k_ckpt) <= 1;
+      auto kern = ck ? StepKernels<V, PW>::template fwd<true> : StepKernels<V, PW>::template fwd<false>;
       if (timed)
-        hipExtLaunchKernelGGL((StepKernels<V, PW>::fwd), grid, block, 0, s, e0, e1, 0, insts, tmap, sc, m,
-                              k_ckpt, flag);
+        hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, insts, tmap, sc, m, k_ckpt);
       else
-        hipLaunchKernelGGL((StepKernels<V, PW>::fwd), grid, block, 0, s, insts, tmap, sc, m, k_ckpt, flag);
+        hipLaunchKernelGGL(kern, grid, block, 0, s, insts, tmap, sc, m, k_ckpt);
       break;
+    }
     case 2:
       hipLaunchKernelGGL((k_adj_init<V, PW>), grid, block, 0, s, insts, tmap, sc, M);
       break;
-    case 3:
+    case 3: {
+      auto kern = flag ? StepKernels<V, PW>::template adj<true> : StepKernels<V, PW>::template adj<false>;
       if (timed)
-        hipExtLaunchKernelGGL((StepKernels<V, PW>::adj), grid, block, 0, s, e0, e1, 0, insts, tmap, sc, m,
-                              k_ckpt, flag);
+        hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, insts, tmap, sc, m, k_ckpt);
       else
-        hipLaunchKernelGGL((StepKernels<V, PW>::adj), grid, block, 0, s, insts, tmap, sc, m, k_ckpt, flag);
+        hipLaunchKernelGGL(kern, grid, block, 0, s, insts, tmap, sc, m, k_ckpt);
       break;
+    }
     default:
       return hipErrorInvalidValue;
   }

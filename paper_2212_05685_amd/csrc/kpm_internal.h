@@ -14,6 +14,7 @@
 //   mom    [M][ntile][R]     per-(step, 8x4 tile, probe) moment partials
 //   gpart  [nrange][19][N] double2  per-probe-range partial dOmega/dH~ (FP64)
 //   pcode  [R][N] bytes      probe entries (written once per call by the alpha_0 kernel)
+//   sink   4 KB              target of the stores of lanes outside the lattice (never read)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -56,6 +57,7 @@ struct InstDev {
   unsigned char* pcode;  // [R][N] probe entries: nibble a (bits 4a..4a+3) of site i is
                          // 8 | k for entry i^k of Nambu component a, 0 for a zero entry
   double* pw;            // [R] probe weights
+  void* sink;            // 4 KB that stores of lanes outside the lattice go to (never read)
   double2* rho;       // [19][N] output
   const double* omega_bar;
   double* omega;
