@@ -88,7 +88,8 @@ def traffic_summary(base: str, copy_bytes: int) -> None:
     kib_w = max(max(v) for v in cw.values())
     f_fetch, f_write = copy_bytes / (kib_f * 1024.0), copy_bytes / (kib_w * 1024.0)
     out = {}
-    for short, tags in (("k_adj", (">::adj(", "k_adj<")), ("k_fwd", (">::fwd(", "k_fwd<"))):
+    # the plain step launches (not the checkpoint-storing forward nor the last adjoint step)
+    for short, tags in (("k_adj", (">::adj<false>(",)), ("k_fwd", (">::fwd<false>(",))):
         fr = [v for k, vs in fetch.items() if any(t in k for t in tags) for v in vs]
         wr = [v for k, vs in write.items() if any(t in k for t in tags) for v in vs]
         if not fr or not wr:
