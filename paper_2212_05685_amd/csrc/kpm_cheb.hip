@@ -549,6 +549,7 @@ __device__ __forceinline__ void adj_loop(const InstDev& I, const Lane& L, const 
   const Off O = lane_offsets<V>(L);
   const unsigned sown = (unsigned)lane * (unsigned)sizeof(Cx<V>);
   const char* sink = (const char*)I.sink;
+  constexpr bool kEarlyOwn = sizeof(V) == 8;
   R4 sa = ld_rec<V>(probe_base<V>(Ax, pbase, N), O.halo);
   R4 sg = ld_rec<V>(probe_base<V>(Gx, pbase, N), O.halo);
   Cx<V> aq{V(0), V(0)}, gq{V(0), V(0)};
@@ -570,6 +571,18 @@ __device__ __forceinline__ void adj_loop(const InstDev& I, const Lane& L, const 
     __builtin_amdgcn_wave_barrier();
     sa = ld_rec<V>(probe_base<V>(Ax, pn, N), O.halo);
     sg = ld_rec<V>(probe_base<V>(Gx, pn, N), O.halo);
+    // FP64 (one wave per SIMD) issues the next own-site loads here, a step
+    // earlier, into separate registers: its waves need the longer lead more
+    // than they lose to the copies.
+    Cx<V> gq_n{V(0), V(0)}, aq_n{V(0), V(0)};
+    unsigned cq_n = 0u;
+    if constexpr (kEarlyOwn) {
+      if (!TAIL) {
+        gq_n = ld_cx<V>(probe_base<V>(Gy, pn, N), O.own);
+        aq_n = ld_cx<V>(probe_base<V>(Asrc, pn, N), O.own);
+        cq_n = ld_code(I, pn, L);
+      }
+    }
     // dOmega/dH~ contribution of index src: conj(gamma_(i,a)) alpha_(j,b)
     const Cx<V> gi = lds_own<V>(lg + L.hoff[0], L.a);
 #pragma unroll
@@ -596,9 +609,15 @@ __device__ __forceinline__ void adj_loop(const InstDev& I, const Lane& L, const 
         an.x = fma(V(2), t.x, -aq.x);
         an.y = fma(V(2), t.y, -aq.y);
       }
-      gq = ld_cx<V>(probe_base<V>(Gy, pn, N), O.own);
-      aq = ld_cx<V>(probe_base<V>(Asrc, pn, N), O.own);
-      cq = ld_code(I, pn, L);
+      if constexpr (kEarlyOwn) {
+        gq = gq_n;
+        aq = aq_n;
+        cq = cq_n;
+      } else {
+        gq = ld_cx<V>(probe_base<V>(Gy, pn, N), O.own);
+        aq = ld_cx<V>(probe_base<V>(Asrc, pn, N), O.own);
+        cq = ld_code(I, pn, L);
+      }
       st_cx<V>(store_addr(L.valid, probe_base<V>(Gy, p, N) + O.own, sink + sown), 0u, gn);
       st_cx<V>(store_addr(L.valid, probe_base<V>(Ay, p, N) + O.own, sink + sown + 2048u), 0u, an);
     }
