@@ -1,7 +1,8 @@
 """GPU parity of the HIP library against the FP64 oracle, through the C ABI.
 
 Tolerances: FP64 form |dOmega|/|Omega| <= 1e-10 and max|d rho|/max|rho| <=
-1e-10 (the same bar for moments relative to mu_0); element-wise kernels
+1e-10 (the same bar for moments relative to mu_0); the FP32 recursion 1e-5
+against the same FP64 oracle; element-wise kernels
 (builder, VJP, bounds, coefficients) to 1e-12 relative or better.  Sizes span
 several 256-site chunks with a ragged tail, several probe blocks with a
 ragged last block, checkpoint intervals from 2 to 64 and M down to 2.
@@ -18,6 +19,7 @@ from tests.gpu_helpers import dev, host, problem, theta_dev
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
+TOL32 = 1e-5     # FP32 recursion against the FP64 oracle
 
 
 def _cfg(Lx=17, Ly=19, nv=2, M=48, probes=None, **kw):
@@ -109,12 +111,12 @@ def test_energy_grad_fp64(M, k, P):
     assert p.status() == 0
 
 
-def _stencil_run(cfg, st, P=0):
+def _stencil_run(cfg, st, P=0, prec=None, tol=TOL):
     """Energy, moments and gradient of an arbitrary stencil on the GPU and in the
     oracle (each side computes its own bounds and coefficients)."""
     from paper_2212_05685_amd import kpm
     kpm.kpm_set_probe_block(P)
-    p = problem(cfg)
+    p = problem(cfg, precision=prec)
     h = dev(st)
     ab = p.bounds(h)
     C = p.coefficients(ab)
@@ -122,9 +124,9 @@ def _stencil_run(cfg, st, P=0):
     rho = host(p.grand_potential_grad(h, ab, C))
     a, b = H.bounds(cfg, st)
     ref = H.plain(cfg, st, a, b, H.coefficients(cfg, a, b))
-    assert abs(host(omega)[0] - ref["omega"]) < TOL * abs(ref["omega"])
-    assert np.max(np.abs(host(mu) - ref["mu"])) < TOL * np.max(np.abs(ref["mu"]))
-    assert H.rel_err(rho, ref["rho"]) < TOL
+    assert abs(host(omega)[0] - ref["omega"]) < tol * abs(ref["omega"])
+    assert np.max(np.abs(host(mu) - ref["mu"])) < tol * np.max(np.abs(ref["mu"]))
+    assert H.rel_err(rho, ref["rho"]) < tol
     assert p.status() == 0
 
 
@@ -141,6 +143,45 @@ def test_general_stencil_full_rows(P):
     neighbour anomalous entries included (the full-row kernels)."""
     cfg = _cfg(M=40, ckpt_k=6)
     _stencil_run(cfg, _random_stencil(cfg, 11), P)
+
+
+@pytest.mark.parametrize("P", [2, 8])
+def test_general_stencil_full_rows_fp32(P):
+    """The FP32 recursion (its own kernels: full rows here) against the FP64
+    oracle at the FP32 form's tolerance, 1e-5 relative."""
+    cfg = _cfg(M=40, ckpt_k=6)
+    _stencil_run(cfg, _random_stencil(cfg, 11), P, prec="fp32", tol=TOL32)
+
+
+@pytest.mark.parametrize("M,k,P", [(2, 2, 4), (3, 2, 1), (4, 3, 2), (5, 2, 8), (48, 5, 4), (33, 2, 16),
+                                   (40, 6, 32)])
+def test_energy_grad_fp32(M, k, P):
+    """FP32 recursion, FP64 reductions: Omega, moments and rho against the FP64
+    oracle to 1e-5 relative, over step counts of both parities, checkpoint
+    intervals down to 2 (every launch next to an anchor or storing one), probe
+    blocks from 1 to 32 (ragged last waves: 27 probes) and a ragged tile edge."""
+    cfg = _cfg(M=M, ckpt_k=k)
+    p, h, ab, C = _run_forward(cfg, prec="fp32", P=P)
+    omega, mu = p.grand_potential(h, ab, C, want_mu=True)
+    rho = host(p.grand_potential_grad(h, ab, C))
+    st, a, b, Cref = H.oracle_inputs(cfg)
+    ref = H.plain(cfg, st, a, b, Cref)
+    assert abs(host(omega)[0] - ref["omega"]) < TOL32 * abs(ref["omega"])
+    assert np.max(np.abs(host(mu) - ref["mu"])) < TOL32 * np.max(np.abs(ref["mu"]))
+    assert H.rel_err(rho, ref["rho"]) < TOL32
+    assert p.status() == 0
+
+
+def test_mixed_sparse_and_full_rows_fp32():
+    """As below, in the FP32 recursion, whose adjoint has separate sparse-row
+    and full-row loops."""
+    cfg = _cfg(M=40, ckpt_k=6)
+    st = H.stencil(cfg).copy()
+    rnd = _random_stencil(cfg, 12, 0.05)
+    for i in (0, 37, 200, cfg.N - 1):
+        for e in (9, 10, 13, 14, 18):
+            st[e, i] = rnd[e, i]
+    _stencil_run(cfg, st, prec="fp32", tol=TOL32)
 
 
 def test_mixed_sparse_and_full_rows():
