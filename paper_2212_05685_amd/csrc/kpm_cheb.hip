@@ -408,6 +408,15 @@ __device__ __forceinline__ void row_apply(Cx<V>& acc, const RowCoef<V>& K,
   }
 }
 
+// Address of a store that every lane issues: its own element, or the sink for
+// lanes outside the lattice.  The empty asm hides the choice from the
+// compiler, which would otherwise split the store into two conditional ones.
+__device__ __forceinline__ const char* store_addr(bool valid, const char* own, const char* sink) {
+  const char* a = valid ? own : sink;
+  asm volatile("" : "+v"(a));
+  return a;
+}
+
 // ------------------------------------------------------------- forward step
 // The forward step keeps the loads of FPD probes in flight: a register ring of
 // staged halo records, own-site values and code bytes.
@@ -445,6 +454,8 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   // past the wave's last probe re-read that probe; lanes outside the lattice
   // store to the sink), so the compiler's memory-wait counts are exact and a
   // wave waits for the loads it needs, not for its earlier stores.
+  constexpr unsigned RB = sizeof(R4), CB = RB / 2;   // bytes of a record, of a component
+  const char* sink_own = (const char*)I.sink + (unsigned)L.s * RB + (unsigned)L.a * CB;
   double momv = 0.0;                     // moment of probe pbase + lane, stored after the loop
   // Ring of FPD probes in flight.  A slot is refilled only after its values
   // have been consumed, so each load lands in the register it is read from
@@ -479,9 +490,9 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
       const int k = live ? lane_code(cq[u], L.a) : -1;
       pq[u] = ldg_comp<V>(nxt, (unsigned)(pn * N) + L.site, L.a);
       cq[u] = ldg_code(I, (unsigned)(pn * N) + L.site);
-      const unsigned sidx = live ? (unsigned)(p * N) + L.site : (unsigned)L.s;
-      stg_comp<V>(live ? nxt : I.sink, sidx, L.a, o);
-      if (CK) stg_comp<V>(live ? ckbuf : I.sink, sidx, L.a, o);
+      const size_t own = (size_t)((unsigned)(p * N) + L.site) * RB + (unsigned)L.a * CB;
+      st_cx<V>(store_addr(live, (const char*)nxt + own, sink_own), 0u, o);
+      if (CK) st_cx<V>(store_addr(live, (const char*)ckbuf + own, sink_own), 0u, o);
       const double v = wave_moment(re_conj_phase<V>(k, o), k >= 0);
       if (lane == p - pbase) momv = v;
       __builtin_amdgcn_wave_barrier();
@@ -520,15 +531,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(const InstDev* __restrict__
       stg_comp<V>(I.G[(M - 1) & 1], rec, L.a, Cx<V>{V(0), V(0)});
     }
   }
-}
-
-// Address of a store that every lane issues: its own element, or the sink for
-// lanes outside the lattice.  The empty asm hides the choice from the
-// compiler, which would otherwise split the store into two conditional ones.
-__device__ __forceinline__ const char* store_addr(bool valid, const char* own, const char* sink) {
-  const char* a = valid ? own : sink;
-  asm volatile("" : "+v"(a));
-  return a;
 }
 
 // One wave's probes of adjoint step m (see adj_body).  One probe is in
