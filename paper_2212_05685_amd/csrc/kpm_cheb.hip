@@ -552,14 +552,17 @@ __device__ __forceinline__ void adj_loop(const InstDev& I, const Lane& L, const 
   const unsigned sown = (unsigned)lane * (unsigned)sizeof(Cx<V>);
   const char* sink = (const char*)I.sink;
   constexpr bool kEarlyOwn = sizeof(V) == 8;
-  R4 sa = ld_rec<V>(probe_base<V>(Ax, pbase, N), O.halo);
-  R4 sg = ld_rec<V>(probe_base<V>(Gx, pbase, N), O.halo);
+  // a block's last waves can have no probe (pbase >= R): they load a valid
+  // probe and skip the loop
+  const int p0 = min(pbase, I.R - 1);
+  R4 sa = ld_rec<V>(probe_base<V>(Ax, p0, N), O.halo);
+  R4 sg = ld_rec<V>(probe_base<V>(Gx, p0, N), O.halo);
   Cx<V> aq{V(0), V(0)}, gq{V(0), V(0)};
   unsigned cq = 0u;
   if (!TAIL) {
-    gq = ld_cx<V>(probe_base<V>(Gy, pbase, N), O.own);
-    aq = ld_cx<V>(probe_base<V>(Asrc, pbase, N), O.own);
-    cq = ld_code(I, pbase, L);
+    gq = ld_cx<V>(probe_base<V>(Gy, p0, N), O.own);
+    aq = ld_cx<V>(probe_base<V>(Asrc, p0, N), O.own);
+    cq = ld_code(I, p0, L);
   }
   int buf = 0;
   for (int p = pbase; p < pend; ++p, buf ^= 1) {
