@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBoundsBlock) void k_bounds(int Lx, int Ly, const d
   smin[threadIdx.x] = emin;
   sfin[threadIdx.x] = finite;
   __syncthreads();
-  for (int s = kBoundsBlock / 2; s > 0; s >>= 1) {
+  for (unsigned s = kBoundsBlock / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
       smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);

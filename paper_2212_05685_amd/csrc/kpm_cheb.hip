@@ -797,7 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_omega(const InstDev* __restrict__ in
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
+  for (unsigned s = kBlock / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
