@@ -1,0 +1,158 @@
+"""Self-consistent RMFT iteration (oracle; test infrastructure only).
+
+Model and methods: the site and bond parameters theta = (n_i, chi_ij, Delta_ij)
+that define the effective TB-BdG matrix are themselves the local order
+parameters (eqs. delta, chi, pairing) of that matrix's ground state, so they
+are found by iterating theta -> h(theta) -> rho -> theta' until they stop
+changing.  App. A: the electron number is held fixed by the Lagrange multiplier
+mu of W.  The paper gives neither the update rule nor the way mu is found; the
+readings used here, step by step:
+
+1. map (spin-singlet theta): n' = n_up + n_dn, chi' = (chi_up + chi_dn)/2,
+   Delta' = (Delta_up + Delta_dn)/2 with the per-spin order parameters of
+   ``mapping.order_parameters``; for a singlet state the two spin estimates of
+   chi and of Delta are the same quantity;
+2. residual = largest |theta' - theta| over n and every chi, Delta entry
+   (complex moduli), density nbar = (1/N) sum_i n'_i;
+3. mu at fixed theta: e(mu) = nbar(mu) - (1 - doping).  Accept the first
+   evaluation with |e| <= tol_n.  Otherwise walk away from the start on the
+   side that e(mu_0) points to (up for e < 0, down for e > 0) with steps
+   mu_step, 2 mu_step, 4 mu_step, ... until e changes sign, then halve the
+   bracket; a midpoint is accepted when |e| <= tol_n or the half-width of the
+   bracket it splits is <= tol_mu;
+4. theta <- theta + mix (theta' - theta) with the rho of the accepted mu.
+
+``rho_fn(theta, mu) -> (omega, rho)`` supplies the density matrix: the plain
+KPM of ``kpm_plain`` (the path's own truncation and probes) or the exact dense
+Fermi-function result of ``dense`` (no truncation).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import builder, chebyshev, dense, kpm_plain, mapping
+
+
+class NoConvergence(RuntimeError):
+    """The mu search used its evaluation budget without accepting."""
+
+
+@dataclass(frozen=True)
+class Params:
+    doping: float
+    mix: float = 0.5
+    tol_n: float = 1e-6
+    tol_mu: float = 1e-10
+    mu_step: float = 0.02
+    tol_residual: float = 0.0
+    max_evals: int = 60
+    coef_K: int | None = None
+
+
+def singlet_theta(rho):
+    """Step 1: (n', chi', Delta') from the [19, N] density-matrix stencil."""
+    op = mapping.order_parameters(rho)
+    n = op["n_up"] + op["n_dn"]
+    chi = 0.5 * (op["chi_up"] + op["chi_dn"])
+    dlt = 0.5 * (op["delta_up"] + op["delta_dn"])
+    return n, chi, dlt
+
+
+def measure(rho, theta):
+    """Step 2: (nbar, residual) of rho against the current theta."""
+    n1, c1, d1 = singlet_theta(rho)
+    n0, c0, d0 = theta
+    res = max(np.max(np.abs(n1 - n0)), np.max(np.abs(c1 - c0)), np.max(np.abs(d1 - d0)))
+    return float(np.mean(n1)), float(res)
+
+
+def update(rho, theta, mix):
+    """Step 4: theta + mix (theta' - theta), with (nbar, residual) of step 2."""
+    n1, c1, d1 = singlet_theta(rho)
+    n0, c0, d0 = theta
+    nbar, res = measure(rho, theta)
+    new = (n0 + mix * (n1 - n0), c0 + mix * (c1 - c0), d0 + mix * (d1 - d0))
+    return new, nbar, res
+
+
+def solve_mu(e_fn, mu0, prm: Params):
+    """Step 3.  e_fn(mu) -> (e, payload).  Returns (mu, payload, evaluations)."""
+    evals = 1
+    e0, pay = e_fn(mu0)
+    if abs(e0) <= prm.tol_n:
+        return mu0, pay, evals
+    below = e0 < 0.0
+    direction = 1.0 if below else -1.0
+    a, s = mu0, prm.mu_step
+    while True:                       # bracket: walk with doubling steps
+        if evals >= prm.max_evals:
+            raise NoConvergence(f"mu search: {evals} evaluations")
+        m = a + direction * s
+        e, pay = e_fn(m)
+        evals += 1
+        if abs(e) <= prm.tol_n:
+            return m, pay, evals
+        if (e < 0.0) == below:
+            a, s = m, 2.0 * s
+        else:
+            b = m
+            break
+    while True:                       # bisection of [a, b]
+        if evals >= prm.max_evals:
+            raise NoConvergence(f"mu search: {evals} evaluations")
+        m = 0.5 * (a + b)
+        e, pay = e_fn(m)
+        evals += 1
+        if abs(e) <= prm.tol_n or 0.5 * abs(b - a) <= prm.tol_mu:
+            return m, pay, evals
+        if (e < 0.0) == below:
+            a = m
+        else:
+            b = m
+
+
+def iterate(rho_fn, theta, mu, prm: Params, n_iter: int):
+    """Up to n_iter iterations from (theta, mu).  Returns (theta, mu, history);
+    history rows are dicts with mu, nbar, residual, omega, evals."""
+    target = 1.0 - prm.doping
+    hist = []
+    for _ in range(n_iter):
+        def e_fn(m, th=theta):
+            omega, rho = rho_fn(th, m)
+            nbar, res = measure(rho, th)
+            return nbar - target, (omega, rho, nbar, res)
+
+        mu, (omega, rho, nbar, res), evals = solve_mu(e_fn, mu, prm)
+        theta, _, _ = update(rho, theta, prm.mix)
+        hist.append({"mu": mu, "nbar": nbar, "residual": res, "omega": omega, "evals": evals})
+        if prm.tol_residual > 0.0 and res <= prm.tol_residual:
+            break
+    return theta, mu, hist
+
+
+# ------------------------------------------------------------- rho suppliers
+def kpm_rho_fn(Lx, Ly, n_v, t, tp, J, T, M, probes, weights, K=None):
+    """Plain KPM (App. B) on the given probe matrix, with the rescale and
+    coefficients recomputed for every h."""
+    def fn(theta, mu):
+        n, chi, dlt = theta
+        st = builder.build_stencil(Lx, Ly, n_v, t, tp, J, mu, n, chi, dlt)
+        Hs = builder.sparse_from_stencil(st, Lx, Ly)
+        a, b = chebyshev.rescale(*chebyshev.gershgorin_sparse(Hs))
+        C = chebyshev.kpm_coefficients(M, T, a, b, K)
+        out = kpm_plain.plain_kpm(Hs, a, b, probes, weights, C, Lx, Ly, want_grad=True)
+        return float(out["omega"]), out["rho"]
+    return fn
+
+
+def exact_rho_fn(Lx, Ly, n_v, t, tp, J, T):
+    """Exact Fermi-function density matrix by dense diagonalisation."""
+    def fn(theta, mu):
+        n, chi, dlt = theta
+        st = builder.build_stencil(Lx, Ly, n_v, t, tp, J, mu, n, chi, dlt)
+        H = builder.dense_from_stencil(st, Lx, Ly)
+        omega, rho = dense.exact(H, T)
+        return omega, builder.stencil_from_dense(rho, Lx, Ly)
+    return fn
