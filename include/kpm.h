@@ -53,7 +53,8 @@ enum {
   KPM_EBOUNDS = -4,    /* device status: |mu_m| > mu_0 or non-finite value, i.e.
                           the spectrum is not inside the rescaled interval       */
   KPM_ENOTSUP = -5,    /* option not supported                                  */
-  KPM_EWORKSPACE = -6  /* workspace too small or not prepared by the forward call */
+  KPM_EWORKSPACE = -6, /* workspace too small or not prepared by the forward call */
+  KPM_ENOCONV = -7     /* chemical-potential search used its evaluation budget    */
 };
 
 enum { KPM_FP64 = 0, KPM_FP32 = 1 };   /* recurrence vectors; reductions always FP64 */
@@ -230,6 +231,86 @@ int kpm_batch_destroy(void* plan);
 /* Probes-per-thread blocking used by the single-lattice calls (0 = automatic,
  * else one of 1, 2, 4, 8, 16, 32).  Process-wide; returns the previous value. */
 int32_t kpm_set_probe_block(int32_t probes_per_thread);
+
+/* ---- self-consistent iteration (RMFT outer loop) ---------------------------
+ * Model and methods: the local order parameters that define h (eqs. delta,
+ * chi, pairing) are fixed by self-consistency, theta -> h(theta) -> rho ->
+ * theta', iterated until they stop changing; App. A: the electron number is
+ * held by the Lagrange multiplier mu.  The paper states neither the update
+ * rule nor how mu is found; this library uses linear mixing of the spin-
+ * averaged map below and a bracketed bisection of mu at every iteration. */
+
+/* Length, in doubles, of the `stats` buffer of kpm_rmft_update: [0] mean n',
+ * [1] max residual, [2] Omega (written by kpm_rmft_iterate), [3..7] unused,
+ * then per-block partial results. */
+#define KPM_RMFT_STATS_LEN 520
+
+/* Spin-singlet map of the density matrix onto the builder's parameters
+ * (eqs. delta, chi, pairing through App. B's Nambu spinor; the two spin
+ * estimates of a singlet quantity are averaged), for every site i and bond
+ * (i, j = i + d), d = 0..3:
+ *   n'_i       = rho_{i0,i0} + 1 - rho_{i1,i1}
+ *   chi'_d,i   = (rho_{i0,j0} - conj(rho_{i1,j1})) / 2
+ *   delta'_d,i = (-conj(rho_{i0,j1}) - rho_{i1,j0}) / 2,
+ * then theta <- theta + mix (theta' - theta) for theta = (n, chi, delta), in
+ * place.  mix in [0, 1]; mix = 0 leaves theta unchanged (measurement only).
+ * stats (device double[KPM_RMFT_STATS_LEN]) receives [0] = (1/N) sum_i n'_i
+ * and [1] = max over i, d of |n' - n|, |chi' - chi|, |delta' - delta|
+ * (complex moduli; theta before the update); NaN propagates to both.  The
+ * reductions run in a fixed order (bitwise reproducible).
+ * rho [19][N] complex (STENCIL layout), n [N], chi/delta [4][N] complex. */
+int kpm_rmft_update(const kpm_lattice* lat, const double* rho, double mix, double* n,
+                    double* chi, double* delta, double* stats, void* stream);
+
+typedef struct {
+  double doping;      /* target hole density: (1/N) sum_i n_i = 1 - doping, 0 < doping < 1 */
+  double mix;         /* linear mixing weight, 0 < mix <= 1                          */
+  double tol_n;       /* accept mu when |mean n' - (1 - doping)| <= tol_n (>= 0)      */
+  double tol_mu;      /* or when half the bisection bracket is <= tol_mu (>= 0)       */
+  double mu_step;     /* first step of the bracket search (> 0)                       */
+  double tol_residual;/* stop once an iteration's residual <= tol_residual (0: never) */
+  int32_t max_evals;  /* density-matrix evaluations allowed per iteration (>= 1)      */
+  int32_t coef_K;     /* quadrature points of kpm_coefficients (0 = default)          */
+} kpm_rmft_params;
+
+typedef struct {      /* one completed iteration (host memory)                        */
+  double mu;          /* accepted chemical potential                                  */
+  double nbar;        /* mean n' at mu                                                */
+  double residual;    /* max |theta' - theta| at mu, before mixing                    */
+  double omega;       /* grand potential Omega of h(theta, mu)                        */
+  int32_t evals;      /* density-matrix evaluations spent                             */
+  int32_t pad;
+} kpm_rmft_record;
+
+/* Workspace bytes of kpm_rmft_iterate (the kpm_workspace_size region first,
+ * then h, rho, ab, C and stats).  0 on invalid arguments. */
+size_t kpm_rmft_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int32_t ckpt_k,
+                               int32_t precision);
+
+/* Up to n_iter self-consistency iterations.  One iteration, with theta fixed:
+ * an evaluation at mu builds h(theta, mu) (kpm_build_H with model->mu
+ * replaced), rescales it (kpm_bounds), expands f (kpm_coefficients with T and
+ * coef_K) and runs kpm_grand_potential + kpm_grand_potential_grad for rho,
+ * then measures e(mu) = mean n' - (1 - doping) (kpm_rmft_update, mix = 0).
+ * mu search, starting at *mu: accept an evaluation with |e| <= tol_n;
+ * otherwise step from the last point on the side of e(*mu) by s = mu_step,
+ * 2 mu_step, 4 mu_step, ... (up if e < 0, down if e > 0) until e changes
+ * sign, then bisect the bracket; accept the midpoint whose |e| <= tol_n or
+ * whose bracket half-width is <= tol_mu.  The accepted rho then updates theta
+ * with `mix` (kpm_rmft_update); *mu becomes the accepted mu.
+ * n, chi, delta: device, updated in place (layouts of kpm_build_H).
+ * mu: host double in/out.  history: host [n_iter] or NULL.  n_done: host,
+ * iterations completed.  ws: kpm_rmft_workspace_size bytes, 256-byte aligned.
+ * Synchronises `stream` after every evaluation (the host decides the next mu).
+ * Returns KPM_ENOCONV when an iteration spends max_evals evaluations without
+ * accepting (theta, *mu and history hold the last completed iteration), the
+ * recursion's KPM_EBOUNDS when h leaves the rescaled interval or a value is
+ * non-finite, KPM_EINVAL for bad arguments (nothing enqueued). */
+int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_probes* probes,
+                     int32_t M, double T, int32_t precision, int32_t ckpt_k,
+                     const kpm_rmft_params* params, int32_t n_iter, double* n, double* chi,
+                     double* delta, double* mu, kpm_rmft_record* history, int32_t* n_done,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* ---- measurement ----------------------------------------------------------
  * Between kpm_profile_begin and kpm_profile_end, one in `sample_every`

@@ -39,6 +39,11 @@ class NoConvergence(RuntimeError):
     """The mu search used its evaluation budget without accepting."""
 
 
+class NonFinite(FloatingPointError):
+    """An evaluation produced a non-finite density (e.g. a site density at or
+    above one, where the Gutzwiller factors are undefined)."""
+
+
 @dataclass(frozen=True)
 class Params:
     doping: float
@@ -79,8 +84,14 @@ def update(rho, theta, mix):
 
 def solve_mu(e_fn, mu0, prm: Params):
     """Step 3.  e_fn(mu) -> (e, payload).  Returns (mu, payload, evaluations)."""
+    def ev(m):
+        e, pay = e_fn(m)
+        if not np.isfinite(e):
+            raise NonFinite(f"mean density not finite at mu = {m}")
+        return e, pay
+
     evals = 1
-    e0, pay = e_fn(mu0)
+    e0, pay = ev(mu0)
     if abs(e0) <= prm.tol_n:
         return mu0, pay, evals
     below = e0 < 0.0
@@ -90,7 +101,7 @@ def solve_mu(e_fn, mu0, prm: Params):
         if evals >= prm.max_evals:
             raise NoConvergence(f"mu search: {evals} evaluations")
         m = a + direction * s
-        e, pay = e_fn(m)
+        e, pay = ev(m)
         evals += 1
         if abs(e) <= prm.tol_n:
             return m, pay, evals
@@ -103,7 +114,7 @@ def solve_mu(e_fn, mu0, prm: Params):
         if evals >= prm.max_evals:
             raise NoConvergence(f"mu search: {evals} evaluations")
         m = 0.5 * (a + b)
-        e, pay = e_fn(m)
+        e, pay = ev(m)
         evals += 1
         if abs(e) <= prm.tol_n or 0.5 * abs(b - a) <= prm.tol_mu:
             return m, pay, evals

@@ -792,6 +792,7 @@ const char* kpm_strerror(int status) {
     case KPM_EBOUNDS: return "spectrum outside the rescaled interval or non-finite value";
     case KPM_ENOTSUP: return "not supported";
     case KPM_EWORKSPACE: return "workspace too small or not prepared by the forward call";
+    case KPM_ENOCONV: return "chemical-potential search used its evaluation budget";
     default: return "unknown status";
   }
 }

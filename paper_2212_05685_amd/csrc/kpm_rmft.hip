@@ -1,0 +1,263 @@
+// Self-consistent RMFT iteration (Model and methods: theta -> h -> rho -> theta';
+// App. A: mu keeps the electron number): the spin-singlet map with linear
+// mixing as one bandwidth-bound kernel plus two fixed-order reductions, and
+// the outer loop with its chemical-potential search on the host, driving the
+// library's own entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/kpm.h"
+
+namespace {
+
+constexpr int kRB = 256;                       // threads per block
+constexpr int kMaxBlocks = 256;                // partial results per reduction
+constexpr int kHead = 8;                       // stats[0..7]: results, then partials
+static_assert(kHead + 2 * kMaxBlocks <= KPM_RMFT_STATS_LEN, "stats buffer too small");
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// max that keeps a NaN from either side
+__device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
+
+__device__ __forceinline__ double cabs(double2 z) { return hypot(z.x, z.y); }
+
+// One site per thread (grid-stride over sites).  The bond (i, i + d) is stored
+// at its tail i, so every read and write is coalesced along i:
+//   rho entries 4d + {0,1,2,3} and 16, 17; n[i]; chi, delta [d][i].
+// Per block: sum of n'_i and max residual -> part[b], part[kMaxBlocks + b].
+__global__ __launch_bounds__(kRB) void k_rmft_map(int N, const double2* __restrict__ rho, double mix,
+                                                  double* __restrict__ n, double2* __restrict__ chi,
+                                                  double2* __restrict__ dlt, double* __restrict__ part) {
+  double nsum = 0.0, res = 0.0;
+  const bool write = mix != 0.0;
+  for (int i = blockIdx.x * kRB + threadIdx.x; i < N; i += gridDim.x * kRB) {
+    const double n1 = rho[(size_t)16 * N + i].x + 1.0 - rho[(size_t)17 * N + i].x;
+    const double n0 = n[i];
+    nsum += n1;
+    res = nan_max(res, fabs(n1 - n0));
+    if (write) n[i] = n0 + mix * (n1 - n0);
+    for (int d = 0; d < 4; ++d) {
+      const double2 r0 = rho[(size_t)(4 * d + 0) * N + i], r1 = rho[(size_t)(4 * d + 1) * N + i];
+      const double2 r2 = rho[(size_t)(4 * d + 2) * N + i], r3 = rho[(size_t)(4 * d + 3) * N + i];
+      // chi' = (rho_{i0,j0} - conj rho_{i1,j1}) / 2, delta' = (-conj rho_{i0,j1} - rho_{i1,j0}) / 2
+      const double2 c1 = make_double2(0.5 * (r0.x - r3.x), 0.5 * (r0.y + r3.y));
+      const double2 d1 = make_double2(0.5 * (-r1.x - r2.x), 0.5 * (r1.y - r2.y));
+      const size_t k = (size_t)d * N + i;
+      const double2 c0 = chi[k], d0 = dlt[k];
+      const double2 dc = make_double2(c1.x - c0.x, c1.y - c0.y);
+      const double2 dd = make_double2(d1.x - d0.x, d1.y - d0.y);
+      res = nan_max(res, nan_max(cabs(dc), cabs(dd)));
+      if (write) {
+        chi[k] = make_double2(c0.x + mix * dc.x, c0.y + mix * dc.y);
+        dlt[k] = make_double2(d0.x + mix * dd.x, d0.y + mix * dd.y);
+      }
+    }
+  }
+  __shared__ double s_sum[kRB], s_max[kRB];
+  s_sum[threadIdx.x] = nsum;
+  s_max[threadIdx.x] = res;
+  __syncthreads();
+  for (unsigned s = kRB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      s_sum[threadIdx.x] += s_sum[threadIdx.x + s];
+      s_max[threadIdx.x] = nan_max(s_max[threadIdx.x], s_max[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s_sum[0];
+    part[kMaxBlocks + blockIdx.x] = s_max[0];
+  }
+}
+
+// One block: the per-block partials in block order -> stats[0] = mean n',
+// stats[1] = max residual.
+__global__ __launch_bounds__(kRB) void k_rmft_finish(int N, int nblocks, double* __restrict__ stats) {
+  const double* part = stats + kHead;
+  __shared__ double s_sum[kRB], s_max[kRB];
+  const int t = threadIdx.x;
+  s_sum[t] = t < nblocks ? part[t] : 0.0;
+  s_max[t] = t < nblocks ? part[kMaxBlocks + t] : 0.0;
+  __syncthreads();
+  for (unsigned s = kRB / 2; s > 0; s >>= 1) {
+    if (t < (int)s) {
+      s_sum[t] += s_sum[t + s];
+      s_max[t] = nan_max(s_max[t], s_max[t + s]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    stats[0] = s_sum[0] / (double)N;
+    stats[1] = s_max[0];
+  }
+}
+
+bool valid_lattice(const kpm_lattice* L) {
+  return L && L->Lx >= 3 && L->Ly >= 3 && (L->n_vortex % 2) == 0 &&
+         (long long)L->Lx * L->Ly <= (1LL << 26);
+}
+
+// Workspace of kpm_rmft_iterate: the recursion workspace first (so that
+// kpm_status_read works on the same pointer), then h, rho, ab, C, stats.
+struct RmftLayout {
+  size_t kws, h, rho, ab, C, stats, total;
+};
+
+RmftLayout rmft_layout(const kpm_lattice* L, int R, int M, int ckpt_k, int precision) {
+  RmftLayout z{};
+  const size_t kws = kpm_workspace_size(L, R, M, ckpt_k, precision);
+  if (kws == 0) return z;
+  const size_t N = (size_t)L->Lx * L->Ly;
+  z.kws = kws;
+  size_t off = align_up(kws);
+  z.h = off;     off += align_up(19 * N * 16);
+  z.rho = off;   off += align_up(19 * N * 16);
+  z.ab = off;    off += align_up(2 * sizeof(double));
+  z.C = off;     off += align_up((size_t)M * sizeof(double));
+  z.stats = off; off += align_up(KPM_RMFT_STATS_LEN * sizeof(double));
+  z.total = off;
+  return z;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kpm_rmft_update(const kpm_lattice* lat, const double* rho, double mix, double* n, double* chi,
+                    double* delta, double* stats, void* stream) {
+  if (!valid_lattice(lat) || !rho || !n || !chi || !delta || !stats) return KPM_EINVAL;
+  if (!(mix >= 0.0 && mix <= 1.0)) return KPM_EINVAL;
+  const int N = lat->Lx * lat->Ly;
+  const int nb = std::min((N + kRB - 1) / kRB, kMaxBlocks);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_rmft_map, dim3(nb), dim3(kRB), 0, s, N,
+                     reinterpret_cast<const double2*>(rho), mix, n,
+                     reinterpret_cast<double2*>(chi), reinterpret_cast<double2*>(delta),
+                     stats + kHead);
+  if (hipGetLastError() != hipSuccess) return KPM_EDEVICE;
+  hipLaunchKernelGGL(k_rmft_finish, dim3(1), dim3(kRB), 0, s, N, nb, stats);
+  if (hipGetLastError() != hipSuccess) return KPM_EDEVICE;
+  return KPM_OK;
+}
+
+size_t kpm_rmft_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int32_t ckpt_k,
+                               int32_t precision) {
+  if (!valid_lattice(lat)) return 0;
+  return rmft_layout(lat, R, M, ckpt_k, precision).total;
+}
+
+int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_probes* probes,
+                     int32_t M, double T, int32_t precision, int32_t ckpt_k,
+                     const kpm_rmft_params* prm, int32_t n_iter, double* n, double* chi,
+                     double* delta, double* mu, kpm_rmft_record* history, int32_t* n_done,
+                     void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_lattice(lat) || !model || !probes || !prm || !n || !chi || !delta || !mu ||
+      !n_done || !ws || n_iter < 0)
+    return KPM_EINVAL;
+  if (!(prm->doping > 0.0 && prm->doping < 1.0) || !(prm->mix > 0.0 && prm->mix <= 1.0) ||
+      !(prm->tol_n >= 0.0) || !(prm->tol_mu >= 0.0) || !(prm->mu_step > 0.0) ||
+      !std::isfinite(prm->mu_step) || !(prm->tol_residual >= 0.0) || prm->max_evals < 1 ||
+      prm->coef_K < 0 || !std::isfinite(*mu) || !(T > 0.0))
+    return KPM_EINVAL;
+  const int32_t R = kpm_probe_count(lat, probes);
+  if (R < 1) return KPM_EINVAL;
+  const RmftLayout z = rmft_layout(lat, R, M, ckpt_k, precision);
+  if (z.total == 0) return KPM_EINVAL;
+  if (ws_bytes < z.total || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return KPM_EWORKSPACE;
+  *n_done = 0;
+
+  char* base = static_cast<char*>(ws);
+  double* h = reinterpret_cast<double*>(base + z.h);
+  double* rho = reinterpret_cast<double*>(base + z.rho);
+  double* ab = reinterpret_cast<double*>(base + z.ab);
+  double* C = reinterpret_cast<double*>(base + z.C);
+  double* stats = reinterpret_cast<double*>(base + z.stats);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double target = 1.0 - prm->doping;
+
+  // One density-matrix evaluation at chemical potential m with theta fixed:
+  // out[0] = mean n', out[1] = residual, out[2] = Omega.
+  auto evaluate = [&](double m, double out[3]) -> int {
+    kpm_model md = *model;
+    md.mu = m;
+    int st;
+    if ((st = kpm_build_H(lat, &md, n, chi, delta, h, stream)) != KPM_OK) return st;
+    if ((st = kpm_bounds(lat, h, ab, stream)) != KPM_OK) return st;
+    if ((st = kpm_coefficients(M, T, ab, prm->coef_K, C, stream)) != KPM_OK) return st;
+    if ((st = kpm_grand_potential(lat, h, ab, probes, M, C, precision, ckpt_k, stats + 2, nullptr,
+                                  ws, z.kws, stream)) != KPM_OK)
+      return st;
+    if ((st = kpm_grand_potential_grad(lat, h, ab, probes, M, C, precision, ckpt_k, nullptr, rho,
+                                       ws, z.kws, stream)) != KPM_OK)
+      return st;
+    if ((st = kpm_rmft_update(lat, rho, 0.0, n, chi, delta, stats, stream)) != KPM_OK) return st;
+    int32_t dev = KPM_OK;
+    if ((st = kpm_status_read(ws, &dev, stream)) != KPM_OK) return st;
+    if (dev != KPM_OK) return dev;
+    if (hipMemcpyAsync(out, stats, 3 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return KPM_EDEVICE;
+    if (!std::isfinite(out[0]) || !std::isfinite(out[1])) return KPM_EBOUNDS;
+    return KPM_OK;
+  };
+
+  double cur = *mu;
+  for (int it = 0; it < n_iter; ++it) {
+    double v[3];
+    int evals = 0, st;
+    // accepted evaluation: its rho is in the workspace, its figures in v
+    double acc = cur;
+    if ((st = evaluate(cur, v)) != KPM_OK) return st;
+    ++evals;
+    const double e0 = v[0] - target;
+    if (!(std::fabs(e0) <= prm->tol_n)) {
+      const bool below = e0 < 0.0;
+      const double dir = below ? 1.0 : -1.0;
+      double a = cur, b = cur, step = prm->mu_step;
+      bool done = false;
+      for (;;) {                                   // walk with doubling steps
+        if (evals >= prm->max_evals) return KPM_ENOCONV;
+        const double m = a + dir * step;
+        if ((st = evaluate(m, v)) != KPM_OK) return st;
+        ++evals;
+        const double e = v[0] - target;
+        if (std::fabs(e) <= prm->tol_n) { acc = m; done = true; break; }
+        if ((e < 0.0) == below) { a = m; step *= 2.0; }
+        else { b = m; break; }
+      }
+      while (!done) {                              // bisection of [a, b]
+        if (evals >= prm->max_evals) return KPM_ENOCONV;
+        const double m = 0.5 * (a + b);
+        if ((st = evaluate(m, v)) != KPM_OK) return st;
+        ++evals;
+        const double e = v[0] - target;
+        if (std::fabs(e) <= prm->tol_n || 0.5 * std::fabs(b - a) <= prm->tol_mu) { acc = m; break; }
+        if ((e < 0.0) == below) a = m;
+        else b = m;
+      }
+    }
+    if ((st = kpm_rmft_update(lat, rho, prm->mix, n, chi, delta, stats, stream)) != KPM_OK) return st;
+    cur = acc;
+    *mu = acc;
+    if (history) {
+      kpm_rmft_record& r = history[it];
+      r.mu = acc;
+      r.nbar = v[0];
+      r.residual = v[1];
+      r.omega = v[2];
+      r.evals = evals;
+      r.pad = 0;
+    }
+    *n_done = it + 1;
+    if (prm->tol_residual > 0.0 && v[1] <= prm->tol_residual) break;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return KPM_EDEVICE;
+  return KPM_OK;
+}
+
+}  // extern "C"

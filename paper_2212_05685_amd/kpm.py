@@ -23,6 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkpm.so")
 
 KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_EBOUNDS, KPM_ENOTSUP, KPM_EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
+KPM_ENOCONV = -7
+KPM_RMFT_STATS_LEN = 520
 KPM_FP64, KPM_FP32 = 0, 1
 KPM_PROBE_UNIT, KPM_PROBE_DENSE_Z4, KPM_PROBE_COLORED_Z4 = 0, 1, 2
 NENT = 19
@@ -32,7 +34,7 @@ EXPORTS = (
     "kpm_workspace_size", "kpm_moments", "kpm_grand_potential", "kpm_grand_potential_grad",
     "kpm_density_matrix", "kpm_status_read", "kpm_batch_create", "kpm_batch_energy_grad",
     "kpm_batch_destroy", "kpm_set_probe_block", "kpm_profile_begin", "kpm_profile_end",
-    "kpm_strerror",
+    "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
 )
 
 
@@ -52,6 +54,17 @@ class ProbeGroup(ctypes.Structure):
 
 class Probes(ctypes.Structure):
     _fields_ = [("groups", POINTER(ProbeGroup)), ("ngroups", c_int32)]
+
+
+class RmftParams(ctypes.Structure):
+    _fields_ = [("doping", c_double), ("mix", c_double), ("tol_n", c_double), ("tol_mu", c_double),
+                ("mu_step", c_double), ("tol_residual", c_double), ("max_evals", c_int32),
+                ("coef_K", c_int32)]
+
+
+class RmftRecord(ctypes.Structure):
+    _fields_ = [("mu", c_double), ("nbar", c_double), ("residual", c_double), ("omega", c_double),
+                ("evals", c_int32), ("pad", c_int32)]
 
 
 class KpmError(RuntimeError):
@@ -91,6 +104,12 @@ def _load():
         "kpm_profile_end": (c_int32, [POINTER(c_double), POINTER(c_int32), POINTER(c_double),
                                       POINTER(c_int32)]),
         "kpm_strerror": (ctypes.c_char_p, [c_int32]),
+        "kpm_rmft_update": (c_int32, [POINTER(Lattice), P, c_double, P, P, P, P, P]),
+        "kpm_rmft_workspace_size": (c_size_t, [POINTER(Lattice), c_int32, c_int32, c_int32, c_int32]),
+        "kpm_rmft_iterate": (c_int32, [POINTER(Lattice), POINTER(Model), POINTER(Probes), c_int32,
+                                       c_double, c_int32, c_int32, POINTER(RmftParams), c_int32, P, P,
+                                       P, POINTER(c_double), POINTER(RmftRecord), POINTER(c_int32),
+                                       P, c_size_t, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -283,6 +302,50 @@ def kpm_profile_end():
 
 def kpm_strerror(status: int) -> str:
     return strerror(status)
+
+
+def kpm_rmft_update(lat, rho, mix, n, chi, delta, stats, stream=None):
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_rmft_update(ctypes.byref(lat), _ptr(rho, torch.complex128, NENT * N, "rho"),
+                                float(mix), _ptr(n, torch.float64, N, "n"),
+                                _ptr(chi, torch.complex128, 4 * N, "chi"),
+                                _ptr(delta, torch.complex128, 4 * N, "delta"),
+                                _ptr(stats, torch.float64, KPM_RMFT_STATS_LEN, "stats"),
+                                _stream(stream)), "kpm_rmft_update")
+
+
+def kpm_rmft_workspace_size(lat, R, M, ckpt_k, precision) -> int:
+    n = _lib.kpm_rmft_workspace_size(ctypes.byref(lat), R, M, ckpt_k, precision)
+    if n == 0:
+        raise KpmError(KPM_EINVAL, "kpm_rmft_workspace_size")
+    return int(n)
+
+
+def rmft_params(doping, mix=0.1, tol_n=1e-6, tol_mu=1e-10, mu_step=0.004, tol_residual=0.0,
+                max_evals=60, coef_K=0) -> RmftParams:
+    return RmftParams(doping, mix, tol_n, tol_mu, mu_step, tol_residual, max_evals, coef_K)
+
+
+def kpm_rmft_iterate(lat, mdl, probes, M, T, precision, ckpt_k, params, n_iter, n, chi, delta, mu,
+                     ws, stream=None):
+    """Runs up to n_iter iterations in place on (n, chi, delta).  Returns
+    (mu, history as a list of dicts, status); status is KPM_OK or KPM_ENOCONV
+    (other errors raise)."""
+    N = lat.Lx * lat.Ly
+    mu_c = c_double(mu)
+    hist = (RmftRecord * max(n_iter, 1))()
+    done = c_int32(0)
+    st = _lib.kpm_rmft_iterate(ctypes.byref(lat), ctypes.byref(mdl), ctypes.byref(_probes(probes)), M,
+                               T, precision, ckpt_k, ctypes.byref(params), n_iter,
+                               _ptr(n, torch.float64, N, "n"), _ptr(chi, torch.complex128, 4 * N, "chi"),
+                               _ptr(delta, torch.complex128, 4 * N, "delta"), ctypes.byref(mu_c),
+                               hist, ctypes.byref(done), _ptr(ws, torch.uint8, None, "ws"),
+                               ws.numel(), _stream(stream))
+    if st not in (KPM_OK, KPM_ENOCONV):
+        raise KpmError(st, "kpm_rmft_iterate")
+    out = [{"mu": r.mu, "nbar": r.nbar, "residual": r.residual, "omega": r.omega, "evals": r.evals}
+           for r in hist[:done.value]]
+    return mu_c.value, out, st
 
 
 def kpm_batch_create(lats: Sequence[Lattice], probes: Sequence[Sequence[ProbeSpec]], M, precision,

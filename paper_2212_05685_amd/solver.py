@@ -29,6 +29,7 @@ class KPMProblem:
     ckpt_k: int = 64
     device: str = "cuda"
     _ws: torch.Tensor = field(default=None, repr=False)
+    _rmft_ws: torch.Tensor = field(default=None, repr=False)
 
     def __post_init__(self):
         self.lat = kpm.lattice(self.Lx, self.Ly, self.n_vortex)
@@ -100,3 +101,43 @@ class KPMProblem:
 
     def status(self) -> int:
         return kpm.kpm_status_read(self.workspace())
+
+    # -- self-consistent iteration (kpm_rmft_iterate)
+    def rmft_workspace(self) -> torch.Tensor:
+        if self._rmft_ws is None:
+            nb = kpm.kpm_rmft_workspace_size(self.lat, self.R, self.M, self.ckpt_k, self.precision)
+            self._rmft_ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        return self._rmft_ws
+
+    def rmft_iterate(self, n, chi, delta, mu, params, n_iter):
+        """Up to n_iter iterations on (n, chi, delta) in place from chemical
+        potential mu.  Returns (mu, history, status)."""
+        return kpm.kpm_rmft_iterate(self.lat, self.mdl, self.probes, self.M, self.T, self.precision,
+                                    self.ckpt_k, params, n_iter, n, chi, delta, mu,
+                                    self.rmft_workspace())
+
+
+def save_rmft_state(path, n, chi, delta, mu, history=()):
+    """Writes theta, mu and the iteration history to an .npz file (a restart
+    point of the self-consistent iteration)."""
+    import numpy as np
+
+    def host(t):
+        return t.detach().cpu().numpy()
+
+    rec = np.array([(h["mu"], h["nbar"], h["residual"], h["omega"], h["evals"]) for h in history],
+                   dtype=np.float64).reshape(-1, 5)
+    np.savez(path, n=host(n), chi=host(chi), delta=host(delta), mu=np.float64(mu), history=rec)
+
+
+def load_rmft_state(path, device="cuda"):
+    """(n, chi, delta, mu, history) from ``save_rmft_state``; tensors on device."""
+    import numpy as np
+
+    with np.load(path, allow_pickle=False) as z:
+        n = torch.from_numpy(z["n"]).to(device)
+        chi = torch.from_numpy(z["chi"]).to(device)
+        delta = torch.from_numpy(z["delta"]).to(device)
+        hist = [{"mu": r[0], "nbar": r[1], "residual": r[2], "omega": r[3], "evals": int(r[4])}
+                for r in z["history"]]
+        return n, chi, delta, float(z["mu"]), hist

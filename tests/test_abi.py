@@ -73,3 +73,64 @@ def test_host_validation():
     old = kpm.kpm_set_probe_block(4)
     assert kpm.kpm_set_probe_block(3) == 4       # invalid value leaves the setting
     assert kpm.kpm_set_probe_block(old) == 4
+
+
+def test_rmft_host_validation():
+    """kpm_rmft_update / kpm_rmft_iterate reject bad arguments before any
+    device work (placeholder pointers are never dereferenced)."""
+    from paper_2212_05685_amd import kpm
+
+    lat = kpm.lattice(8, 8, 0)
+    fake = ctypes.c_void_p(256)
+    assert ctypes.sizeof(kpm.RmftParams) == 56 and ctypes.sizeof(kpm.RmftRecord) == 40
+    assert kpm.RmftRecord.evals.offset == 32
+    for mix in (-0.1, 1.5, float("nan")):
+        assert kpm._lib.kpm_rmft_update(ctypes.byref(lat), fake, mix, fake, fake, fake, fake,
+                                        None) == kpm.KPM_EINVAL
+    assert kpm._lib.kpm_rmft_update(ctypes.byref(kpm.lattice(2, 8, 0)), fake, 0.5, fake, fake, fake,
+                                    fake, None) == kpm.KPM_EINVAL
+    base = kpm.kpm_workspace_size(lat, 16, 64, 8, kpm.KPM_FP64)
+    full = kpm.kpm_rmft_workspace_size(lat, 16, 64, 8, kpm.KPM_FP64)
+    assert full > base + 2 * 19 * 64 * 16
+    assert kpm._lib.kpm_rmft_workspace_size(ctypes.byref(lat), 16, 1, 8, 0) == 0
+
+    mdl = kpm.model(1.0, -0.3, 0.3, 0.0)
+    pr = kpm._probes([kpm.ProbeSpec(kpm.KPM_PROBE_UNIT, 16)])
+    mu = ctypes.c_double(1.0)
+    done = ctypes.c_int32(-1)
+
+    def call(prm, ws_bytes=full, n_iter=1, T=0.005, ws=ctypes.c_void_p(1 << 20)):
+        return kpm._lib.kpm_rmft_iterate(ctypes.byref(lat), ctypes.byref(mdl), ctypes.byref(pr), 64, T,
+                                         kpm.KPM_FP64, 8, ctypes.byref(prm), n_iter, fake, fake, fake,
+                                         ctypes.byref(mu), None, ctypes.byref(done), ws, ws_bytes, None)
+
+    good = kpm.rmft_params(0.16)
+    for bad in (kpm.rmft_params(0.0), kpm.rmft_params(1.0), kpm.rmft_params(0.16, mix=0.0),
+                kpm.rmft_params(0.16, mix=1.2), kpm.rmft_params(0.16, tol_n=-1.0),
+                kpm.rmft_params(0.16, mu_step=0.0), kpm.rmft_params(0.16, max_evals=0),
+                kpm.rmft_params(0.16, coef_K=-1)):
+        assert call(bad) == kpm.KPM_EINVAL
+    assert call(good, n_iter=-1) == kpm.KPM_EINVAL
+    assert call(good, T=0.0) == kpm.KPM_EINVAL
+    assert call(good, ws_bytes=full - 1) == kpm.KPM_EWORKSPACE
+    assert call(good, ws=ctypes.c_void_p((1 << 20) + 64)) == kpm.KPM_EWORKSPACE
+    assert done.value == -1                     # nothing ran
+    assert kpm.strerror(kpm.KPM_ENOCONV).startswith("chemical-potential")
+
+
+def test_rmft_state_round_trip(tmp_path):
+    import numpy as np
+    import torch
+
+    from paper_2212_05685_amd.solver import load_rmft_state, save_rmft_state
+
+    rng = np.random.default_rng(5)
+    n = torch.from_numpy(rng.uniform(0.7, 0.9, 12))
+    chi = torch.from_numpy(rng.normal(size=(4, 12)) + 1j * rng.normal(size=(4, 12)))
+    dlt = torch.from_numpy(rng.normal(size=(4, 12)) + 1j * rng.normal(size=(4, 12)))
+    hist = [{"mu": 1.5, "nbar": 0.84, "residual": 0.01, "omega": -3.0, "evals": 7}]
+    p = tmp_path / "state.npz"
+    save_rmft_state(p, n, chi, dlt, 1.625, hist)
+    n2, c2, d2, mu2, h2 = load_rmft_state(p, device="cpu")
+    assert torch.equal(n, n2) and torch.equal(chi, c2) and torch.equal(dlt, d2)
+    assert mu2 == 1.625 and h2 == hist

@@ -13,7 +13,10 @@ radius 3 lattice constants, hole doping 0.05-0.25, and an optional period-8
 checkerboard pair/charge-density modulation.
 
 Recipe (every config):
-* chi = 0.2 on nearest-neighbour bonds, 0 on next-nearest-neighbour bonds;
+* chi = chi0 (default 0.2) on nearest-neighbour bonds, 0 on next-nearest-
+  neighbour bonds.  A real chi does not carry the Peierls phases of a field,
+  so with a field the self-consistent runs seed chi0 = 0 and let the first
+  density matrix supply the bond phases;
 * Delta = +0.1 on x bonds, -0.1 on y bonds, 0 on diagonal bonds;
 * n_i = 1 - delta (m_i = 0);
 * ``noise``: uniform(-noise, noise) real noise per nn bond on chi and Delta and
@@ -79,6 +82,7 @@ class Config:
     t: float = T_HOP
     tp: float = TP_HOP
     J: float = J_EX
+    chi0: float = 0.2            # seed chi on nearest-neighbour bonds
 
     @property
     def N(self) -> int:
@@ -132,7 +136,7 @@ def make_theta(cfg: Config):
     n = np.full(N, 1.0 - cfg.doping)
     chi = np.zeros((4, N), dtype=np.complex128)
     dlt = np.zeros((4, N), dtype=np.complex128)
-    chi[0] = chi[1] = 0.2
+    chi[0] = chi[1] = cfg.chi0
     dlt[0] = 0.1
     dlt[1] = -0.1
     if cfg.noise:
@@ -209,6 +213,24 @@ def C5(precision="fp32") -> Config:
     return Config("C5_100x100_vortex_pdw", 100, 100, 2, 0.125, 4096,
                   (ProbeSpec("colored_z4", 2, s, 8, 8, 1, 0, 0.5),),
                   precision, ckpt_k=64, seed=s, vortex=True, pdw=0.02)
+
+
+def RMFT(precision="fp32") -> Config:
+    """Plain-vortex self-consistency workload of the Results section: 48 x 96
+    torus, two vortices half the lattice apart in y, mean hole density 0.16,
+    M = 1024 (paper range 1000-2000), 128 colored probes (range 64-144)."""
+    s = _seed(6)
+    return Config("RMFT_48x96_plain_vortex", 48, 96, 2, 0.16, 1024,
+                  (ProbeSpec("colored_z4", 1, s, 8, 8, 1, 0, 1.0),),
+                  precision, ckpt_k=64, seed=s, vortex=True, chi0=0.0)
+
+
+def random_stencil(N: int, seed: int, scale: float = 0.5):
+    """Seeded complex [19, N] array of stencil entries, uniform in
+    [-scale, scale] for both parts (a stand-in density matrix for tests of the
+    order-parameter map)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-scale, scale, (19, N)) + 1j * rng.uniform(-scale, scale, (19, N))
 
 
 def scaled(cfg: Config, **kw) -> Config:
