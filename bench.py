@@ -251,7 +251,91 @@ def batched_form(steps: int):
     }
 
 
-def cpu_baseline(cfg):
+def rmft_form(iters: int, warmup: int):
+    """Self-consistent iteration on the plain-vortex workload of the Results
+    section (48 x 96, two vortices, mean hole density 0.16, M = 1024, 128
+    colored probes, FP32 recursion): every iteration runs the chemical-
+    potential search (density-matrix evaluations) and the mixing update.
+    After `warmup` iterations, the same state is iterated `iters` times with
+    each search; the fused adjoint kernel is timed live during the Illinois
+    run, and the oracle's cost per evaluation is sampled on one probe."""
+    import torch
+    from paper_2212_05685_amd import kpm
+    import workloads as wl
+
+    cfg = wl.RMFT("fp32")
+    prob, th = make_problem(cfg, "fp32")
+    n, chi, dlt = th
+
+    def params(search):
+        return kpm.rmft_params(cfg.doping, mix=0.1, tol_n=1e-5, tol_mu=1e-9, mu_step=0.004,
+                               max_evals=60, search=search)
+
+    mu_w, _, st = prob.rmft_iterate(n, chi, dlt, cfg.mu, params(kpm.KPM_RMFT_ILLINOIS), warmup)
+    if st != kpm.KPM_OK:
+        raise RuntimeError(f"rmft warmup status {st}")
+    torch.cuda.synchronize()
+    log(f"rmft warmup {warmup} iterations done, mu = {mu_w:.6f}")
+    out = {}
+    prof = None
+    for name, search in (("illinois", kpm.KPM_RMFT_ILLINOIS), ("bisection", kpm.KPM_RMFT_BISECTION)):
+        n2, chi2, dlt2 = n.clone(), chi.clone(), dlt.clone()
+        torch.cuda.synchronize()
+        if name == "illinois":
+            kpm.kpm_profile_begin(4)
+        t0 = time.perf_counter()
+        mu, hist, st = prob.rmft_iterate(n2, chi2, dlt2, mu_w, params(search), iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if name == "illinois":
+            prof = kpm.kpm_profile_end()
+        if st != kpm.KPM_OK or len(hist) != iters:
+            raise RuntimeError(f"rmft status {st}")
+        evals = sum(h["evals"] for h in hist)
+        log(f"rmft {name}: {iters} iterations, {dt / iters * 1e3:.1f} ms/iteration, "
+            f"{evals / iters:.1f} evaluations each")
+        out[name] = {"s_per_iteration": dt / iters, "evaluations_per_iteration": evals / iters,
+                     "ms_per_density_matrix_evaluation": dt / evals * 1e3,
+                     "residual_first": hist[0]["residual"], "residual_last": hist[-1]["residual"],
+                     "mu_last": mu}
+    R, N = prob.R, cfg.N
+    adj_bytes = 6 * 16 * R * N + 36 * 8 * N
+    _, _, adj_ms, n_adj = prof
+    adj_s = adj_ms / max(n_adj, 1) * 1e-3
+    achieved = adj_bytes / adj_s / 1e9
+    cpu = cpu_baseline(cfg, quiet=True)
+    t_eval_cpu = cpu["seconds"] * R
+    ill = out["illinois"]
+    return {
+        "workload": "48x96 torus, 2 vortices (plain-vortex seed, chi seeded 0), doping 0.16, M=1024, "
+                    "128 colored Z4 probes (8x8, Nambu split), FP32 recurrence; mixing 0.1, mu search "
+                    "to |mean n - 0.84| <= 1e-5",
+        "iterations_timed": iters,
+        "warmup_iterations": warmup,
+        "s_per_iteration": ill["s_per_iteration"],
+        "evaluations_per_iteration": ill["evaluations_per_iteration"],
+        "ms_per_density_matrix_evaluation": ill["ms_per_density_matrix_evaluation"],
+        "search": out,
+        "speedup_illinois_over_bisection": out["bisection"]["s_per_iteration"] / ill["s_per_iteration"],
+        "roofline": {
+            "kernel": "k_adj (fused adjoint step) at 48x96, R=128",
+            "bound": "hbm",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": adj_bytes, "avg_launch_us": adj_s * 1e6,
+            "launches_timed": n_adj,
+        },
+        "cpu_baseline": {
+            "value": t_eval_cpu * ill["evaluations_per_iteration"], "unit": "s/iteration",
+            "cores": 1, "kind": "oracle",
+            "sample": f"oracle forward + adjoint on 1 of {R} probes at 48x96, M={cfg.M}: "
+                      f"{cpu['seconds']:.2f} s, times {R} probes and the measured "
+                      f"{ill['evaluations_per_iteration']:.1f} evaluations per iteration",
+        },
+    }
+
+
+def cpu_baseline(cfg, quiet=False):
     """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
     probe of the same workload, single thread."""
     import numpy as np
@@ -275,6 +359,8 @@ def cpu_baseline(cfg):
         t1 = time.perf_counter()
     vsteps = 3 * cfg.M - 5
     log(f"cpu baseline: {t1 - t0:.1f} s")
+    if quiet:
+        return {"seconds": t1 - t0}
     return {"value": vsteps / (t1 - t0), "unit": "vector-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"1 of {cfg.R} probes of the 100x100 workload (M={cfg.M}): plain FP64 forward "
                       f"recursion + beta adjoint with every vector stored (oracle O2), single thread, "
@@ -289,6 +375,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--no-batched-form", action="store_true")
+    ap.add_argument("--no-rmft-form", action="store_true")
+    ap.add_argument("--only-rmft-form", action="store_true",
+                    help="run only the self-consistent iteration timing and print its JSON (profiling)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without per-kernel events (roofline fields omitted)")
     ap.add_argument("--moments", type=int, default=0,
@@ -327,6 +416,9 @@ def main():
     if args.probe_block:
         from paper_2212_05685_amd import kpm
         kpm.kpm_set_probe_block(args.probe_block)
+    if args.only_rmft_form:
+        print(json.dumps({"rmft_form": rmft_form(args.steps, args.warmup)}), flush=True)
+        return
     cfg = wl.C5("fp32")
     if args.moments:
         cfg = wl.scaled(cfg, M=args.moments)
@@ -408,6 +500,10 @@ def main():
 
     if not args.no_batched_form and not args.moments:
         result["batched_form"] = batched_form(3)
+        torch.cuda.empty_cache()
+
+    if not args.no_rmft_form and not args.moments:
+        result["rmft_form"] = rmft_form(5, 2)
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:

@@ -262,6 +262,8 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread);
 int kpm_rmft_update(const kpm_lattice* lat, const double* rho, double mix, double* n,
                     double* chi, double* delta, double* stats, void* stream);
 
+enum { KPM_RMFT_BISECTION = 0, KPM_RMFT_ILLINOIS = 1 };   /* mu search inside the bracket */
+
 typedef struct {
   double doping;      /* target hole density: (1/N) sum_i n_i = 1 - doping, 0 < doping < 1 */
   double mix;         /* linear mixing weight, 0 < mix <= 1                          */
@@ -271,6 +273,8 @@ typedef struct {
   double tol_residual;/* stop once an iteration's residual <= tol_residual (0: never) */
   int32_t max_evals;  /* density-matrix evaluations allowed per iteration (>= 1)      */
   int32_t coef_K;     /* quadrature points of kpm_coefficients (0 = default)          */
+  int32_t search;     /* KPM_RMFT_BISECTION or KPM_RMFT_ILLINOIS                      */
+  int32_t pad;
 } kpm_rmft_params;
 
 typedef struct {      /* one completed iteration (host memory)                        */
@@ -295,8 +299,14 @@ size_t kpm_rmft_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int
  * mu search, starting at *mu: accept an evaluation with |e| <= tol_n;
  * otherwise step from the last point on the side of e(*mu) by s = mu_step,
  * 2 mu_step, 4 mu_step, ... (up if e < 0, down if e > 0) until e changes
- * sign, then bisect the bracket; accept the midpoint whose |e| <= tol_n or
- * whose bracket half-width is <= tol_mu.  The accepted rho then updates theta
+ * sign, then narrow the bracket [a, b] (b the newest point):
+ *   BISECTION: m = (a + b)/2; accept m when |e(m)| <= tol_n or
+ *              |b - a|/2 <= tol_mu, else keep the half that brackets the root;
+ *   ILLINOIS:  m = b - e_b (b - a)/(e_b - e_a) (false position); if e(m) and
+ *              e_b differ in sign a <- b, else e_a <- e_a/2; then b <- m;
+ *              accept m when |e(m)| <= tol_n or |b - a| <= tol_mu
+ *              (Dowell & Jarratt, BIT 11, 168 (1971)).
+ * The accepted rho then updates theta
  * with `mix` (kpm_rmft_update); *mu becomes the accepted mu.
  * n, chi, delta: device, updated in place (layouts of kpm_build_H).
  * mu: host double in/out.  history: host [n_iter] or NULL.  n_done: host,

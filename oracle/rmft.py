@@ -19,7 +19,12 @@ readings used here, step by step:
    side that e(mu_0) points to (up for e < 0, down for e > 0) with steps
    mu_step, 2 mu_step, 4 mu_step, ... until e changes sign, then halve the
    bracket; a midpoint is accepted when |e| <= tol_n or the half-width of the
-   bracket it splits is <= tol_mu;
+   bracket it splits is <= tol_mu.  Alternatively (search = "illinois") the
+   bracket [a, b], b the newest point, is narrowed by false position,
+   m = b - e_b (b - a)/(e_b - e_a), with the Illinois modification (Dowell and
+   Jarratt, BIT 11, 168 (1971)): if e(m) has the sign of e_b the kept end's
+   value e_a is halved, otherwise a takes b's place; b <- m; accepted when
+   |e| <= tol_n or |b - a| <= tol_mu;
 4. theta <- theta + mix (theta' - theta) with the rho of the accepted mu.
 
 ``rho_fn(theta, mu) -> (omega, rho)`` supplies the density matrix: the plain
@@ -54,6 +59,7 @@ class Params:
     tol_residual: float = 0.0
     max_evals: int = 60
     coef_K: int | None = None
+    search: str = "bisection"      # or "illinois"
 
 
 def singlet_theta(rho):
@@ -96,7 +102,7 @@ def solve_mu(e_fn, mu0, prm: Params):
         return mu0, pay, evals
     below = e0 < 0.0
     direction = 1.0 if below else -1.0
-    a, s = mu0, prm.mu_step
+    a, ea, s = mu0, e0, prm.mu_step
     while True:                       # bracket: walk with doubling steps
         if evals >= prm.max_evals:
             raise NoConvergence(f"mu search: {evals} evaluations")
@@ -106,10 +112,26 @@ def solve_mu(e_fn, mu0, prm: Params):
         if abs(e) <= prm.tol_n:
             return m, pay, evals
         if (e < 0.0) == below:
-            a, s = m, 2.0 * s
+            a, ea, s = m, e, 2.0 * s
         else:
-            b = m
+            b, eb = m, e
             break
+    if prm.search == "illinois":
+        while True:
+            if evals >= prm.max_evals:
+                raise NoConvergence(f"mu search: {evals} evaluations")
+            m = b - eb * (b - a) / (eb - ea)
+            e, pay = ev(m)
+            evals += 1
+            if (e < 0.0) != (eb < 0.0):
+                a, ea = b, eb
+            else:
+                ea = 0.5 * ea
+            b, eb = m, e
+            if abs(e) <= prm.tol_n or abs(b - a) <= prm.tol_mu:
+                return m, pay, evals
+    if prm.search != "bisection":
+        raise ValueError(f"unknown search {prm.search!r}")
     while True:                       # bisection of [a, b]
         if evals >= prm.max_evals:
             raise NoConvergence(f"mu search: {evals} evaluations")

@@ -162,7 +162,8 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
   if (!(prm->doping > 0.0 && prm->doping < 1.0) || !(prm->mix > 0.0 && prm->mix <= 1.0) ||
       !(prm->tol_n >= 0.0) || !(prm->tol_mu >= 0.0) || !(prm->mu_step > 0.0) ||
       !std::isfinite(prm->mu_step) || !(prm->tol_residual >= 0.0) || prm->max_evals < 1 ||
-      prm->coef_K < 0 || !std::isfinite(*mu) || !(T > 0.0))
+      prm->coef_K < 0 || !std::isfinite(*mu) || !(T > 0.0) ||
+      (prm->search != KPM_RMFT_BISECTION && prm->search != KPM_RMFT_ILLINOIS))
     return KPM_EINVAL;
   const int32_t R = kpm_probe_count(lat, probes);
   if (R < 1) return KPM_EINVAL;
@@ -218,7 +219,7 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
     if (!(std::fabs(e0) <= prm->tol_n)) {
       const bool below = e0 < 0.0;
       const double dir = below ? 1.0 : -1.0;
-      double a = cur, b = cur, step = prm->mu_step;
+      double a = cur, b = cur, fa = e0, fb = e0, step = prm->mu_step;
       bool done = false;
       for (;;) {                                   // walk with doubling steps
         if (evals >= prm->max_evals) return KPM_ENOCONV;
@@ -227,10 +228,10 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
         ++evals;
         const double e = v[0] - target;
         if (std::fabs(e) <= prm->tol_n) { acc = m; done = true; break; }
-        if ((e < 0.0) == below) { a = m; step *= 2.0; }
-        else { b = m; break; }
+        if ((e < 0.0) == below) { a = m; fa = e; step *= 2.0; }
+        else { b = m; fb = e; break; }
       }
-      while (!done) {                              // bisection of [a, b]
+      while (!done && prm->search == KPM_RMFT_BISECTION) {   // bisection of [a, b]
         if (evals >= prm->max_evals) return KPM_ENOCONV;
         const double m = 0.5 * (a + b);
         if ((st = evaluate(m, v)) != KPM_OK) return st;
@@ -239,6 +240,21 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
         if (std::fabs(e) <= prm->tol_n || 0.5 * std::fabs(b - a) <= prm->tol_mu) { acc = m; break; }
         if ((e < 0.0) == below) a = m;
         else b = m;
+      }
+      // Illinois false position on [a, b], b the newest point: the secant
+      // root of (a, fa), (b, fb); the retained end's value is halved when it
+      // is kept twice in a row (Dowell & Jarratt, BIT 11, 168 (1971)).
+      while (!done && prm->search == KPM_RMFT_ILLINOIS) {
+        if (evals >= prm->max_evals) return KPM_ENOCONV;
+        const double m = b - fb * (b - a) / (fb - fa);
+        if ((st = evaluate(m, v)) != KPM_OK) return st;
+        ++evals;
+        const double e = v[0] - target;
+        if ((e < 0.0) != (fb < 0.0)) { a = b; fa = fb; }
+        else fa = 0.5 * fa;
+        b = m;
+        fb = e;
+        if (std::fabs(e) <= prm->tol_n || std::fabs(b - a) <= prm->tol_mu) { acc = m; break; }
       }
     }
     if ((st = kpm_rmft_update(lat, rho, prm->mix, n, chi, delta, stats, stream)) != KPM_OK) return st;

@@ -5,7 +5,7 @@ kpm_rmft_iterate) against the oracle's loop (oracle/rmft.py), through the C ABI.
   density matrices, element by element, at a ragged size, at the 48 x 96
   workload size and above the one-pass grid (grid-stride path): FP64 with the
   same operations, so 1e-14 absolute;
-* whole iterations in FP64 (bisection decisions, evaluation counts, mu,
+* whole iterations in FP64 with either search (bracket decisions, evaluation counts, mu,
   mean density, residual, Omega and theta after every iteration) against the
   oracle loop on the plain KPM: evaluation counts exact, values to the FP64
   bar 1e-10 (relative for Omega and rho-derived values);
@@ -83,14 +83,18 @@ def _gpu_loop(cfg, p, n_iter, mu0, precision=None):
 
     pb = problem(cfg, precision=precision)
     n, chi, dlt = theta_dev(cfg)
-    prm = kpm.rmft_params(p.doping, p.mix, p.tol_n, p.tol_mu, p.mu_step, p.tol_residual, p.max_evals)
+    search = {"bisection": kpm.KPM_RMFT_BISECTION, "illinois": kpm.KPM_RMFT_ILLINOIS}[p.search]
+    prm = kpm.rmft_params(p.doping, p.mix, p.tol_n, p.tol_mu, p.mu_step, p.tol_residual, p.max_evals,
+                          search=search)
     mu, hist, st = pb.rmft_iterate(n, chi, dlt, mu0, prm, n_iter)
     return (host(n), host(chi), host(dlt)), mu, hist, st
 
 
-def test_iterate_parity_fp64():
+@pytest.mark.parametrize("search", ["bisection", "illinois"])
+def test_iterate_parity_fp64(search):
     cfg = _loop_cfg()
-    prm = ormft.Params(doping=0.16, mix=0.1, tol_n=1e-5, tol_mu=1e-10, mu_step=0.004, max_evals=60)
+    prm = ormft.Params(doping=0.16, mix=0.1, tol_n=1e-5, tol_mu=1e-10, mu_step=0.004, max_evals=60,
+                       search=search)
     mu0 = cfg.mu
     th_ref, mu_ref, hist_ref = _oracle_loop(cfg, prm, 3, mu0)
     th, mu, hist, st = _gpu_loop(cfg, prm, 3, mu0)
@@ -140,7 +144,8 @@ def test_iterate_budget_leaves_theta():
 def test_rmft_workload_48x96():
     """Two iterations of the plain-vortex workload (FP32 recursion)."""
     cfg = wl.RMFT()
-    prm = ormft.Params(doping=cfg.doping, mix=0.1, tol_n=1e-5, tol_mu=1e-9, mu_step=0.004, max_evals=60)
+    prm = ormft.Params(doping=cfg.doping, mix=0.1, tol_n=1e-5, tol_mu=1e-9, mu_step=0.004, max_evals=60,
+                       search="illinois")
     th, mu, hist, st = _gpu_loop(cfg, prm, 2, cfg.mu)
     assert st == 0 and len(hist) == 2
     for h in hist:

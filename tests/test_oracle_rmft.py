@@ -80,16 +80,17 @@ def test_mu_search_matches_kspace_bisection():
     mu_k = kspace.mu_for_doping(DOP, chi, dlt, T_, TP, J, TEMP, L=L, tol=1e-14)
     th = _uniform_theta(chi, dlt, L * L)
     fn = rmft.exact_rho_fn(L, L, 0, T_, TP, J, TEMP)
-    prm = rmft.Params(doping=DOP, tol_n=1e-12, tol_mu=1e-14, mu_step=0.05, max_evals=80)
-
     def e_fn(m):
         _, rho = fn(th, m)
         nbar, _ = rmft.measure(rho, th)
         return nbar - (1.0 - DOP), None
 
-    for mu0 in (0.0, 3.0):                        # from below and from above
-        mu, _, evals = rmft.solve_mu(e_fn, mu0, prm)
-        assert abs(mu - mu_k) < 1e-9, (mu0, mu, mu_k, evals)
+    for search in ("bisection", "illinois"):
+        prm = rmft.Params(doping=DOP, tol_n=1e-12, tol_mu=1e-14, mu_step=0.05, max_evals=80,
+                          search=search)
+        for mu0 in (0.0, 3.0):                    # from below and from above
+            mu, _, evals = rmft.solve_mu(e_fn, mu0, prm)
+            assert abs(mu - mu_k) < 1e-9, (search, mu0, mu, mu_k, evals)
 
 
 def test_mu_search_budget():
@@ -100,6 +101,22 @@ def test_mu_search_budget():
     prm = rmft.Params(doping=DOP, tol_n=0.0, tol_mu=1e-12, mu_step=0.01, max_evals=100)
     mu, _, evals = rmft.solve_mu(lambda m: (m - 1.0, None), 0.0, prm)
     assert abs(mu - 1.0) <= 1e-12 and evals > 7
+    # false position is exact on a linear e(mu): one step after the bracket
+    prm = rmft.Params(doping=DOP, tol_n=1e-12, tol_mu=0.0, mu_step=0.01, max_evals=100,
+                      search="illinois")
+    mu, _, evals_il = rmft.solve_mu(lambda m: (m - 1.0, None), 0.0, prm)
+    assert abs(mu - 1.0) <= 1e-12 and evals_il == 9    # start, 7 walk steps, 1 secant step
+
+
+@pytest.mark.parametrize("search", ["bisection", "illinois"])
+def test_mu_search_closed_form_root(search):
+    """A smooth monotone e(mu) with a known root: tanh((mu - 1)/0.3) - 0.2."""
+    root = 1.0 + 0.3 * np.arctanh(0.2)
+    prm = rmft.Params(doping=DOP, tol_n=1e-13, tol_mu=0.0, mu_step=0.004, max_evals=200, search=search)
+    for mu0 in (-2.0, 0.9, 3.5):
+        mu, _, evals = rmft.solve_mu(lambda m: (np.tanh((m - 1.0) / 0.3) - 0.2, None), mu0, prm)
+        assert abs(mu - root) < 1e-12, (mu0, mu, evals)
+        assert evals < (40 if search == "illinois" else 80)
 
 
 def test_singlet_spin_estimates_agree():

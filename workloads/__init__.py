@@ -21,9 +21,9 @@ Recipe (every config):
 * n_i = 1 - delta (m_i = 0);
 * ``noise``: uniform(-noise, noise) real noise per nn bond on chi and Delta and
   per site on n; ``complex_noise``: complex noise on every direction instead;
-* ``vortex``: Delta_ij *= prod_v tanh(|r_ij - R_v| / 3) exp(i sum_v arg(r_ij - R_v))
-  with r_ij the bond midpoint, minimum-image displacement, and R_v as in
-  ``vortex_centres``;
+* ``vortex``: Delta_ij *= prod_v tanh(|r_ij - R_v| / core) exp(i sum_v arg(r_ij - R_v))
+  with r_ij the bond midpoint, minimum-image displacement, R_v as in
+  ``vortex_centres`` and core = 3 unless a config sets it;
 * ``pdw``: Delta_ij += pdw * eta_ij [cos(2 pi x_ij / 8) + cos(2 pi y_ij / 8)]
   (eta = +1 on x bonds, -1 on y bonds), and delta_i += pdw [cos(2 pi x_i/8) +
   cos(2 pi y_i/8)], applied before the vortex factor;
@@ -83,6 +83,7 @@ class Config:
     tp: float = TP_HOP
     J: float = J_EX
     chi0: float = 0.2            # seed chi on nearest-neighbour bonds
+    core: float = 3.0            # tanh radius of the vortex seed (lattice constants)
 
     @property
     def N(self) -> int:
@@ -163,7 +164,7 @@ def make_theta(cfg: Config):
             phase = np.zeros(N)
             for (X, Y) in vortex_centres(Lx, Ly, cfg.n_v):
                 ux, uy = _min_image(xm - X, Lx), _min_image(ym - Y, Ly)
-                amp *= np.tanh(np.hypot(ux, uy) / 3.0)
+                amp *= np.tanh(np.hypot(ux, uy) / cfg.core)
                 phase += np.arctan2(uy, ux)
             dlt[d] *= amp * np.exp(1j * phase)
     return n, chi, dlt
