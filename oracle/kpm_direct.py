@@ -17,6 +17,10 @@ Steps, in this order:
 1. D = coefficients of F_M' in the same basis (numpy's Chebyshev derivative);
 2. y_l = sum_m D_m alpha_m with the recursion of App. B (eq. alpha);
 3. rho on the stencil pairs (I, J): (1/a) sum_l w_l conj(r_{l,I}) y_{l,J};
+   the two diagonal entries (i0, i0), (i1, i1) keep their real part (the
+   diagonal of the Hermitian rho is real; for a finite probe set the
+   estimate's imaginary part there is probing noise, and the stencil layout
+   stores those entries as real);
 4. Omega from the moments of the same recursion (eq. F_KPM).
 """
 from __future__ import annotations
@@ -60,4 +64,6 @@ def direct_rho(Hs, a, b, probes, weights, C, Lx, Ly):
         omega += w * float(np.dot(C, mom))
         ys[ell] = y
         rho += w * np.conj(r[I]) * y[J]
+    rho[16] = rho[16].real
+    rho[17] = rho[17].real
     return {"rho": rho / a, "omega": omega, "y": ys}

@@ -5,7 +5,8 @@
 * with the complete set of unit vectors it equals the truncated density
   matrix of dense diagonalisation (O1), (1/a) F_M'(H~)^T;
 * with colored or random Z4 probes it equals (1/a) [F_M'(H~) P]^T, P the
-  weighted probe projector, built from the eigendecomposition;
+  weighted probe projector, built from the eigendecomposition (diagonal
+  entries as their real part, the stencil layout's convention);
 * Omega equals the plain recursion's (O2).
 """
 import numpy as np
@@ -61,6 +62,7 @@ def test_probe_estimate_equals_projector_form(probes):
     Fp = (U * dF[None, :]) @ U.conj().T                     # F_M'(H~)
     P = (R.T * w[None, :]) @ R.conj()                       # sum_l w_l r_l r_l^dag
     ref = builder.stencil_from_dense((Fp @ P).T, cfg.Lx, cfg.Ly) / a
+    ref[16], ref[17] = ref[16].real, ref[17].real       # diagonal stored as real
     assert H.rel_err(out["rho"], ref) < 1e-11
     plain = kpm_plain.plain_kpm(Hs, a, b, R, w, C, cfg.Lx, cfg.Ly, want_grad=False)
     assert abs(out["omega"] - plain["omega"]) < 1e-12 * abs(plain["omega"])
