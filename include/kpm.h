@@ -202,6 +202,26 @@ int kpm_density_matrix(const kpm_lattice* lat, const double* h, const double* ab
                        double* delta_up, double* delta_dn, void* ws, size_t ws_bytes,
                        void* stream);
 
+/* Direct probing estimate of the density matrix: the probe average of App. B
+ * applied to the Chebyshev series of f' = n_F instead of differentiating the
+ * probe-estimated Omega (Weisse et al., Rev. Mod. Phys. 78, 275, for KPM
+ * correlation functions):
+ *   rho_IJ ~= (1/a) sum_l w_l conj(r_{l,I}) [F_M'(H~) r_l]_J,
+ * F_M(x) = sum_m C_m T_m(x) the damped series of kpm_coefficients and F_M' its
+ * exact derivative, sum_k D_k T_k with D from e_{k-1} = e_{k+1} + 2k C_k.
+ * One forward recursion (eq. alpha) with y_l = sum_m D_m alpha_m accumulated
+ * in FP64 every second step; no checkpoints, no adjoint.  For the complete
+ * unit-vector set it equals kpm_grand_potential_grad's rho; for other probes
+ * the two are different estimates of the same matrix.  omega [1] receives
+ * Omega as kpm_grand_potential; rho [19][N] complex (STENCIL layout).
+ * ws: at least kpm_workspace_size(lat, R, M, M, precision) bytes (any ckpt_k
+ * <= M gives a large enough size); the call invalidates the workspace for
+ * kpm_grand_potential_grad.  Device errors are latched as for the recursion. */
+int kpm_density_matrix_direct(const kpm_lattice* lat, const double* h, const double* ab,
+                              const kpm_probes* probes, int32_t M, const double* C,
+                              int32_t precision, double* omega, double* rho, void* ws,
+                              size_t ws_bytes, void* stream);
+
 /* Device status word latched by the last recursion on ws: KPM_OK or
  * KPM_EBOUNDS.  Synchronises `stream`. *status is host memory. */
 int kpm_status_read(const void* ws, int32_t* status, void* stream);

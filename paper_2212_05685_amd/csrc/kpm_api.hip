@@ -29,6 +29,9 @@ hipError_t launch_omega(const InstDev*, int, int, hipStream_t);
 hipError_t launch_rho(const InstDev*, const int2*, int, hipStream_t);
 hipError_t launch_map(int, const double*, double*, double*, double*, double*, double*, double*,
                       hipStream_t);
+hipError_t launch_direct_coef(const InstDev*, int, int, hipStream_t);
+hipError_t launch_direct_acc(bool, const InstDev*, int, long long, int, int, hipStream_t);
+hipError_t launch_rho_direct(const InstDev*, const int2*, int, hipStream_t);
 hipError_t profile_begin(int);
 hipError_t profile_end(double*, int*, double*, int*);
 
@@ -610,6 +613,41 @@ int kpm_density_matrix(const kpm_lattice* lat, const double* h, const double* ab
   if (st != KPM_OK) return st;
   KPM_HIP(launch_map(lat->Lx * lat->Ly, rho, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn,
                      static_cast<hipStream_t>(stream)));
+  return KPM_OK;
+}
+
+int kpm_density_matrix_direct(const kpm_lattice* lat, const double* h, const double* ab,
+                              const kpm_probes* probes, int32_t M, const double* C,
+                              int32_t precision, double* omega, double* rho, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (!C || !omega || !rho) return KPM_EINVAL;
+  Ctx c;
+  // no checkpoints are read: the smallest checkpoint area (interval M) suffices
+  int st = prepare_single(c, lat, h, ab, probes, M, C, precision, std::max<int32_t>(M, 2), ws,
+                          ws_bytes);
+  if (st != KPM_OK) return st;
+  c.inst[0].omega = omega;
+  c.inst[0].rho = reinterpret_cast<double2*>(rho);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_fwd.erase(ws);                       // the adjoint buffers are overwritten below
+  }
+  if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+  const long long records = (long long)c.inst[0].R * c.inst[0].N;
+  hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, c.d_inst, 1, 0);
+  KPM_HIP(hipGetLastError());
+  KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
+  KPM_HIP(launch_direct_coef(c.d_inst, 1, M, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), 0, M, c.k, 0, s));
+  for (int m = 0; m + 1 < M; ++m) {
+    // step m writes alpha_{m+1}; after an even step alpha_m, alpha_{m+1} sit in A[0], A[1]
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, M, c.k, 0, s));
+    if ((m & 1) == 0) KPM_HIP(launch_direct_acc(c.fp32, c.d_inst, 1, records, m, m == 0, s));
+  }
+  if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
+  KPM_HIP(launch_omega(c.d_inst, 1, M, s));
+  KPM_HIP(launch_rho_direct(c.d_inst, c.d_cmap, c.nch(), s));
   return KPM_OK;
 }
 

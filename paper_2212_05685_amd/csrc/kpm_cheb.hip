@@ -855,6 +855,123 @@ __global__ __launch_bounds__(kBlock) void k_map(int N, const double2* __restrict
   }
 }
 
+// ------------------------------------------------- direct probing estimate
+// rho_IJ ~= (1/a) sum_p w_p conj(r_{p,I}) y_{p,J},  y_p = F_M'(H~) r_p
+// = sum_m D_m alpha_{p,m} (the series of f' applied to each probe).  y is an
+// FP64 record per (probe, site) in the adjoint buffers G[0..1], which the
+// direct path does not use (2 FP32 records or 1 FP64 record of space each);
+// D is kept in the first M doubles of musum, which the moment reduction
+// overwrites only after the last accumulation.
+
+// Coefficients of the derivative series: with e_M = e_{M+1} = 0,
+// e_{k-1} = e_{k+1} + 2 k C_k (k = M-1 .. 1), D_0 = e_0 / 2, D_k = e_k.
+__global__ void k_direct_coef(const InstDev* __restrict__ insts, int M) {
+  if (threadIdx.x != 0) return;
+  const InstDev& I = insts[blockIdx.x];
+  double* D = I.musum;
+  double e1 = 0.0, e2 = 0.0;                    // e_{k}, e_{k+1}
+  D[M - 1] = 0.0;
+  for (int k = M - 1; k >= 1; --k) {
+    const double e0 = e2 + 2.0 * (double)k * I.C[k];   // e_{k-1}
+    if (k - 1 >= 1) D[k - 1] = e0;
+    else D[0] = 0.5 * e0;
+    e2 = e1;
+    e1 = e0;
+  }
+}
+
+// y += D_m alpha_m + D_{m+1} alpha_{m+1} for even m (alpha_m in A[0],
+// alpha_{m+1} in A[1]); first: y = that sum.  One record per thread,
+// grid-stride over the R N records of instance blockIdx.y.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_direct_acc(const InstDev* __restrict__ insts, int m,
+                                                       int first) {
+  const InstDev& I = insts[blockIdx.y];
+  const double* D = I.musum;
+  const double d0 = D[m], d1 = D[m + 1];
+  const unsigned total = (unsigned)I.R * (unsigned)I.N;
+  for (unsigned idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
+    const Rec<V> a0 = ld_rec<V>(I.A[0], idx), a1 = ld_rec<V>(I.A[1], idx);
+    Rec<double> y;
+    if (first) {
+      y.c[0] = {0.0, 0.0};
+      y.c[1] = {0.0, 0.0};
+    } else {
+      y = ld_rec<double>(I.G[0], idx);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      y.c[c].x = fma(d0, (double)a0.c[c].x, y.c[c].x);
+      y.c[c].y = fma(d0, (double)a0.c[c].y, y.c[c].y);
+      y.c[c].x = fma(d1, (double)a1.c[c].x, y.c[c].x);
+      y.c[c].y = fma(d1, (double)a1.c[c].y, y.c[c].y);
+    }
+    st_rec<double>(I.G[0], idx, y);
+  }
+}
+
+// One thread per site i: over the probes with a non-zero entry at (i, a),
+// accumulate w conj(r_{(i,a)}) y_J for the stored entries of row (i, a):
+// 4d + 2a + b (J = (i + d, b)), 16 / 18 (a = 0: J = (i, 0), (i, 1)), 17 (a = 1).
+__global__ __launch_bounds__(kBlock) void k_rho_direct(const InstDev* __restrict__ insts,
+                                                       const int2* __restrict__ cmap) {
+  const int2 cm = cmap[blockIdx.x];
+  const InstDev& I = insts[cm.x];
+  const int i = cm.y + threadIdx.x;
+  if (i >= I.N) return;
+  const int Lx = I.Lx, Ly = I.Ly, N = I.N;
+  const int x = i % Lx, y = i / Lx;
+  int nb[4];
+  {
+    const int xp = (x + 1 == Lx) ? 0 : x + 1;
+    const int yp = (y + 1 == Ly) ? 0 : y + 1, ym = (y == 0) ? Ly - 1 : y - 1;
+    nb[0] = y * Lx + xp;
+    nb[1] = yp * Lx + x;
+    nb[2] = yp * Lx + xp;
+    nb[3] = ym * Lx + xp;
+  }
+  Cx<double> acc[kNent];
+#pragma unroll
+  for (int e = 0; e < kNent; ++e) acc[e] = {0.0, 0.0};
+  const unsigned char* code = I.pcode;
+  for (int p = 0; p < I.R; ++p) {
+    const unsigned byte = code[(size_t)p * N + i];
+    if (byte == 0u) continue;
+    const double w = I.pw[p];
+    const long long base = (long long)p * N;
+    const Rec<double> yi = ld_rec<double>(I.G[0], base + i);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const unsigned nib = (byte >> (4 * a)) & 15u;
+      if (!(nib & 8u)) continue;
+      // w conj(i^k)
+      const Cx<double> r = phase_times<double>((int)(nib & 3u), w);
+      const Cx<double> rc = {r.x, -r.y};
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const Rec<double> yj = ld_rec<double>(I.G[0], base + nb[d]);
+        cfma(acc[4 * d + 2 * a + 0], rc, yj.c[0]);
+        cfma(acc[4 * d + 2 * a + 1], rc, yj.c[1]);
+      }
+      if (a == 0) {
+        cfma(acc[16], rc, yi.c[0]);
+        cfma(acc[18], rc, yi.c[1]);
+      } else {
+        cfma(acc[17], rc, yi.c[1]);
+      }
+    }
+  }
+  const double scale = 1.0 / I.ab[0];
+  bool bad = false;
+  for (int e = 0; e < kNent; ++e) {
+    double sx = acc[e].x * scale, sy = acc[e].y * scale;
+    if (e == 16 || e == 17) sy = 0.0;
+    bad = bad || !isfinite(sx) || !isfinite(sy);
+    I.rho[(long long)e * N + i] = make_double2(sx, sy);
+  }
+  if (bad && I.status) *I.status = -4;
+}
+
 // ------------------------------------------------------------- profiling
 // When enabled, one in `every` forward-step and adjoint-step launches carries
 // a pair of HIP events recorded by the dispatch itself (hipExtLaunchKernelGGL),
@@ -1004,6 +1121,27 @@ hipError_t launch_omega(const InstDev* insts, int ninst, int M, hipStream_t s) {
 
 hipError_t launch_rho(const InstDev* insts, const int2* cmap, int nchunks, hipStream_t s) {
   hipLaunchKernelGGL(k_rho, dim3(nchunks), dim3(kBlock), 0, s, insts, cmap);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_coef(const InstDev* insts, int ninst, int M, hipStream_t s) {
+  hipLaunchKernelGGL(k_direct_coef, dim3(ninst), dim3(64), 0, s, insts, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_acc(bool fp32, const InstDev* insts, int ninst, long long records, int m,
+                             int first, hipStream_t s) {
+  const long long want = (records + kBlock - 1) / kBlock;
+  dim3 grid((unsigned)std::min<long long>(want, 8192), ninst);
+  if (fp32)
+    hipLaunchKernelGGL(k_direct_acc<float>, grid, dim3(kBlock), 0, s, insts, m, first);
+  else
+    hipLaunchKernelGGL(k_direct_acc<double>, grid, dim3(kBlock), 0, s, insts, m, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho_direct(const InstDev* insts, const int2* cmap, int nchunks, hipStream_t s) {
+  hipLaunchKernelGGL(k_rho_direct, dim3(nchunks), dim3(kBlock), 0, s, insts, cmap);
   return hipGetLastError();
 }
 

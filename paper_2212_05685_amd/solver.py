@@ -99,6 +99,14 @@ class KPMProblem:
                                out["chi_dn"], out["delta_up"], out["delta_dn"], self.workspace())
         return out
 
+    def density_matrix_direct(self, h, ab, C):
+        """(omega, rho) by the direct probing estimate (forward recursion only)."""
+        omega = self.zeros(1, dtype=torch.float64)
+        rho = self.zeros(kpm.NENT, self.N)
+        kpm.kpm_density_matrix_direct(self.lat, h, ab, self.probes, self.M, C, self.precision, omega,
+                                      rho, self.workspace())
+        return omega, rho
+
     def status(self) -> int:
         return kpm.kpm_status_read(self.workspace())
 

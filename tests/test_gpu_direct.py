@@ -1,0 +1,97 @@
+"""GPU parity of the direct probing estimate of rho (kpm_density_matrix_direct)
+against the oracle (oracle/kpm_direct.py), through the C ABI.
+
+* small lattices, colored + dense Z4 probes, M from 2 (one recursion step,
+  one accumulation) to 257 (odd: the last step's alpha has D = 0): FP64 to
+  1e-10 relative, FP32 recursion to 1e-5;
+* the complete unit-vector set: equal to the truncated density matrix of
+  dense diagonalisation (O1) to 1e-10;
+* 100 x 100 (the benchmark workload, M = 4096, 256 colored probes): every
+  density-matrix row (i, a) with (i, a) in one colour class is a sum over the
+  two probes (one per draw) that are non-zero there, so the oracle computes
+  those rows exactly from two probes; FP64 to 1e-10, FP32 to 1e-5;
+* the call invalidates the workspace for the adjoint.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import builder, kpm_direct
+from tests import helpers as H
+from tests.gpu_helpers import dev, host, problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+TOL32 = 1e-5
+
+
+def _cfg(Lx=17, Ly=19, nv=2, M=48, probes=None):
+    probes = probes or (wl.ProbeSpec("colored_z4", 1, 77, 4, 3, 1, 0, 1.0),
+                        wl.ProbeSpec("dense_z4", 3, 99, weight=1 / 3))
+    return wl.Config("d", Lx, Ly, nv, 0.13, M, tuple(probes), "fp64", vortex=nv > 0, complex_noise=0.02)
+
+
+def _gpu_direct(cfg, st, a, b, C, prec):
+    pb = problem(cfg, precision=prec)
+    h = dev(st)
+    ab = dev(np.array([a, b]))
+    om, rho = pb.density_matrix_direct(h, ab, dev(C))
+    assert pb.status() == 0
+    return float(host(om)[0]), host(rho)
+
+
+@pytest.mark.parametrize("M", [2, 3, 48, 257])
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL), ("fp32", TOL32)])
+def test_direct_against_oracle(M, prec, tol):
+    cfg = _cfg(M=M)
+    st, a, b, C = H.oracle_inputs(cfg)
+    R, w = H.probe_matrix(cfg)
+    Hs = builder.sparse_from_stencil(st, cfg.Lx, cfg.Ly)
+    ref = kpm_direct.direct_rho(Hs, a, b, R, w, C, cfg.Lx, cfg.Ly)
+    om, rho = _gpu_direct(cfg, st, a, b, C, prec)
+    assert abs(om - ref["omega"]) < tol * abs(ref["omega"])
+    assert H.rel_err(rho, ref["rho"]) < tol
+
+
+def test_direct_unit_probes_equal_dense_truncated():
+    cfg = wl.C1()
+    st, a, b, C = H.oracle_inputs(cfg)
+    om_ref, rho_ref = H.dense_truncated(cfg, st, a, b, C)
+    om, rho = _gpu_direct(cfg, st, a, b, C, "fp64")
+    assert abs(om - om_ref) < TOL * abs(om_ref)
+    assert H.rel_err(rho, rho_ref) < TOL
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL), ("fp32", TOL32)])
+def test_direct_fullsize_colour_class(prec, tol):
+    cfg = wl.C5(prec)
+    st, a, b, C = H.oracle_inputs(cfg)
+    R, w = H.probe_matrix(cfg)
+    x0, y0, comp = 3, 5, 0
+    I0 = 2 * (y0 * cfg.Lx + x0) + comp
+    sel = np.nonzero(R[:, I0])[0]
+    assert len(sel) == 2                       # one probe per draw
+    rows = np.nonzero(R[sel[0]])[0]            # the colour class, component comp
+    assert np.all(rows % 2 == comp) and np.array_equal(rows, np.nonzero(R[sel[1]])[0])
+    Hs = builder.sparse_from_stencil(st, cfg.Lx, cfg.Ly)
+    ref = kpm_direct.direct_rho(Hs, a, b, R[sel], w[sel], C, cfg.Lx, cfg.Ly)["rho"]
+    _, rho = _gpu_direct(cfg, st, a, b, C, prec)
+    sites = rows // 2
+    ents = [4 * d + 2 * comp + bb for d in range(4) for bb in range(2)] + ([16, 18] if comp == 0 else [17])
+    got, exp = rho[ents][:, sites], ref[ents][:, sites]
+    assert np.max(np.abs(got - exp)) < tol * np.max(np.abs(exp))
+
+
+def test_direct_invalidates_adjoint():
+    from paper_2212_05685_amd import kpm
+
+    cfg = _cfg(M=16)
+    st, a, b, C = H.oracle_inputs(cfg)
+    pb = problem(cfg, precision="fp64")
+    h, ab, Cd = dev(st), dev(np.array([a, b])), dev(C)
+    pb.grand_potential(h, ab, Cd)
+    pb.density_matrix_direct(h, ab, Cd)
+    with pytest.raises(kpm.KpmError):
+        pb.grand_potential_grad(h, ab, Cd)
