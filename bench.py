@@ -335,6 +335,45 @@ def rmft_form(iters: int, warmup: int):
     }
 
 
+def direct_form(steps: int, prob, th, dt_adjoint):
+    """The same 100x100 step with rho from the direct probing estimate
+    (forward recursion with the f' series accumulated per probe) instead of
+    the adjoint; the two are different estimates of the same matrix."""
+    import numpy as np
+    import torch
+
+    n, chi, dlt = th
+
+    def step():
+        h = prob.build_H(n, chi, dlt)
+        ab = prob.bounds(h)
+        C = prob.coefficients(ab)
+        om, rho = prob.density_matrix_direct(h, ab, C)
+        grads = prob.build_H_vjp(n, chi, dlt, rho)
+        return om, rho, grads, (h, ab, C)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        om, rho, grads, (h, ab, C) = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    if prob.status() != 0:
+        raise RuntimeError(f"device status {prob.status()}")
+    out = prob.density_matrix(h, ab, C)
+    r_dir, r_adj = rho.cpu().numpy(), out["rho"].cpu().numpy()
+    log(f"direct form: {dt * 1e3:.1f} ms/step")
+    return {
+        "ms_per_step": dt * 1e3,
+        "speedup_over_adjoint_form": dt_adjoint / dt,
+        "omega_rel_diff_vs_adjoint_form": abs(float(om.item()) - float(out["omega"].item()))
+                                          / abs(float(out["omega"].item())),
+        "rho_max_rel_diff_vs_adjoint_form": float(np.max(np.abs(r_dir - r_adj)) / np.max(np.abs(r_adj))),
+        "accumulation_bytes_per_launch": 96 * prob.R * prob.N,
+    }
+
+
 def cpu_baseline(cfg, quiet=False):
     """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
     probe of the same workload, single thread."""
@@ -376,6 +415,7 @@ def main():
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--no-batched-form", action="store_true")
     ap.add_argument("--no-rmft-form", action="store_true")
+    ap.add_argument("--no-direct-form", action="store_true")
     ap.add_argument("--only-rmft-form", action="store_true",
                     help="run only the self-consistent iteration timing and print its JSON (profiling)")
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -478,6 +518,9 @@ def main():
         },
         "hbm_GBs_algorithmic_whole_step": ((M - 1) * fwd_bytes + (M - 2) * adj_bytes) / dt / 1e9,
     }
+
+    if not args.no_direct_form and not args.moments:
+        result["direct_form"] = direct_form(args.steps, prob, th, dt)
 
     if not args.no_fp64_form:
         del prob
