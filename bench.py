@@ -374,6 +374,36 @@ def direct_form(steps: int, prob, th, dt_adjoint):
     }
 
 
+def doubling_form(steps: int, prob, th):
+    """Omega alone on the 100x100 workload: the forward recursion of
+    kpm_grand_potential (M - 1 steps) against moment doubling (M/2 steps)."""
+    import torch
+
+    n, chi, dlt = th
+    h = prob.build_H(n, chi, dlt)
+    ab = prob.bounds(h)
+    C = prob.coefficients(ab)
+    res = {}
+    for name, fn in (("forward", lambda: prob.grand_potential(h, ab, C)),
+                     ("doubling", lambda: prob.moments_doubling(h, ab, C)[0])):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            om = fn()
+        torch.cuda.synchronize()
+        res[name] = ((time.perf_counter() - t0) / steps, float(om.item()))
+    if prob.status() != 0:
+        raise RuntimeError(f"device status {prob.status()}")
+    log(f"omega only: forward {res['forward'][0] * 1e3:.1f} ms, doubling {res['doubling'][0] * 1e3:.1f} ms")
+    return {
+        "ms_omega_forward": res["forward"][0] * 1e3,
+        "ms_omega_doubling": res["doubling"][0] * 1e3,
+        "speedup_doubling": res["forward"][0] / res["doubling"][0],
+        "omega_rel_diff": abs(res["doubling"][1] - res["forward"][1]) / abs(res["forward"][1]),
+    }
+
+
 def cpu_baseline(cfg, quiet=False):
     """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
     probe of the same workload, single thread."""
@@ -521,6 +551,7 @@ def main():
 
     if not args.no_direct_form and not args.moments:
         result["direct_form"] = direct_form(args.steps, prob, th, dt)
+        result["doubling_form"] = doubling_form(args.steps, prob, th)
 
     if not args.no_fp64_form:
         del prob

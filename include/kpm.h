@@ -222,6 +222,23 @@ int kpm_density_matrix_direct(const kpm_lattice* lat, const double* h, const dou
                               int32_t precision, double* omega, double* rho, void* ws,
                               size_t ws_bytes, void* stream);
 
+/* Chebyshev moments by moment doubling (Weisse et al., Rev. Mod. Phys. 78,
+ * 275): with T_{2j} = 2 T_j^2 - T_0 and T_{2j+1} = 2 T_{j+1} T_j - T_1 and
+ * T_j(H~) Hermitian,
+ *   mu_{2j}   = 2 alpha_j^dag alpha_j - mu_0,
+ *   mu_{2j+1} = 2 Re(alpha_{j+1}^dag alpha_j) - mu_1,
+ * so the recursion of App. B (eq. alpha) runs to alpha_{M/2} only: half the
+ * steps of kpm_moments for the same M moments.  The two sums per step are
+ * reduced inside the forward step in FP64.  mu: [R][M] doubles or NULL;
+ * with C (kpm_coefficients) and omega both given, Omega as kpm_grand_potential;
+ * at least one of mu, omega.  ws: as kpm_density_matrix_direct; the call
+ * invalidates the workspace for kpm_grand_potential_grad.  In FP32 the
+ * doubled moments carry the rounding of the squared norms (about twice the
+ * relative error of the direct moments). */
+int kpm_moments_doubling(const kpm_lattice* lat, const double* h, const double* ab,
+                         const kpm_probes* probes, int32_t M, const double* C, int32_t precision,
+                         double* omega, double* mu, void* ws, size_t ws_bytes, void* stream);
+
 /* Device status word latched by the last recursion on ws: KPM_OK or
  * KPM_EBOUNDS.  Synchronises `stream`. *status is host memory. */
 int kpm_status_read(const void* ws, int32_t* status, void* stream);

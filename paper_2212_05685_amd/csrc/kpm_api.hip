@@ -30,6 +30,7 @@ hipError_t launch_rho(const InstDev*, const int2*, int, hipStream_t);
 hipError_t launch_map(int, const double*, double*, double*, double*, double*, double*, double*,
                       hipStream_t);
 hipError_t launch_direct_coef(const InstDev*, int, int, hipStream_t);
+hipError_t launch_mom_double(const InstDev*, int, int, int, double*, hipStream_t);
 hipError_t launch_direct_acc(bool, const InstDev*, int, long long, int, int, hipStream_t);
 hipError_t launch_rho_direct(const InstDev*, const int2*, int, hipStream_t);
 hipError_t profile_begin(int);
@@ -648,6 +649,34 @@ int kpm_density_matrix_direct(const kpm_lattice* lat, const double* h, const dou
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_omega(c.d_inst, 1, M, s));
   KPM_HIP(launch_rho_direct(c.d_inst, c.d_cmap, c.nch(), s));
+  return KPM_OK;
+}
+
+int kpm_moments_doubling(const kpm_lattice* lat, const double* h, const double* ab,
+                         const kpm_probes* probes, int32_t M, const double* C, int32_t precision,
+                         double* omega, double* mu, void* ws, size_t ws_bytes, void* stream) {
+  if ((C == nullptr) != (omega == nullptr) || (!mu && !omega)) return KPM_EINVAL;
+  Ctx c;
+  int st = prepare_single(c, lat, h, ab, probes, M, C, precision, std::max<int32_t>(M, 2), ws,
+                          ws_bytes);
+  if (st != KPM_OK) return st;
+  c.inst[0].omega = omega;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_fwd.erase(ws);
+  }
+  if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+  hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, c.d_inst, 1, 0);
+  KPM_HIP(hipGetLastError());
+  KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), 0, M, c.k, 0, s));
+  // alpha_1 .. alpha_{M/2}: every moment slot below M is then written
+  for (int m = 0; m < M / 2; ++m)
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, 4, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, M, c.k, 0, s));
+  if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
+  KPM_HIP(launch_mom_double(c.d_inst, 1, c.inst[0].R * M, M, mu, s));
+  if (omega) KPM_HIP(launch_omega(c.d_inst, 1, M, s));
   return KPM_OK;
 }
 

@@ -425,7 +425,11 @@ constexpr int FPD = 2;
 // alpha_{m+1} into A[(m+1)&1] (holding alpha_{m-1}) from alpha_m in A[m&1];
 // m == 0: alpha_1 = H~ alpha_0.  Moment partial of alpha_{m+1} per (probe, tile).
 // CK: this step's alpha_{m+1} is also a checkpoint.
-template <typename V, int PW, bool CK>
+// DBL (moment doubling, k_ckpt then carries M): instead of r^dag alpha_{m+1},
+// the partials of alpha_{m+1}^dag alpha_{m+1} and Re(alpha_{m+1}^dag alpha_m)
+// go to moment slots 2(m+1) and 2m+1 (when below M), from which
+// mu_{2j} = 2 alpha_j^dag alpha_j - mu_0 and mu_{2j+1} = 2 Re(alpha_{j+1}^dag alpha_j) - mu_1.
+template <typename V, int PW, bool CK, bool DBL = false>
 __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
                                          const int4* __restrict__ tmap, Sched sc, int m,
                                          int k_ckpt) {
@@ -449,6 +453,10 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
                    : nullptr;
   // global (not generic) pointer: a generic store would be a FLAT access
   GPtrW<double> mom = (GPtrW<double>)(I.mom) + ((long long)mo * I.nchunk + tm.w) * I.R;
+  const int Mtot = k_ckpt;                                  // DBL only
+  GPtrW<double> momS = (GPtrW<double>)(I.mom) + ((long long)(2 * mo) * I.nchunk + tm.w) * I.R;
+  GPtrW<double> momX = (GPtrW<double>)(I.mom) + ((long long)(2 * m + 1) * I.nchunk + tm.w) * I.R;
+  double momx = 0.0;                                        // DBL: Re(alpha_{m+1}^dag alpha_m)
   const int pend = min(pbase + PW, I.R);
   // Every load and store of the probe loop is issued unconditionally (loads
   // past the wave's last probe re-read that probe; lanes outside the lattice
@@ -493,12 +501,33 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
       const size_t own = (size_t)((unsigned)(p * N) + L.site) * RB + (unsigned)L.a * CB;
       st_cx<V>(store_addr(live, (const char*)nxt + own, sink_own), 0u, o);
       if (CK) st_cx<V>(store_addr(live, (const char*)ckbuf + own, sink_own), 0u, o);
-      const double v = wave_moment(re_conj_phase<V>(k, o), k >= 0);
-      if (lane == p - pbase) momv = v;
+      if constexpr (DBL) {
+        // own alpha_m component from the staged record; lanes outside the
+        // lattice and repeated probes contribute nothing
+        const Cx<V> am = lds_own<V>(lds + L.hoff[0], L.a);
+        const double ox = (double)o.x, oy = (double)o.y;
+        const double sv = live ? fma(ox, ox, oy * oy) : 0.0;
+        const double xv = live ? fma(ox, (double)am.x, oy * (double)am.y) : 0.0;
+        const double ssum = wave_sum(sv), xsum = wave_sum(xv);
+        if (lane == p - pbase) {
+          momv = ssum;
+          momx = xsum;
+        }
+      } else {
+        const double v = wave_moment(re_conj_phase<V>(k, o), k >= 0);
+        if (lane == p - pbase) momv = v;
+      }
       __builtin_amdgcn_wave_barrier();
     }
   }
-  if (lane < pend - pbase) mom[pbase + lane] = momv;
+  if constexpr (DBL) {
+    if (lane < pend - pbase) {
+      if (2 * m + 1 < Mtot) momX[pbase + lane] = momx;
+      if (2 * mo < Mtot) momS[pbase + lane] = momv;
+    }
+  } else {
+    if (lane < pend - pbase) mom[pbase + lane] = momv;
+  }
 }
 
 // ------------------------------------------------------------- adjoint
@@ -731,6 +760,11 @@ template <int PW> struct StepKernels<float, PW> {
            int k_ckpt) {
     fwd_body<float, PW, CK>(insts, tmap, sc, m, k_ckpt);
   }
+  static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+  void fwd2(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
+            int M) {
+    fwd_body<float, PW, false, true>(insts, tmap, sc, m, M);
+  }
   template <bool TAIL>
   static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
   void adj(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
@@ -744,6 +778,11 @@ template <int PW> struct StepKernels<double, PW> {
   void fwd(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
            int k_ckpt) {
     fwd_body<double, PW, CK>(insts, tmap, sc, m, k_ckpt);
+  }
+  static __global__ __launch_bounds__(kBlock)
+  void fwd2(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
+            int M) {
+    fwd_body<double, PW, false, true>(insts, tmap, sc, m, M);
   }
   template <bool TAIL>
   static __global__ __launch_bounds__(kBlock)
@@ -768,6 +807,21 @@ __global__ __launch_bounds__(kBlock) void k_mom_reduce(const InstDev* __restrict
   for (int c = 0; c < I.nchunk; ++c) s += src[(long long)c * I.R];
   I.musum[(long long)p * M + m] = s;
   if (mu_user) mu_user[(long long)p * M + m] = s;
+}
+
+// Moment doubling: slots m >= 2 of musum hold alpha_j^dag alpha_j (m = 2j) and
+// Re(alpha_{j+1}^dag alpha_j) (m = 2j + 1); slots 0 and 1 are mu_0 and mu_1.
+// mu_m = 2 musum_m - mu_{m & 1} (T_{2j} = 2 T_j^2 - 1, T_{2j+1} = 2 T_{j+1} T_j - T_1).
+__global__ __launch_bounds__(kBlock) void k_mom_double(const InstDev* __restrict__ insts, int M,
+                                                       double* __restrict__ mu_user) {
+  const InstDev& I = insts[blockIdx.y];
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (long long)I.R * M) return;
+  const int p = (int)(t / M), m = (int)(t - (long long)p * M);
+  double* row = I.musum + (long long)p * M;
+  const double v = m >= 2 ? 2.0 * row[m] - row[m & 1] : row[m];
+  if (m >= 2) row[m] = v;
+  if (mu_user) mu_user[(long long)p * M + m] = v;
 }
 
 // Omega = sum_m C_m sum_p w_p mu_{p,m}: one block per (instance, 256 m),
@@ -1071,6 +1125,9 @@ static hipError_t launch_all(int which, const InstDev* insts, const int4* tmap, 
     case 2:
       hipLaunchKernelGGL((k_adj_init<V, PW>), grid, block, 0, s, insts, tmap, sc, M);
       break;
+    case 4:
+      hipLaunchKernelGGL((StepKernels<V, PW>::fwd2), grid, block, 0, s, insts, tmap, sc, m, M);
+      break;
     case 3: {
       auto kern = flag ? StepKernels<V, PW>::template adj<true> : StepKernels<V, PW>::template adj<false>;
       if (timed)
@@ -1121,6 +1178,13 @@ hipError_t launch_omega(const InstDev* insts, int ninst, int M, hipStream_t s) {
 
 hipError_t launch_rho(const InstDev* insts, const int2* cmap, int nchunks, hipStream_t s) {
   hipLaunchKernelGGL(k_rho, dim3(nchunks), dim3(kBlock), 0, s, insts, cmap);
+  return hipGetLastError();
+}
+
+hipError_t launch_mom_double(const InstDev* insts, int ninst, int maxRM, int M, double* mu_user,
+                             hipStream_t s) {
+  dim3 grid((maxRM + kBlock - 1) / kBlock, ninst);
+  hipLaunchKernelGGL(k_mom_double, grid, dim3(kBlock), 0, s, insts, M, mu_user);
   return hipGetLastError();
 }
 

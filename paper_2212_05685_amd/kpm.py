@@ -36,7 +36,7 @@ EXPORTS = (
     "kpm_density_matrix", "kpm_status_read", "kpm_batch_create", "kpm_batch_energy_grad",
     "kpm_batch_destroy", "kpm_set_probe_block", "kpm_profile_begin", "kpm_profile_end",
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
-    "kpm_density_matrix_direct",
+    "kpm_density_matrix_direct", "kpm_moments_doubling",
 )
 
 
@@ -96,6 +96,8 @@ def _load():
         "kpm_density_matrix": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P, c_int32,
                                          c_int32, P, P, P, P, P, P, P, P, P, c_size_t, P]),
         "kpm_status_read": (c_int32, [P, POINTER(c_int32), P]),
+        "kpm_moments_doubling": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P, c_int32,
+                                           P, P, P, c_size_t, P]),
         "kpm_density_matrix_direct": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P,
                                                 c_int32, P, P, P, c_size_t, P]),
         "kpm_batch_create": (c_int32, [c_int32, POINTER(Lattice), POINTER(Probes), c_int32, c_int32,
@@ -287,6 +289,16 @@ def kpm_density_matrix_direct(lat, h, ab, probes, M, C, precision, omega, rho, w
         ctypes.byref(_probes(probes)), M, _ptr(C, torch.float64, M, "C"), precision,
         _ptr(omega, torch.float64, 1, "omega"), _ptr(rho, torch.complex128, NENT * N, "rho"),
         _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream)), "kpm_density_matrix_direct")
+
+
+def kpm_moments_doubling(lat, h, ab, probes, M, C, precision, omega, mu, ws, stream=None):
+    N = lat.Lx * lat.Ly
+    R = kpm_probe_count(lat, probes)
+    _check(_lib.kpm_moments_doubling(
+        ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"), _ptr(ab, torch.float64, 2, "ab"),
+        ctypes.byref(_probes(probes)), M, _ptr(C, torch.float64, M, "C"), precision,
+        _ptr(omega, torch.float64, 1, "omega"), _ptr(mu, torch.float64, R * M, "mu"),
+        _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream)), "kpm_moments_doubling")
 
 
 def kpm_status_read(ws, stream=None) -> int:

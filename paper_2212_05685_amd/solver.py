@@ -107,6 +107,14 @@ class KPMProblem:
                                       rho, self.workspace())
         return omega, rho
 
+    def moments_doubling(self, h, ab, C=None):
+        """(omega or None, mu [R][M]) from half the recursion (moment doubling)."""
+        mu = self.zeros(self.R, self.M, dtype=torch.float64)
+        omega = self.zeros(1, dtype=torch.float64) if C is not None else None
+        kpm.kpm_moments_doubling(self.lat, h, ab, self.probes, self.M, C, self.precision, omega, mu,
+                                 self.workspace())
+        return omega, mu
+
     def status(self) -> int:
         return kpm.kpm_status_read(self.workspace())
 

@@ -10,7 +10,11 @@ against the oracle (oracle/kpm_direct.py), through the C ABI.
   density-matrix row (i, a) with (i, a) in one colour class is a sum over the
   two probes (one per draw) that are non-zero there, so the oracle computes
   those rows exactly from two probes; FP64 to 1e-10, FP32 to 1e-5;
-* the call invalidates the workspace for the adjoint.
+* the call invalidates the workspace for the adjoint;
+* moment doubling (kpm_moments_doubling): the M moments from M/2 steps
+  against the oracle's plain moments, small lattices for several M and two
+  sampled probes at 100 x 100 (FP32: twice the recursion tolerance, the
+  squared norms carry twice the relative rounding).
 """
 import numpy as np
 import pytest
@@ -120,3 +124,33 @@ def test_probe_estimators_against_exact():
     print("max |rho - rho_exact| / max |rho_exact| at R = 128:", errs)
     for est in ("direct", "adjoint"):
         assert errs[("colored", est)] < 0.5 * errs[("random", est)]
+
+
+@pytest.mark.parametrize("M", [2, 3, 64, 257])
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL), ("fp32", 2 * TOL32)])
+def test_moments_doubling_against_oracle(M, prec, tol):
+    """kpm_moments_doubling (M/2 steps) against the oracle's plain moments and
+    Omega (M - 1 steps, O2); tolerance relative to mu_0."""
+    cfg = _cfg(M=M)
+    st, a, b, C = H.oracle_inputs(cfg)
+    ref = H.plain(cfg, st, a, b, C, want_grad=False)
+    pb = problem(cfg, precision=prec)
+    om, mu = pb.moments_doubling(dev(st), dev(np.array([a, b])), dev(C))
+    assert pb.status() == 0
+    mu = host(mu)
+    assert np.max(np.abs(mu - ref["mu"])) < tol * np.max(np.abs(ref["mu"]))
+    assert abs(float(host(om)[0]) - ref["omega"]) < tol * abs(ref["omega"])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL), ("fp32", 2 * TOL32)])
+def test_moments_doubling_fullsize_sampled(prec, tol):
+    """100 x 100, M = 4096: the doubled moments of two sampled probes against
+    the oracle's recursion on those probes."""
+    cfg = wl.C5(prec)
+    st, a, b, C = H.oracle_inputs(cfg)
+    sub = np.array([7, 200])
+    ref = H.plain(cfg, st, a, b, C, want_grad=False, subset=sub)
+    pb = problem(cfg, precision=prec)
+    _, mu = pb.moments_doubling(dev(st), dev(np.array([a, b])), None)
+    mu = host(mu)[sub]
+    assert np.max(np.abs(mu - ref["mu"])) < tol * np.max(np.abs(ref["mu"]))

@@ -66,3 +66,28 @@ def test_probe_estimate_equals_projector_form(probes):
     assert H.rel_err(out["rho"], ref) < 1e-11
     plain = kpm_plain.plain_kpm(Hs, a, b, R, w, C, cfg.Lx, cfg.Ly, want_grad=False)
     assert abs(out["omega"] - plain["omega"]) < 1e-12 * abs(plain["omega"])
+
+
+def test_moment_doubling_identity():
+    """The identities used by kpm_moments_doubling, checked on a random
+    Hermitian matrix with spectrum in (-1, 1) through its eigendecomposition:
+    r^dag T_{2j} r = 2 |T_j r|^2 - r^dag r and
+    r^dag T_{2j+1} r = 2 Re((T_{j+1} r)^dag T_j r) - r^dag T_1 r."""
+    rng = np.random.default_rng(9)
+    n = 24
+    A = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    Hm = (A + A.conj().T) / 2
+    E, U = np.linalg.eigh(Hm)
+    Hm = Hm / (1.05 * np.max(np.abs(E)))
+    E, U = np.linalg.eigh(Hm)
+    th = np.arccos(E)
+    r = np.exp(0.5j * np.pi * rng.integers(0, 4, n))
+
+    def T(j):
+        return (U * np.cos(j * th)[None, :]) @ U.conj().T
+
+    mu = [np.vdot(r, T(m) @ r).real for m in range(20)]
+    for j in range(1, 10):
+        a_j, a_j1 = T(j) @ r, T(j + 1) @ r
+        assert abs(2 * np.vdot(a_j, a_j).real - mu[0] - mu[2 * j]) < 1e-12 * mu[0]
+        assert abs(2 * np.vdot(a_j1, a_j).real - mu[1] - mu[2 * j + 1]) < 1e-12 * mu[0]
