@@ -257,8 +257,9 @@ def rmft_form(iters: int, warmup: int):
     colored probes, FP32 recursion): every iteration runs the chemical-
     potential search (density-matrix evaluations) and the mixing update.
     After `warmup` iterations, the same state is iterated `iters` times with
-    each search; the fused adjoint kernel is timed live during the Illinois
-    run, and the oracle's cost per evaluation is sampled on one probe."""
+    each search, and with the Illinois search on the direct estimate of rho;
+    the fused adjoint kernel is timed live during the Illinois run, and the
+    oracle's cost per evaluation is sampled on one probe."""
     import torch
     from paper_2212_05685_amd import kpm
     import workloads as wl
@@ -267,9 +268,9 @@ def rmft_form(iters: int, warmup: int):
     prob, th = make_problem(cfg, "fp32")
     n, chi, dlt = th
 
-    def params(search):
+    def params(search, estimator=kpm.KPM_RMFT_ADJOINT):
         return kpm.rmft_params(cfg.doping, mix=0.1, tol_n=1e-5, tol_mu=1e-9, mu_step=0.004,
-                               max_evals=60, search=search)
+                               max_evals=60, search=search, estimator=estimator)
 
     mu_w, _, st = prob.rmft_iterate(n, chi, dlt, cfg.mu, params(kpm.KPM_RMFT_ILLINOIS), warmup)
     if st != kpm.KPM_OK:
@@ -278,13 +279,15 @@ def rmft_form(iters: int, warmup: int):
     log(f"rmft warmup {warmup} iterations done, mu = {mu_w:.6f}")
     out = {}
     prof = None
-    for name, search in (("illinois", kpm.KPM_RMFT_ILLINOIS), ("bisection", kpm.KPM_RMFT_BISECTION)):
+    for name, search, est in (("illinois", kpm.KPM_RMFT_ILLINOIS, kpm.KPM_RMFT_ADJOINT),
+                              ("bisection", kpm.KPM_RMFT_BISECTION, kpm.KPM_RMFT_ADJOINT),
+                              ("illinois_direct", kpm.KPM_RMFT_ILLINOIS, kpm.KPM_RMFT_DIRECT)):
         n2, chi2, dlt2 = n.clone(), chi.clone(), dlt.clone()
         torch.cuda.synchronize()
         if name == "illinois":
             kpm.kpm_profile_begin(4)
         t0 = time.perf_counter()
-        mu, hist, st = prob.rmft_iterate(n2, chi2, dlt2, mu_w, params(search), iters)
+        mu, hist, st = prob.rmft_iterate(n2, chi2, dlt2, mu_w, params(search, est), iters)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         if name == "illinois":
@@ -317,6 +320,7 @@ def rmft_form(iters: int, warmup: int):
         "ms_per_density_matrix_evaluation": ill["ms_per_density_matrix_evaluation"],
         "search": out,
         "speedup_illinois_over_bisection": out["bisection"]["s_per_iteration"] / ill["s_per_iteration"],
+        "speedup_direct_estimate": ill["s_per_iteration"] / out["illinois_direct"]["s_per_iteration"],
         "roofline": {
             "kernel": "k_adj (fused adjoint step) at 48x96, R=128",
             "bound": "hbm",

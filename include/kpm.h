@@ -300,6 +300,7 @@ int kpm_rmft_update(const kpm_lattice* lat, const double* rho, double mix, doubl
                     double* chi, double* delta, double* stats, void* stream);
 
 enum { KPM_RMFT_BISECTION = 0, KPM_RMFT_ILLINOIS = 1 };   /* mu search inside the bracket */
+enum { KPM_RMFT_ADJOINT = 0, KPM_RMFT_DIRECT = 1 };       /* rho of an evaluation           */
 
 typedef struct {
   double doping;      /* target hole density: (1/N) sum_i n_i = 1 - doping, 0 < doping < 1 */
@@ -311,7 +312,8 @@ typedef struct {
   int32_t max_evals;  /* density-matrix evaluations allowed per iteration (>= 1)      */
   int32_t coef_K;     /* quadrature points of kpm_coefficients (0 = default)          */
   int32_t search;     /* KPM_RMFT_BISECTION or KPM_RMFT_ILLINOIS                      */
-  int32_t pad;
+  int32_t estimator;  /* KPM_RMFT_ADJOINT (kpm_grand_potential + _grad) or
+                         KPM_RMFT_DIRECT (kpm_density_matrix_direct)                 */
 } kpm_rmft_params;
 
 typedef struct {      /* one completed iteration (host memory)                        */
@@ -331,7 +333,8 @@ size_t kpm_rmft_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int
 /* Up to n_iter self-consistency iterations.  One iteration, with theta fixed:
  * an evaluation at mu builds h(theta, mu) (kpm_build_H with model->mu
  * replaced), rescales it (kpm_bounds), expands f (kpm_coefficients with T and
- * coef_K) and runs kpm_grand_potential + kpm_grand_potential_grad for rho,
+ * coef_K) and runs kpm_grand_potential + kpm_grand_potential_grad for rho
+ * (or kpm_density_matrix_direct when estimator is KPM_RMFT_DIRECT),
  * then measures e(mu) = mean n' - (1 - doping) (kpm_rmft_update, mix = 0).
  * mu search, starting at *mu: accept an evaluation with |e| <= tol_n;
  * otherwise step from the last point on the side of e(*mu) by s = mu_step,

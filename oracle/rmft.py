@@ -28,8 +28,9 @@ readings used here, step by step:
 4. theta <- theta + mix (theta' - theta) with the rho of the accepted mu.
 
 ``rho_fn(theta, mu) -> (omega, rho)`` supplies the density matrix: the plain
-KPM of ``kpm_plain`` (the path's own truncation and probes) or the exact dense
-Fermi-function result of ``dense`` (no truncation).
+KPM of ``kpm_plain`` (the path's own truncation and probes; the adjoint), the
+direct probing estimate of ``kpm_direct``, or the exact dense Fermi-function
+result of ``dense`` (no truncation).
 """
 from __future__ import annotations
 
@@ -37,7 +38,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import builder, chebyshev, dense, kpm_plain, mapping
+from . import builder, chebyshev, dense, kpm_direct, kpm_plain, mapping
 
 
 class NoConvergence(RuntimeError):
@@ -176,6 +177,19 @@ def kpm_rho_fn(Lx, Ly, n_v, t, tp, J, T, M, probes, weights, K=None):
         a, b = chebyshev.rescale(*chebyshev.gershgorin_sparse(Hs))
         C = chebyshev.kpm_coefficients(M, T, a, b, K)
         out = kpm_plain.plain_kpm(Hs, a, b, probes, weights, C, Lx, Ly, want_grad=True)
+        return float(out["omega"]), out["rho"]
+    return fn
+
+
+def direct_rho_fn(Lx, Ly, n_v, t, tp, J, T, M, probes, weights, K=None):
+    """Direct probing estimate (series of f' per probe) on the given probes."""
+    def fn(theta, mu):
+        n, chi, dlt = theta
+        st = builder.build_stencil(Lx, Ly, n_v, t, tp, J, mu, n, chi, dlt)
+        Hs = builder.sparse_from_stencil(st, Lx, Ly)
+        a, b = chebyshev.rescale(*chebyshev.gershgorin_sparse(Hs))
+        C = chebyshev.kpm_coefficients(M, T, a, b, K)
+        out = kpm_direct.direct_rho(Hs, a, b, probes, weights, C, Lx, Ly)
         return float(out["omega"]), out["rho"]
     return fn
 

@@ -163,7 +163,8 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
       !(prm->tol_n >= 0.0) || !(prm->tol_mu >= 0.0) || !(prm->mu_step > 0.0) ||
       !std::isfinite(prm->mu_step) || !(prm->tol_residual >= 0.0) || prm->max_evals < 1 ||
       prm->coef_K < 0 || !std::isfinite(*mu) || !(T > 0.0) ||
-      (prm->search != KPM_RMFT_BISECTION && prm->search != KPM_RMFT_ILLINOIS))
+      (prm->search != KPM_RMFT_BISECTION && prm->search != KPM_RMFT_ILLINOIS) ||
+      (prm->estimator != KPM_RMFT_ADJOINT && prm->estimator != KPM_RMFT_DIRECT))
     return KPM_EINVAL;
   const int32_t R = kpm_probe_count(lat, probes);
   if (R < 1) return KPM_EINVAL;
@@ -190,12 +191,18 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
     if ((st = kpm_build_H(lat, &md, n, chi, delta, h, stream)) != KPM_OK) return st;
     if ((st = kpm_bounds(lat, h, ab, stream)) != KPM_OK) return st;
     if ((st = kpm_coefficients(M, T, ab, prm->coef_K, C, stream)) != KPM_OK) return st;
-    if ((st = kpm_grand_potential(lat, h, ab, probes, M, C, precision, ckpt_k, stats + 2, nullptr,
-                                  ws, z.kws, stream)) != KPM_OK)
-      return st;
-    if ((st = kpm_grand_potential_grad(lat, h, ab, probes, M, C, precision, ckpt_k, nullptr, rho,
-                                       ws, z.kws, stream)) != KPM_OK)
-      return st;
+    if (prm->estimator == KPM_RMFT_DIRECT) {
+      if ((st = kpm_density_matrix_direct(lat, h, ab, probes, M, C, precision, stats + 2, rho, ws,
+                                          z.kws, stream)) != KPM_OK)
+        return st;
+    } else {
+      if ((st = kpm_grand_potential(lat, h, ab, probes, M, C, precision, ckpt_k, stats + 2,
+                                    nullptr, ws, z.kws, stream)) != KPM_OK)
+        return st;
+      if ((st = kpm_grand_potential_grad(lat, h, ab, probes, M, C, precision, ckpt_k, nullptr, rho,
+                                         ws, z.kws, stream)) != KPM_OK)
+        return st;
+    }
     if ((st = kpm_rmft_update(lat, rho, 0.0, n, chi, delta, stats, stream)) != KPM_OK) return st;
     int32_t dev = KPM_OK;
     if ((st = kpm_status_read(ws, &dev, stream)) != KPM_OK) return st;
