@@ -408,6 +408,32 @@ def doubling_form(steps: int, prob, th):
     }
 
 
+def ldos_form(steps: int, prob, th, cfg):
+    """KPM local density of states along a 24-site line through a vortex core
+    of the 100x100 workload (48 Nambu indices, M = 4096, 1001 energies)."""
+    import torch
+    import workloads as wl
+
+    n, chi, dlt = th
+    h = prob.build_H(n, chi, dlt)
+    ab = prob.bounds(h)
+    X, Y = wl.vortex_centres(cfg.Lx, cfg.Ly, cfg.n_v)[0]
+    first = 2 * (int(Y) * cfg.Lx + int(X) - 12)
+    a, b = (float(v) for v in ab.cpu())
+    E = torch.linspace(b - 0.3 * a, b + 0.3 * a, 1001, dtype=torch.float64, device="cuda")
+    prob.ldos(h, ab, first, 48, E)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = prob.ldos(h, ab, first, 48, E)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    log(f"ldos line: {dt * 1e3:.1f} ms")
+    return {"workload": "48 Nambu indices (24 sites through a vortex core), M=4096, 1001 energies, FP32 "
+                        "recursion, FP64 series", "ms_per_linecut": dt * 1e3,
+            "finite": bool(torch.isfinite(out).all().item()), "min": float(out.min().item())}
+
+
 def cpu_baseline(cfg, quiet=False):
     """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
     probe of the same workload, single thread."""
@@ -556,6 +582,7 @@ def main():
     if not args.no_direct_form and not args.moments:
         result["direct_form"] = direct_form(args.steps, prob, th, dt)
         result["doubling_form"] = doubling_form(args.steps, prob, th)
+        result["ldos_form"] = ldos_form(args.steps, prob, th, cfg)
 
     if not args.no_fp64_form:
         del prob

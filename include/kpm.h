@@ -239,6 +239,23 @@ int kpm_moments_doubling(const kpm_lattice* lat, const double* h, const double* 
                          const kpm_probes* probes, int32_t M, const double* C, int32_t precision,
                          double* omega, double* mu, void* ws, size_t ws_bytes, void* stream);
 
+/* Local density of states by KPM (Results: LDOS of the vortex states; the
+ * expansion of App. B applied to unit probes, with the Jackson kernel of
+ * Weisse et al., Rev. Mod. Phys. 78, 275): for the Nambu indices
+ * I = first .. first + count - 1 (I = 2i + a),
+ *   A_I(E) = [g_0 mu_{I,0} + 2 sum_{m=1}^{M-1} g_m mu_{I,m} T_m(x)] / (pi a sqrt(1 - x^2)),
+ * x = (E - ab[1])/ab[0], mu_{I,m} = e_I^dag T_m(H~) e_I, and A = 0 for |x| >= 1.
+ * A_{(i,0)} is the spin-up electron spectral density of site i; A_{(i,1)}(E)
+ * the spin-down hole density, i.e. the spin-down electron density at -E.
+ * energies: device double[ne]; out: device double[count][ne]; 1 <= count <=
+ * 65535 (one grid row per probe).  The series
+ * is summed in FP64 whatever the recursion precision.  ws: as
+ * kpm_density_matrix_direct with R = count; the call invalidates the
+ * workspace for kpm_grand_potential_grad. */
+int kpm_ldos(const kpm_lattice* lat, const double* h, const double* ab, int32_t first,
+             int32_t count, int32_t M, int32_t precision, const double* energies, int32_t ne,
+             double* out, void* ws, size_t ws_bytes, void* stream);
+
 /* Device status word latched by the last recursion on ws: KPM_OK or
  * KPM_EBOUNDS.  Synchronises `stream`. *status is host memory. */
 int kpm_status_read(const void* ws, int32_t* status, void* stream);

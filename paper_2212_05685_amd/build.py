@@ -11,7 +11,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["kpm_build.hip", "kpm_cheb.hip", "kpm_api.hip", "kpm_rmft.hip"]
+SRC = ["kpm_build.hip", "kpm_cheb.hip", "kpm_api.hip", "kpm_rmft.hip", "kpm_ldos.hip"]
 LIB = os.path.join(HERE, "libkpm.so")
 
 

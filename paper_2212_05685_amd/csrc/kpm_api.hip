@@ -31,6 +31,7 @@ hipError_t launch_map(int, const double*, double*, double*, double*, double*, do
                       hipStream_t);
 hipError_t launch_direct_coef(const InstDev*, int, int, hipStream_t);
 hipError_t launch_mom_double(const InstDev*, int, int, int, double*, hipStream_t);
+hipError_t launch_ldos(const InstDev*, int, int, const double*, int, double*, hipStream_t);
 hipError_t launch_direct_acc(bool, const InstDev*, int, long long, int, int, hipStream_t);
 hipError_t launch_rho_direct(const InstDev*, const int2*, int, hipStream_t);
 hipError_t profile_begin(int);
@@ -677,6 +678,34 @@ int kpm_moments_doubling(const kpm_lattice* lat, const double* h, const double* 
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_mom_double(c.d_inst, 1, c.inst[0].R * M, M, mu, s));
   if (omega) KPM_HIP(launch_omega(c.d_inst, 1, M, s));
+  return KPM_OK;
+}
+
+int kpm_ldos(const kpm_lattice* lat, const double* h, const double* ab, int32_t first,
+             int32_t count, int32_t M, int32_t precision, const double* energies, int32_t ne,
+             double* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!energies || !out || ne < 1 || count < 1 || count > 65535 || first < 0) return KPM_EINVAL;
+  kpm_probe_group g{};
+  g.kind = KPM_PROBE_UNIT;
+  g.count = count;
+  g.first = first;
+  g.px = g.py = 1;
+  g.weight = 1.0;
+  const kpm_probes pr{&g, 1};
+  Ctx c;
+  int st = prepare_single(c, lat, h, ab, &pr, M, nullptr, precision, std::max<int32_t>(M, 2), ws,
+                          ws_bytes);
+  if (st != KPM_OK) return st;
+  if ((long long)ne * count >= (1LL << 31)) return KPM_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_fwd.erase(ws);
+  }
+  if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+  if ((st = run_forward(c, false, M, s)) != KPM_OK) return st;
+  if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
+  KPM_HIP(launch_ldos(c.d_inst, count, M, energies, ne, out, s));
   return KPM_OK;
 }
 

@@ -37,7 +37,7 @@ EXPORTS = (
     "kpm_density_matrix", "kpm_status_read", "kpm_batch_create", "kpm_batch_energy_grad",
     "kpm_batch_destroy", "kpm_set_probe_block", "kpm_profile_begin", "kpm_profile_end",
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
-    "kpm_density_matrix_direct", "kpm_moments_doubling",
+    "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos",
 )
 
 
@@ -97,6 +97,8 @@ def _load():
         "kpm_density_matrix": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P, c_int32,
                                          c_int32, P, P, P, P, P, P, P, P, P, c_size_t, P]),
         "kpm_status_read": (c_int32, [P, POINTER(c_int32), P]),
+        "kpm_ldos": (c_int32, [POINTER(Lattice), P, P, c_int32, c_int32, c_int32, c_int32, P, c_int32, P,
+                               P, c_size_t, P]),
         "kpm_moments_doubling": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P, c_int32,
                                            P, P, P, c_size_t, P]),
         "kpm_density_matrix_direct": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P,
@@ -300,6 +302,16 @@ def kpm_moments_doubling(lat, h, ab, probes, M, C, precision, omega, mu, ws, str
         ctypes.byref(_probes(probes)), M, _ptr(C, torch.float64, M, "C"), precision,
         _ptr(omega, torch.float64, 1, "omega"), _ptr(mu, torch.float64, R * M, "mu"),
         _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream)), "kpm_moments_doubling")
+
+
+def kpm_ldos(lat, h, ab, first, count, M, precision, energies, out, ws, stream=None):
+    N = lat.Lx * lat.Ly
+    ne = energies.numel()
+    _check(_lib.kpm_ldos(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"),
+                         _ptr(ab, torch.float64, 2, "ab"), first, count, M, precision,
+                         _ptr(energies, torch.float64, ne, "energies"), ne,
+                         _ptr(out, torch.float64, count * ne, "out"),
+                         _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream)), "kpm_ldos")
 
 
 def kpm_status_read(ws, stream=None) -> int:

@@ -115,6 +115,14 @@ class KPMProblem:
                                  self.workspace())
         return omega, mu
 
+    def ldos(self, h, ab, first, count, energies):
+        """A_I(E) [count][len(energies)] for Nambu indices first .. first+count-1,
+        with its own workspace sized for count unit probes."""
+        ws = kpm.workspace(self.lat, count, self.M, self.M, self.precision, self.device)
+        out = self.zeros(count, energies.numel(), dtype=torch.float64)
+        kpm.kpm_ldos(self.lat, h, ab, first, count, self.M, self.precision, energies, out, ws)
+        return out
+
     def status(self) -> int:
         return kpm.kpm_status_read(self.workspace())
 
