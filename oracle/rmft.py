@@ -25,7 +25,14 @@ readings used here, step by step:
    Jarratt, BIT 11, 168 (1971)): if e(m) has the sign of e_b the kept end's
    value e_a is halved, otherwise a takes b's place; b <- m; accepted when
    |e| <= tol_n or |b - a| <= tol_mu;
-4. theta <- theta + mix (theta' - theta) with the rho of the accepted mu.
+4. theta <- theta + mix (theta' - theta) with the rho of the accepted mu; or,
+   with anderson = m > 0, Anderson mixing (Anderson, J. ACM 12, 547 (1965);
+   in the form of Walker and Ni, SIAM J. Numer. Anal. 49, 1715 (2011)) on the
+   flat vector x = (n, Re/Im chi, Re/Im Delta) with residual f = x' - x: with
+   the differences dF_j, dX_j of the last min(k, m) iterations,
+   gamma = argmin |f - dF gamma| (normal equations, with a Tikhonov shift of
+   1e-12 times the largest diagonal entry), x <- x + mix f - sum_j gamma_j
+   (dX_j + mix dF_j); the first iteration of a call is a linear step.
 
 ``rho_fn(theta, mu) -> (omega, rho)`` supplies the density matrix: the plain
 KPM of ``kpm_plain`` (the path's own truncation and probes; the adjoint), the
@@ -61,6 +68,7 @@ class Params:
     max_evals: int = 60
     coef_K: int | None = None
     search: str = "bisection"      # or "illinois"
+    anderson: int = 0              # history depth of Anderson mixing (0: linear mixing)
 
 
 def singlet_theta(rho):
@@ -87,6 +95,48 @@ def update(rho, theta, mix):
     nbar, res = measure(rho, theta)
     new = (n0 + mix * (n1 - n0), c0 + mix * (c1 - c0), d0 + mix * (d1 - d0))
     return new, nbar, res
+
+
+def pack(theta):
+    """Flat real vector (n, chi as interleaved re/im, Delta as interleaved re/im)."""
+    n, chi, dlt = theta
+    return np.concatenate([np.asarray(n, dtype=np.float64),
+                           np.ascontiguousarray(chi, dtype=np.complex128).ravel().view(np.float64),
+                           np.ascontiguousarray(dlt, dtype=np.complex128).ravel().view(np.float64)])
+
+
+def unpack(x, N):
+    n = x[:N].copy()
+    chi = x[N:9 * N].copy().view(np.complex128).reshape(4, N)
+    dlt = x[9 * N:].copy().view(np.complex128).reshape(4, N)
+    return n, chi, dlt
+
+
+class Anderson:
+    """Step 4 with history depth m (see the module docstring)."""
+
+    def __init__(self, m, mix):
+        self.m, self.mix = m, mix
+        self.dF, self.dX = [], []
+        self.f_prev = self.x_prev = None
+
+    def step(self, x, f):
+        if self.f_prev is not None:
+            self.dF.append(f - self.f_prev)
+            self.dX.append(x - self.x_prev)
+            if len(self.dF) > self.m:
+                self.dF.pop(0)
+                self.dX.pop(0)
+        self.f_prev, self.x_prev = f, x
+        new = x + self.mix * f
+        if self.dF:
+            F = np.stack(self.dF, axis=1)
+            G = F.T @ F
+            G = G + 1e-12 * np.max(np.diag(G)) * np.eye(len(self.dF))
+            gamma = np.linalg.solve(G, F.T @ f)
+            for j, g in enumerate(gamma):
+                new = new - g * (self.dX[j] + self.mix * self.dF[j])
+        return new
 
 
 def solve_mu(e_fn, mu0, prm: Params):
@@ -152,6 +202,7 @@ def iterate(rho_fn, theta, mu, prm: Params, n_iter: int):
     history rows are dicts with mu, nbar, residual, omega, evals."""
     target = 1.0 - prm.doping
     hist = []
+    acc = Anderson(prm.anderson, prm.mix) if prm.anderson > 0 else None
     for _ in range(n_iter):
         def e_fn(m, th=theta):
             omega, rho = rho_fn(th, m)
@@ -159,7 +210,11 @@ def iterate(rho_fn, theta, mu, prm: Params, n_iter: int):
             return nbar - target, (omega, rho, nbar, res)
 
         mu, (omega, rho, nbar, res), evals = solve_mu(e_fn, mu, prm)
-        theta, _, _ = update(rho, theta, prm.mix)
+        if acc is None:
+            theta, _, _ = update(rho, theta, prm.mix)
+        else:
+            x = pack(theta)
+            theta = unpack(acc.step(x, pack(singlet_theta(rho)) - x), len(theta[0]))
         hist.append({"mu": mu, "nbar": nbar, "residual": res, "omega": omega, "evals": evals})
         if prm.tol_residual > 0.0 and res <= prm.tol_residual:
             break

@@ -178,3 +178,55 @@ def test_iteration_contracts_to_fixed_point(fixed_point):
     assert dist(th) < 0.8 * d_start
     assert all(abs(h["nbar"] - (1.0 - DOP)) <= 1e-6 for h in hist)
     assert abs(mu - mu_k) < 1e-2
+
+
+def test_pack_round_trip_and_layout():
+    rng = np.random.default_rng(2)
+    N = 7
+    th = (rng.normal(size=N), rng.normal(size=(4, N)) + 1j * rng.normal(size=(4, N)),
+          rng.normal(size=(4, N)) + 1j * rng.normal(size=(4, N)))
+    x = rmft.pack(th)
+    assert x.shape == (17 * N,)
+    assert x[N] == th[1][0, 0].real and x[N + 1] == th[1][0, 0].imag      # interleaved re/im
+    assert x[9 * N + 2] == th[2][0, 1].real
+    for a, b in zip(rmft.unpack(x, N), th):
+        assert np.array_equal(a, b)
+
+
+def test_anderson_solves_linear_fixed_point():
+    """On an affine map g(x) = A x + c (contraction), Anderson mixing with
+    depth >= dim reaches the fixed point (I - A)^-1 c in dim + 2 steps."""
+    rng = np.random.default_rng(4)
+    d = 5
+    Q = np.linalg.qr(rng.normal(size=(d, d)))[0]
+    A = Q @ np.diag([0.9, -0.8, 0.5, 0.2, -0.95]) @ Q.T
+    c = rng.normal(size=d)
+    xs = np.linalg.solve(np.eye(d) - A, c)
+    acc = rmft.Anderson(d, 0.3)
+    x = np.zeros(d)
+    for _ in range(d + 2):
+        x = acc.step(x, A @ x + c - x)
+    assert np.max(np.abs(x - xs)) < 1e-8
+    # linear mixing alone is far from converged after as many steps
+    y = np.zeros(d)
+    for _ in range(d + 2):
+        y = y + 0.3 * (A @ y + c - y)
+    assert np.max(np.abs(y - xs)) > 1e-2
+
+
+def test_anderson_loop_converges_faster(fixed_point):
+    """The perturbed uniform state of test_iteration_contracts_to_fixed_point:
+    Anderson mixing (depth 5) ends 12 iterations with a residual several times
+    below linear mixing's."""
+    mu_k, chi, dlt = fixed_point
+    N = L * L
+    n0, c0, d0 = _uniform_theta(chi, dlt, N)
+    rng = np.random.default_rng(11)
+    pert = 0.01
+    th = (n0 + rng.uniform(-pert, pert, N), c0 + rng.uniform(-pert, pert, (4, N)),
+          d0 + rng.uniform(-pert, pert, (4, N)) * np.array([[1], [1], [0], [0]]))
+    fn = rmft.exact_rho_fn(L, L, 0, T_, TP, J, TEMP)
+    base = dict(doping=DOP, mix=0.1, tol_n=1e-8, tol_mu=1e-12, mu_step=0.004, max_evals=60)
+    _, _, h_lin = rmft.iterate(fn, th, mu_k, rmft.Params(**base), 12)
+    _, _, h_and = rmft.iterate(fn, th, mu_k, rmft.Params(**base, anderson=5), 12)
+    assert h_and[-1]["residual"] < 0.3 * h_lin[-1]["residual"], (h_and[-1], h_lin[-1])
