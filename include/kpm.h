@@ -299,6 +299,9 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread);
  * then per-block partial results. */
 #define KPM_RMFT_STATS_LEN 520
 
+/* Largest history depth of Anderson mixing in kpm_rmft_iterate. */
+#define KPM_RMFT_MAX_ANDERSON 8
+
 /* Spin-singlet map of the density matrix onto the builder's parameters
  * (eqs. delta, chi, pairing through App. B's Nambu spinor; the two spin
  * estimates of a singlet quantity are averaged), for every site i and bond
@@ -331,6 +334,9 @@ typedef struct {
   int32_t search;     /* KPM_RMFT_BISECTION or KPM_RMFT_ILLINOIS                      */
   int32_t estimator;  /* KPM_RMFT_ADJOINT (kpm_grand_potential + _grad) or
                          KPM_RMFT_DIRECT (kpm_density_matrix_direct)                 */
+  int32_t anderson;   /* 0: linear mixing; 1 .. KPM_RMFT_MAX_ANDERSON: Anderson mixing
+                         with that history depth (see kpm_rmft_iterate)              */
+  int32_t pad;
 } kpm_rmft_params;
 
 typedef struct {      /* one completed iteration (host memory)                        */
@@ -363,8 +369,16 @@ size_t kpm_rmft_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int
  *              e_b differ in sign a <- b, else e_a <- e_a/2; then b <- m;
  *              accept m when |e(m)| <= tol_n or |b - a| <= tol_mu
  *              (Dowell & Jarratt, BIT 11, 168 (1971)).
- * The accepted rho then updates theta
- * with `mix` (kpm_rmft_update); *mu becomes the accepted mu.
+ * The accepted rho then updates theta with `mix` (kpm_rmft_update), or, with
+ * anderson = m > 0, by Anderson mixing (Anderson, J. ACM 12, 547 (1965); the
+ * form of Walker & Ni, SIAM J. Numer. Anal. 49, 1715 (2011)) on the flat
+ * vector x = (n, chi, delta as interleaved re/im), 17 N doubles, with
+ * residual f = x' - x (x' the map of kpm_rmft_update): keeping the
+ * differences dX_j, dF_j of the last min(k, m) iterations of this call,
+ *   gamma = solve(G + 1e-12 max_i G_ii I, dF^T f), G = dF^T dF,
+ *   x <- x + mix f - sum_j gamma_j (dX_j + mix dF_j)   (oldest j first);
+ * the history starts empty at each call (its first iteration is linear).
+ * *mu becomes the accepted mu.
  * n, chi, delta: device, updated in place (layouts of kpm_build_H).
  * mu: host double in/out.  history: host [n_iter] or NULL.  n_done: host,
  * iterations completed.  ws: kpm_rmft_workspace_size bytes, 256-byte aligned.

@@ -32,7 +32,8 @@ readings used here, step by step:
    the differences dF_j, dX_j of the last min(k, m) iterations,
    gamma = argmin |f - dF gamma| (normal equations, with a Tikhonov shift of
    1e-12 times the largest diagonal entry), x <- x + mix f - sum_j gamma_j
-   (dX_j + mix dF_j); the first iteration of a call is a linear step.
+   (dX_j + mix dF_j); the first iteration of a call, and any iteration whose
+   differences are all zero, is a linear step.
 
 ``rho_fn(theta, mu) -> (omega, rho)`` supplies the density matrix: the plain
 KPM of ``kpm_plain`` (the path's own truncation and probes; the adjoint), the
@@ -132,6 +133,8 @@ class Anderson:
         if self.dF:
             F = np.stack(self.dF, axis=1)
             G = F.T @ F
+            if not np.max(np.diag(G)) > 0.0:      # an all-zero history: the linear step
+                return new
             G = G + 1e-12 * np.max(np.diag(G)) * np.eye(len(self.dF))
             gamma = np.linalg.solve(G, F.T @ f)
             for j, g in enumerate(gamma):

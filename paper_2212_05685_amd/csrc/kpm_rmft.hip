@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/kpm.h"
 
@@ -97,6 +98,121 @@ __global__ __launch_bounds__(kRB) void k_rmft_finish(int N, int nblocks, double*
   }
 }
 
+// ------------------------------------------------------- Anderson mixing
+// Flat parameter vector x of L = 17 N doubles: n [N], chi [4][N] and delta
+// [4][N] as interleaved (re, im) -- the byte layout of the three user arrays
+// one after the other.  The residual f = x' - x uses the map above.
+constexpr int kMaxAnd = KPM_RMFT_MAX_ANDERSON;
+constexpr int kDotChunk = 8 * kRB;                 // elements per block in the dot products
+
+__global__ __launch_bounds__(kRB) void k_and_resid(int N, const double2* __restrict__ rho,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ f) {
+  const int i = blockIdx.x * kRB + threadIdx.x;
+  if (i >= N) return;
+  f[i] = rho[(size_t)16 * N + i].x + 1.0 - rho[(size_t)17 * N + i].x - x[i];
+  for (int d = 0; d < 4; ++d) {
+    const double2 r0 = rho[(size_t)(4 * d + 0) * N + i], r1 = rho[(size_t)(4 * d + 1) * N + i];
+    const double2 r2 = rho[(size_t)(4 * d + 2) * N + i], r3 = rho[(size_t)(4 * d + 3) * N + i];
+    const size_t c = (size_t)N + 2 * ((size_t)d * N + i), e = c + 8 * (size_t)N;
+    f[c] = 0.5 * (r0.x - r3.x) - x[c];
+    f[c + 1] = 0.5 * (r0.y + r3.y) - x[c + 1];
+    f[e] = 0.5 * (-r1.x - r2.x) - x[e];
+    f[e + 1] = 0.5 * (r1.y - r2.y) - x[e + 1];
+  }
+}
+
+// dX = x - x_prev, dF = f - f_prev (when have_prev), then x_prev = x, f_prev = f.
+__global__ __launch_bounds__(kRB) void k_and_hist(long long L, const double* __restrict__ x,
+                                                  const double* __restrict__ f,
+                                                  double* __restrict__ xp, double* __restrict__ fp,
+                                                  double* __restrict__ dX, double* __restrict__ dF,
+                                                  int have_prev) {
+  for (long long k = (long long)blockIdx.x * kRB + threadIdx.x; k < L; k += (long long)gridDim.x * kRB) {
+    const double xv = x[k], fv = f[k];
+    if (have_prev) {
+      dX[k] = xv - xp[k];
+      dF[k] = fv - fp[k];
+    }
+    xp[k] = xv;
+    fp[k] = fv;
+  }
+}
+
+struct Slots {
+  int s[kMaxAnd];
+};
+
+// Partial dot products, block (chunk c, pair q): pairs q < T = mk (mk + 1)/2
+// are <dF_i, dF_j>, i <= j (row-major upper triangle), pairs T + i are
+// <dF_i, f>; i, j index the chronological slot list.
+__global__ __launch_bounds__(kRB) void k_and_dots(long long L, const double* __restrict__ dFbase,
+                                                  const double* __restrict__ f, Slots sl, int mk,
+                                                  double* __restrict__ part, int nchunk) {
+  const int q = blockIdx.y, T = mk * (mk + 1) / 2;
+  int i, j = -1;
+  if (q < T) {
+    int r = q;
+    i = 0;
+    while (r >= mk - i) { r -= mk - i; ++i; }
+    j = i + r;
+  } else {
+    i = q - T;
+  }
+  const double* u = dFbase + (size_t)sl.s[i] * L;
+  const double* v = j >= 0 ? dFbase + (size_t)sl.s[j] * L : f;
+  const long long k0 = (long long)blockIdx.x * kDotChunk;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < kDotChunk; t += kRB) {
+    const long long k = k0 + t;
+    if (k < L) acc = fma(u[k], v[k], acc);
+  }
+  __shared__ double sh[kRB];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (unsigned s = kRB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)q * nchunk + blockIdx.x] = sh[0];
+}
+
+// One block per pair: the chunk partials in chunk order.
+__global__ __launch_bounds__(kRB) void k_and_dots_finish(const double* __restrict__ part, int nchunk,
+                                                         double* __restrict__ out) {
+  const int q = blockIdx.x;
+  __shared__ double sh[kRB];
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += kRB) acc += part[(size_t)q * nchunk + c];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (unsigned s = kRB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = sh[0];
+}
+
+struct Gammas {
+  double g[kMaxAnd];
+};
+
+// x <- x + beta f - sum_j gamma_j (dX_j + beta dF_j), j in chronological order.
+__global__ __launch_bounds__(kRB) void k_and_update(long long L, double* __restrict__ x,
+                                                    const double* __restrict__ f,
+                                                    const double* __restrict__ dXbase,
+                                                    const double* __restrict__ dFbase, Slots sl,
+                                                    Gammas gm, int mk, double beta) {
+  for (long long k = (long long)blockIdx.x * kRB + threadIdx.x; k < L; k += (long long)gridDim.x * kRB) {
+    double v = x[k] + beta * f[k];
+    for (int j = 0; j < mk; ++j) {
+      const size_t o = (size_t)sl.s[j] * L + k;
+      v -= gm.g[j] * (dXbase[o] + beta * dFbase[o]);
+    }
+    x[k] = v;
+  }
+}
+
 bool valid_lattice(const kpm_lattice* L) {
   return L && L->Lx >= 3 && L->Ly >= 3 && (L->n_vortex % 2) == 0 &&
          (long long)L->Lx * L->Ly <= (1LL << 26);
@@ -105,7 +221,7 @@ bool valid_lattice(const kpm_lattice* L) {
 // Workspace of kpm_rmft_iterate: the recursion workspace first (so that
 // kpm_status_read works on the same pointer), then h, rho, ab, C, stats.
 struct RmftLayout {
-  size_t kws, h, rho, ab, C, stats, total;
+  size_t kws, h, rho, ab, C, stats, and_vec, and_part, and_dots, total;
 };
 
 RmftLayout rmft_layout(const kpm_lattice* L, int R, int M, int ckpt_k, int precision) {
@@ -120,8 +236,107 @@ RmftLayout rmft_layout(const kpm_lattice* L, int R, int M, int ckpt_k, int preci
   z.ab = off;    off += align_up(2 * sizeof(double));
   z.C = off;     off += align_up((size_t)M * sizeof(double));
   z.stats = off; off += align_up(KPM_RMFT_STATS_LEN * sizeof(double));
+  // Anderson: x, f, x_prev, f_prev, then kMaxAnd dX and kMaxAnd dF vectors
+  const size_t Lv = 17 * N;
+  const size_t nchunk = (Lv + kDotChunk - 1) / kDotChunk;
+  const size_t npair = (size_t)kMaxAnd * (kMaxAnd + 1) / 2 + kMaxAnd;
+  z.and_vec = off;  off += align_up((4 + 2 * (size_t)kMaxAnd) * Lv * sizeof(double));
+  z.and_part = off; off += align_up(npair * nchunk * sizeof(double));
+  z.and_dots = off; off += align_up(npair * sizeof(double));
   z.total = off;
   return z;
+}
+
+// Gaussian elimination with partial pivoting on the mk x mk system (in place).
+bool solve_small(std::vector<double>& A, std::vector<double>& b, int n) {
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[p * n + c])) p = r;
+    if (!(std::fabs(A[p * n + c]) > 0.0)) return false;
+    if (p != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[p * n + k]);
+      std::swap(b[c], b[p]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double l = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= l * A[c * n + k];
+      b[r] -= l * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double v = b[r];
+    for (int k = r + 1; k < n; ++k) v -= A[r * n + k] * b[k];
+    b[r] = v / A[r * n + r];
+  }
+  return true;
+}
+
+// One Anderson update of theta from the accepted rho (see kpm_rmft_params).
+int anderson_step(const kpm_rmft_params* prm, int N, long long Lv, const double* rho, double* n,
+                  double* chi, double* delta, double* ax, double* af, double* axp, double* afp,
+                  double* adX, double* adF, double* apart, double* adots, int nchunk, int vgrid,
+                  std::vector<int>& order, bool& have_prev, hipStream_t s) {
+  const size_t nb = (size_t)N * sizeof(double);
+  if (hipMemcpyAsync(ax, n, nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ax + N, chi, 8 * nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ax + 9 * (size_t)N, delta, 8 * nb, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return KPM_EDEVICE;
+  hipLaunchKernelGGL(k_and_resid, dim3((N + kRB - 1) / kRB), dim3(kRB), 0, s, N,
+                     reinterpret_cast<const double2*>(rho), ax, af);
+  int slot = -1;
+  if (have_prev) {
+    if ((int)order.size() < prm->anderson) {
+      slot = (int)order.size();
+    } else {
+      slot = order.front();
+      order.erase(order.begin());
+    }
+    order.push_back(slot);
+  }
+  hipLaunchKernelGGL(k_and_hist, dim3(vgrid), dim3(kRB), 0, s, Lv, ax, af, axp, afp,
+                     adX + (size_t)std::max(slot, 0) * Lv, adF + (size_t)std::max(slot, 0) * Lv,
+                     have_prev ? 1 : 0);
+  have_prev = true;
+  const int mk = (int)order.size();
+  Slots sl{};
+  for (int j = 0; j < mk; ++j) sl.s[j] = order[j];
+  Gammas gm{};
+  if (mk > 0) {
+    const int T = mk * (mk + 1) / 2;
+    hipLaunchKernelGGL(k_and_dots, dim3(nchunk, T + mk), dim3(kRB), 0, s, Lv, adF, af, sl, mk,
+                       apart, nchunk);
+    hipLaunchKernelGGL(k_and_dots_finish, dim3(T + mk), dim3(kRB), 0, s, apart, nchunk, adots);
+    std::vector<double> d(T + mk);
+    if (hipMemcpyAsync(d.data(), adots, d.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return KPM_EDEVICE;
+    std::vector<double> A(mk * mk), b(mk);
+    int q = 0;
+    for (int i = 0; i < mk; ++i)
+      for (int j = i; j < mk; ++j) A[i * mk + j] = A[j * mk + i] = d[q++];
+    double dmax = 0.0;
+    for (int i = 0; i < mk; ++i) dmax = std::max(dmax, A[i * mk + i]);
+    if (!std::isfinite(dmax)) return KPM_EBOUNDS;
+    if (dmax > 0.0) {                    // an all-zero history leaves the linear step
+      for (int i = 0; i < mk; ++i) A[i * mk + i] += 1e-12 * dmax;
+      for (int i = 0; i < mk; ++i) b[i] = d[T + i];
+      if (!solve_small(A, b, mk)) return KPM_EBOUNDS;
+      for (int j = 0; j < mk; ++j) {
+        if (!std::isfinite(b[j])) return KPM_EBOUNDS;
+        gm.g[j] = b[j];
+      }
+    }
+  }
+  hipLaunchKernelGGL(k_and_update, dim3(vgrid), dim3(kRB), 0, s, Lv, ax, af, adX, adF, sl, gm, mk,
+                     prm->mix);
+  if (hipGetLastError() != hipSuccess) return KPM_EDEVICE;
+  if (hipMemcpyAsync(n, ax, nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(chi, ax + N, 8 * nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(delta, ax + 9 * (size_t)N, 8 * nb, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return KPM_EDEVICE;
+  return KPM_OK;
 }
 
 }  // namespace
@@ -164,7 +379,8 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
       !std::isfinite(prm->mu_step) || !(prm->tol_residual >= 0.0) || prm->max_evals < 1 ||
       prm->coef_K < 0 || !std::isfinite(*mu) || !(T > 0.0) ||
       (prm->search != KPM_RMFT_BISECTION && prm->search != KPM_RMFT_ILLINOIS) ||
-      (prm->estimator != KPM_RMFT_ADJOINT && prm->estimator != KPM_RMFT_DIRECT))
+      (prm->estimator != KPM_RMFT_ADJOINT && prm->estimator != KPM_RMFT_DIRECT) ||
+      prm->anderson < 0 || prm->anderson > KPM_RMFT_MAX_ANDERSON)
     return KPM_EINVAL;
   const int32_t R = kpm_probe_count(lat, probes);
   if (R < 1) return KPM_EINVAL;
@@ -181,6 +397,20 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
   double* stats = reinterpret_cast<double*>(base + z.stats);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double target = 1.0 - prm->doping;
+  const int N = lat->Lx * lat->Ly;
+  const long long Lv = 17LL * N;
+  double* ax = reinterpret_cast<double*>(base + z.and_vec);
+  double* af = ax + Lv;
+  double* axp = af + Lv;
+  double* afp = axp + Lv;
+  double* adX = afp + Lv;
+  double* adF = adX + (size_t)kMaxAnd * Lv;
+  double* apart = reinterpret_cast<double*>(base + z.and_part);
+  double* adots = reinterpret_cast<double*>(base + z.and_dots);
+  const int nchunk = (int)((Lv + kDotChunk - 1) / kDotChunk);
+  const int vgrid = (int)std::min<long long>((Lv + kRB - 1) / kRB, 4096);
+  std::vector<int> order;            // Anderson slots, oldest first
+  bool have_prev = false;
 
   // One density-matrix evaluation at chemical potential m with theta fixed:
   // out[0] = mean n', out[1] = residual, out[2] = Omega.
@@ -264,7 +494,12 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
         if (std::fabs(e) <= prm->tol_n || std::fabs(b - a) <= prm->tol_mu) { acc = m; break; }
       }
     }
-    if ((st = kpm_rmft_update(lat, rho, prm->mix, n, chi, delta, stats, stream)) != KPM_OK) return st;
+    if (prm->anderson == 0) {
+      if ((st = kpm_rmft_update(lat, rho, prm->mix, n, chi, delta, stats, stream)) != KPM_OK) return st;
+    } else if ((st = anderson_step(prm, N, Lv, rho, n, chi, delta, ax, af, axp, afp, adX, adF, apart,
+                                   adots, nchunk, vgrid, order, have_prev, s)) != KPM_OK) {
+      return st;
+    }
     cur = acc;
     *mu = acc;
     if (history) {

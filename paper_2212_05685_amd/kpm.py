@@ -62,7 +62,8 @@ class Probes(ctypes.Structure):
 class RmftParams(ctypes.Structure):
     _fields_ = [("doping", c_double), ("mix", c_double), ("tol_n", c_double), ("tol_mu", c_double),
                 ("mu_step", c_double), ("tol_residual", c_double), ("max_evals", c_int32),
-                ("coef_K", c_int32), ("search", c_int32), ("estimator", c_int32)]
+                ("coef_K", c_int32), ("search", c_int32), ("estimator", c_int32),
+                ("anderson", c_int32), ("pad", c_int32)]
 
 
 class RmftRecord(ctypes.Structure):
@@ -361,9 +362,9 @@ def kpm_rmft_workspace_size(lat, R, M, ckpt_k, precision) -> int:
 
 def rmft_params(doping, mix=0.1, tol_n=1e-6, tol_mu=1e-10, mu_step=0.004, tol_residual=0.0,
                 max_evals=60, coef_K=0, search=KPM_RMFT_BISECTION,
-                estimator=KPM_RMFT_ADJOINT) -> RmftParams:
+                estimator=KPM_RMFT_ADJOINT, anderson=0) -> RmftParams:
     return RmftParams(doping, mix, tol_n, tol_mu, mu_step, tol_residual, max_evals, coef_K, search,
-                      estimator)
+                      estimator, anderson, 0)
 
 
 def kpm_rmft_iterate(lat, mdl, probes, M, T, precision, ckpt_k, params, n_iter, n, chi, delta, mu,

@@ -119,6 +119,7 @@ def main(argv=None):
     ap.add_argument("--tol-n", type=float, default=1e-5)
     ap.add_argument("--search", choices=("illinois", "bisection"), default="illinois")
     ap.add_argument("--estimator", choices=("adjoint", "direct"), default="adjoint")
+    ap.add_argument("--anderson", type=int, default=0, help="Anderson history depth (0: linear mixing)")
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--chunk", type=int, default=25)
     ap.add_argument("--tol-residual", type=float, default=0.0)
@@ -145,7 +146,8 @@ def main(argv=None):
     search = kpm.KPM_RMFT_ILLINOIS if args.search == "illinois" else kpm.KPM_RMFT_BISECTION
     est = kpm.KPM_RMFT_DIRECT if args.estimator == "direct" else kpm.KPM_RMFT_ADJOINT
     prm = kpm.rmft_params(cfg.doping, mix=args.mix, tol_n=args.tol_n, tol_mu=1e-9, mu_step=0.004,
-                          tol_residual=args.tol_residual, max_evals=60, search=search, estimator=est)
+                          tol_residual=args.tol_residual, max_evals=60, search=search, estimator=est,
+                          anderson=args.anderson)
     t0 = time.perf_counter()
     done = 0
     while done < args.iters:

@@ -82,7 +82,7 @@ def test_rmft_host_validation():
 
     lat = kpm.lattice(8, 8, 0)
     fake = ctypes.c_void_p(256)
-    assert ctypes.sizeof(kpm.RmftParams) == 64 and kpm.RmftParams.search.offset == 56 and kpm.RmftParams.estimator.offset == 60 and ctypes.sizeof(kpm.RmftRecord) == 40
+    assert ctypes.sizeof(kpm.RmftParams) == 72 and kpm.RmftParams.anderson.offset == 64 and kpm.RmftParams.search.offset == 56 and kpm.RmftParams.estimator.offset == 60 and ctypes.sizeof(kpm.RmftRecord) == 40
     assert kpm.RmftRecord.evals.offset == 32
     for mix in (-0.1, 1.5, float("nan")):
         assert kpm._lib.kpm_rmft_update(ctypes.byref(lat), fake, mix, fake, fake, fake, fake,
@@ -109,7 +109,8 @@ def test_rmft_host_validation():
                 kpm.rmft_params(0.16, mix=1.2), kpm.rmft_params(0.16, tol_n=-1.0),
                 kpm.rmft_params(0.16, mu_step=0.0), kpm.rmft_params(0.16, max_evals=0),
                 kpm.rmft_params(0.16, coef_K=-1), kpm.rmft_params(0.16, search=2),
-                kpm.rmft_params(0.16, estimator=2)):
+                kpm.rmft_params(0.16, estimator=2), kpm.rmft_params(0.16, anderson=-1),
+                kpm.rmft_params(0.16, anderson=9)):
         assert call(bad) == kpm.KPM_EINVAL
     assert call(good, n_iter=-1) == kpm.KPM_EINVAL
     assert call(good, T=0.0) == kpm.KPM_EINVAL

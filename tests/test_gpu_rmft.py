@@ -5,8 +5,8 @@ kpm_rmft_iterate) against the oracle's loop (oracle/rmft.py), through the C ABI.
   density matrices, element by element, at a ragged size, at the 48 x 96
   workload size and above the one-pass grid (grid-stride path): FP64 with the
   same operations, so 1e-14 absolute;
-* whole iterations in FP64 with either search and either estimator of rho
-  (bracket decisions, evaluation counts, mu,
+* whole iterations in FP64 with either search, either estimator of rho and
+  linear or Anderson mixing (bracket decisions, evaluation counts, mu,
   mean density, residual, Omega and theta after every iteration) against the
   oracle loop on the plain KPM: evaluation counts exact, values to the FP64
   bar 1e-10 (relative for Omega and rho-derived values);
@@ -81,6 +81,7 @@ def _oracle_loop(cfg, prm, n_iter, mu0, estimator="adjoint"):
 
 
 def _gpu_loop(cfg, p, n_iter, mu0, precision=None, estimator="adjoint"):
+    """p: oracle Params (search, anderson, tolerances) mirrored into the ABI's."""
     from paper_2212_05685_amd import kpm
 
     pb = problem(cfg, precision=precision)
@@ -88,21 +89,24 @@ def _gpu_loop(cfg, p, n_iter, mu0, precision=None, estimator="adjoint"):
     search = {"bisection": kpm.KPM_RMFT_BISECTION, "illinois": kpm.KPM_RMFT_ILLINOIS}[p.search]
     est = {"adjoint": kpm.KPM_RMFT_ADJOINT, "direct": kpm.KPM_RMFT_DIRECT}[estimator]
     prm = kpm.rmft_params(p.doping, p.mix, p.tol_n, p.tol_mu, p.mu_step, p.tol_residual, p.max_evals,
-                          search=search, estimator=est)
+                          search=search, estimator=est, anderson=p.anderson)
     mu, hist, st = pb.rmft_iterate(n, chi, dlt, mu0, prm, n_iter)
     return (host(n), host(chi), host(dlt)), mu, hist, st
 
 
-@pytest.mark.parametrize("search,estimator", [("bisection", "adjoint"), ("illinois", "adjoint"),
-                                              ("illinois", "direct")])
-def test_iterate_parity_fp64(search, estimator):
+@pytest.mark.parametrize("search,estimator,anderson", [("bisection", "adjoint", 0),
+                                                       ("illinois", "adjoint", 0),
+                                                       ("illinois", "direct", 0),
+                                                       ("illinois", "adjoint", 2)])
+def test_iterate_parity_fp64(search, estimator, anderson):
     cfg = _loop_cfg()
     prm = ormft.Params(doping=0.16, mix=0.1, tol_n=1e-5, tol_mu=1e-10, mu_step=0.004, max_evals=60,
-                       search=search)
+                       search=search, anderson=anderson)
     mu0 = cfg.mu
-    th_ref, mu_ref, hist_ref = _oracle_loop(cfg, prm, 3, mu0, estimator)
-    th, mu, hist, st = _gpu_loop(cfg, prm, 3, mu0, estimator=estimator)
-    assert st == 0 and len(hist) == len(hist_ref) == 3
+    n_it = 4 if anderson else 3                 # Anderson: the ring wraps at the fourth iteration
+    th_ref, mu_ref, hist_ref = _oracle_loop(cfg, prm, n_it, mu0, estimator)
+    th, mu, hist, st = _gpu_loop(cfg, prm, n_it, mu0, estimator=estimator)
+    assert st == 0 and len(hist) == len(hist_ref) == n_it
     for g, r in zip(hist, hist_ref):
         assert g["evals"] == r["evals"], (hist, hist_ref)
         assert abs(g["mu"] - r["mu"]) < 1e-12
