@@ -481,6 +481,7 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   // Straight-line steps (a step past the wave's last probe recomputes the
   // last probe and stores to the sink), so that the wait counts are static.
   for (int p0 = pbase; p0 < pend; p0 += FPD) {
+    double dsv[FPD], dxv[FPD];            // DBL: this lane's terms of the ring's probes
 #pragma unroll
     for (int u = 0; u < FPD; ++u) {
       const int p = p0 + u;
@@ -506,18 +507,35 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
         // lattice and repeated probes contribute nothing
         const Cx<V> am = lds_own<V>(lds + L.hoff[0], L.a);
         const double ox = (double)o.x, oy = (double)o.y;
-        const double sv = live ? fma(ox, ox, oy * oy) : 0.0;
-        const double xv = live ? fma(ox, (double)am.x, oy * (double)am.y) : 0.0;
-        const double ssum = wave_sum(sv), xsum = wave_sum(xv);
-        if (lane == p - pbase) {
-          momv = ssum;
-          momx = xsum;
-        }
+        dsv[u] = live ? fma(ox, ox, oy * oy) : 0.0;
+        dxv[u] = live ? fma(ox, (double)am.x, oy * (double)am.y) : 0.0;
       } else {
         const double v = wave_moment(re_conj_phase<V>(k, o), k >= 0);
         if (lane == p - pbase) momv = v;
       }
       __builtin_amdgcn_wave_barrier();
+    }
+    if constexpr (DBL) {
+      static_assert(FPD == 2, "the butterfly below reduces two probes' sums");
+      // Transposed butterfly over the four sums (S, X of probes p0, p0 + 1):
+      // the lane halves trade one probe's pair, the quarters one quantity,
+      // then plain halving; quarter (u, q) ends with the sum of quantity q
+      // (0: S, 1: X) of probe p0 + u.
+      const bool hi = (lane & 32) != 0, q1 = (lane & 16) != 0;
+      const double k0 = hi ? dsv[1] : dsv[0], k1 = hi ? dxv[1] : dxv[0];
+      const double s0 = hi ? dsv[0] : dsv[1], s1 = hi ? dxv[0] : dxv[1];
+      const double c0 = k0 + __shfl_xor(s0, 32, 64), c1 = k1 + __shfl_xor(s1, 32, 64);
+      double d = (q1 ? c1 : c0) + __shfl_xor(q1 ? c0 : c1, 16, 64);
+#pragma unroll
+      for (int sh = 8; sh >= 1; sh >>= 1) d += __shfl_xor(d, sh, 64);
+#pragma unroll
+      for (int u = 0; u < FPD; ++u) {
+        const double ssum = read_lane(d, 32 * u), xsum = read_lane(d, 32 * u + 16);
+        if (lane == p0 + u - pbase) {
+          momv = ssum;
+          momx = xsum;
+        }
+      }
     }
   }
   if constexpr (DBL) {
