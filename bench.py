@@ -374,7 +374,8 @@ def direct_form(steps: int, prob, th, dt_adjoint):
         "omega_rel_diff_vs_adjoint_form": abs(float(om.item()) - float(out["omega"].item()))
                                           / abs(float(out["omega"].item())),
         "rho_max_rel_diff_vs_adjoint_form": float(np.max(np.abs(r_dir - r_adj)) / np.max(np.abs(r_adj))),
-        "accumulation_bytes_per_launch": 96 * prob.R * prob.N,
+        # even steps: the forward step plus read and write of the FP64 y records
+        "accumulating_step_bytes_per_launch": 48 * prob.R * prob.N + 36 * 8 * prob.N + 64 * prob.R * prob.N,
     }
 
 

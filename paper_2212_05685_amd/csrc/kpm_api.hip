@@ -32,7 +32,6 @@ hipError_t launch_map(int, const double*, double*, double*, double*, double*, do
 hipError_t launch_direct_coef(const InstDev*, int, int, hipStream_t);
 hipError_t launch_mom_double(const InstDev*, int, int, int, double*, hipStream_t);
 hipError_t launch_ldos(const InstDev*, int, int, const double*, int, double*, hipStream_t);
-hipError_t launch_direct_acc(bool, const InstDev*, int, long long, int, int, hipStream_t);
 hipError_t launch_rho_direct(const InstDev*, const int2*, int, hipStream_t);
 hipError_t profile_begin(int);
 hipError_t profile_end(double*, int*, double*, int*);
@@ -636,17 +635,15 @@ int kpm_density_matrix_direct(const kpm_lattice* lat, const double* h, const dou
     g_fwd.erase(ws);                       // the adjoint buffers are overwritten below
   }
   if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
-  const long long records = (long long)c.inst[0].R * c.inst[0].N;
   hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, c.d_inst, 1, 0);
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
   KPM_HIP(launch_direct_coef(c.d_inst, 1, M, s));
   KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), 0, M, c.k, 0, s));
-  for (int m = 0; m + 1 < M; ++m) {
-    // step m writes alpha_{m+1}; after an even step alpha_m, alpha_{m+1} sit in A[0], A[1]
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, M, c.k, 0, s));
-    if ((m & 1) == 0) KPM_HIP(launch_direct_acc(c.fp32, c.d_inst, 1, records, m, m == 0, s));
-  }
+  // step m writes alpha_{m+1}; even steps also add D_m alpha_m + D_{m+1} alpha_{m+1} to y
+  for (int m = 0; m + 1 < M; ++m)
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, (m & 1) ? 1 : 5, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, M,
+                        c.k, m == 0 ? 1 : 0, s));
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_omega(c.d_inst, 1, M, s));
   KPM_HIP(launch_rho_direct(c.d_inst, c.d_cmap, c.nch(), s));

@@ -429,7 +429,11 @@ constexpr int FPD = 2;
 // the partials of alpha_{m+1}^dag alpha_{m+1} and Re(alpha_{m+1}^dag alpha_m)
 // go to moment slots 2(m+1) and 2m+1 (when below M), from which
 // mu_{2j} = 2 alpha_j^dag alpha_j - mu_0 and mu_{2j+1} = 2 Re(alpha_{j+1}^dag alpha_j) - mu_1.
-template <typename V, int PW, bool CK, bool DBL = false>
+// ACC (direct probing estimate, even m): also y += D_m alpha_m + D_{m+1}
+// alpha_{m+1} for the lane's own component, y the FP64 records in G[0..1] and
+// D in musum; ACC == 2 starts y (first pair).  y's own component rides in the
+// same register ring as the other per-probe loads.
+template <typename V, int PW, bool CK, bool DBL = false, int ACC = 0>
 __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
                                          const int4* __restrict__ tmap, Sched sc, int m,
                                          int k_ckpt) {
@@ -465,18 +469,24 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   constexpr unsigned RB = sizeof(R4), CB = RB / 2;   // bytes of a record, of a component
   const char* sink_own = (const char*)I.sink + (unsigned)L.s * RB + (unsigned)L.a * CB;
   double momv = 0.0;                     // moment of probe pbase + lane, stored after the loop
+  // ACC: y records (FP64, 32 B) and their sink slots; D_m, D_{m+1}
+  const void* ybuf = I.G[0];
+  const char* sink_y = (const char*)I.sink + (unsigned)L.s * 32u + (unsigned)L.a * 16u;
+  const double Dm = ACC ? I.musum[m] : 0.0, Dm1 = ACC ? I.musum[m + 1] : 0.0;
   // Ring of FPD probes in flight.  A slot is refilled only after its values
   // have been consumed, so each load lands in the register it is read from
   // later (no copies, which would force an early wait for the load).
   R4 st[FPD];
   Cx<V> pq[FPD];
   unsigned cq[FPD];
+  Cx<double> yq[FPD];
 #pragma unroll
   for (int u = 0; u < FPD; ++u) {
     const int p = min(pbase + u, pend - 1);
     st[u] = ldg_rec<V>(cur, (unsigned)(p * N) + L.halo);
     pq[u] = ldg_comp<V>(nxt, (unsigned)(p * N) + L.site, L.a);
     cq[u] = ldg_code(I, (unsigned)(p * N) + L.site);
+    if constexpr (ACC == 1) yq[u] = ldg_comp<double>(ybuf, (unsigned)(p * N) + L.site, L.a);
   }
   // Straight-line steps (a step past the wave's last probe recomputes the
   // last probe and stores to the sink), so that the wait counts are static.
@@ -502,6 +512,17 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
       const size_t own = (size_t)((unsigned)(p * N) + L.site) * RB + (unsigned)L.a * CB;
       st_cx<V>(store_addr(live, (const char*)nxt + own, sink_own), 0u, o);
       if (CK) st_cx<V>(store_addr(live, (const char*)ckbuf + own, sink_own), 0u, o);
+      if constexpr (ACC != 0) {
+        const Cx<V> am = lds_own<V>(lds + L.hoff[0], L.a);
+        Cx<double> y = ACC == 1 ? yq[u] : Cx<double>{0.0, 0.0};
+        y.x = fma(Dm, (double)am.x, y.x);
+        y.y = fma(Dm, (double)am.y, y.y);
+        y.x = fma(Dm1, (double)o.x, y.x);
+        y.y = fma(Dm1, (double)o.y, y.y);
+        if constexpr (ACC == 1) yq[u] = ldg_comp<double>(ybuf, (unsigned)(pn * N) + L.site, L.a);
+        const size_t yown = (size_t)((unsigned)(p * N) + L.site) * 32u + (unsigned)L.a * 16u;
+        st_cx<double>(store_addr(live, (const char*)ybuf + yown, sink_y), 0u, y);
+      }
       if constexpr (DBL) {
         // own alpha_m component from the staged record; lanes outside the
         // lattice and repeated probes contribute nothing
@@ -783,6 +804,12 @@ template <int PW> struct StepKernels<float, PW> {
             int M) {
     fwd_body<float, PW, false, true>(insts, tmap, sc, m, M);
   }
+  template <int ACC>
+  static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+  void fwdacc(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
+              int k_ckpt) {
+    fwd_body<float, PW, false, false, ACC>(insts, tmap, sc, m, k_ckpt);
+  }
   template <bool TAIL>
   static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
   void adj(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
@@ -801,6 +828,12 @@ template <int PW> struct StepKernels<double, PW> {
   void fwd2(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
             int M) {
     fwd_body<double, PW, false, true>(insts, tmap, sc, m, M);
+  }
+  template <int ACC>
+  static __global__ __launch_bounds__(kBlock)
+  void fwdacc(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
+              int k_ckpt) {
+    fwd_body<double, PW, false, false, ACC>(insts, tmap, sc, m, k_ckpt);
   }
   template <bool TAIL>
   static __global__ __launch_bounds__(kBlock)
@@ -929,9 +962,10 @@ __global__ __launch_bounds__(kBlock) void k_map(int N, const double2* __restrict
 
 // ------------------------------------------------- direct probing estimate
 // rho_IJ ~= (1/a) sum_p w_p conj(r_{p,I}) y_{p,J},  y_p = F_M'(H~) r_p
-// = sum_m D_m alpha_{p,m} (the series of f' applied to each probe).  y is an
-// FP64 record per (probe, site) in the adjoint buffers G[0..1], which the
-// direct path does not use (2 FP32 records or 1 FP64 record of space each);
+// = sum_m D_m alpha_{p,m} (the series of f' applied to each probe), which the
+// forward steps with even m accumulate (fwd_body, ACC).  y is an FP64 record
+// per (probe, site) in the adjoint buffers G[0..1], which the direct path
+// does not use (2 FP32 records or 1 FP64 record of space each);
 // D is kept in the first M doubles of musum, which the moment reduction
 // overwrites only after the last accumulation.
 
@@ -949,36 +983,6 @@ __global__ void k_direct_coef(const InstDev* __restrict__ insts, int M) {
     else D[0] = 0.5 * e0;
     e2 = e1;
     e1 = e0;
-  }
-}
-
-// y += D_m alpha_m + D_{m+1} alpha_{m+1} for even m (alpha_m in A[0],
-// alpha_{m+1} in A[1]); first: y = that sum.  One record per thread,
-// grid-stride over the R N records of instance blockIdx.y.
-template <typename V>
-__global__ __launch_bounds__(kBlock) void k_direct_acc(const InstDev* __restrict__ insts, int m,
-                                                       int first) {
-  const InstDev& I = insts[blockIdx.y];
-  const double* D = I.musum;
-  const double d0 = D[m], d1 = D[m + 1];
-  const unsigned total = (unsigned)I.R * (unsigned)I.N;
-  for (unsigned idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
-    const Rec<V> a0 = ld_rec<V>(I.A[0], idx), a1 = ld_rec<V>(I.A[1], idx);
-    Rec<double> y;
-    if (first) {
-      y.c[0] = {0.0, 0.0};
-      y.c[1] = {0.0, 0.0};
-    } else {
-      y = ld_rec<double>(I.G[0], idx);
-    }
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      y.c[c].x = fma(d0, (double)a0.c[c].x, y.c[c].x);
-      y.c[c].y = fma(d0, (double)a0.c[c].y, y.c[c].y);
-      y.c[c].x = fma(d1, (double)a1.c[c].x, y.c[c].x);
-      y.c[c].y = fma(d1, (double)a1.c[c].y, y.c[c].y);
-    }
-    st_rec<double>(I.G[0], idx, y);
   }
 }
 
@@ -1146,6 +1150,12 @@ static hipError_t launch_all(int which, const InstDev* insts, const int4* tmap, 
     case 4:
       hipLaunchKernelGGL((StepKernels<V, PW>::fwd2), grid, block, 0, s, insts, tmap, sc, m, M);
       break;
+    case 5: {
+      // forward step with the direct-estimate accumulation (flag: first pair)
+      auto kern = flag ? StepKernels<V, PW>::template fwdacc<2> : StepKernels<V, PW>::template fwdacc<1>;
+      hipLaunchKernelGGL(kern, grid, block, 0, s, insts, tmap, sc, m, k_ckpt);
+      break;
+    }
     case 3: {
       auto kern = flag ? StepKernels<V, PW>::template adj<true> : StepKernels<V, PW>::template adj<false>;
       if (timed)
@@ -1208,17 +1218,6 @@ hipError_t launch_mom_double(const InstDev* insts, int ninst, int maxRM, int M, 
 
 hipError_t launch_direct_coef(const InstDev* insts, int ninst, int M, hipStream_t s) {
   hipLaunchKernelGGL(k_direct_coef, dim3(ninst), dim3(64), 0, s, insts, M);
-  return hipGetLastError();
-}
-
-hipError_t launch_direct_acc(bool fp32, const InstDev* insts, int ninst, long long records, int m,
-                             int first, hipStream_t s) {
-  const long long want = (records + kBlock - 1) / kBlock;
-  dim3 grid((unsigned)std::min<long long>(want, 8192), ninst);
-  if (fp32)
-    hipLaunchKernelGGL(k_direct_acc<float>, grid, dim3(kBlock), 0, s, insts, m, first);
-  else
-    hipLaunchKernelGGL(k_direct_acc<double>, grid, dim3(kBlock), 0, s, insts, m, first);
   return hipGetLastError();
 }
 
