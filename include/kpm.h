@@ -122,6 +122,29 @@ int32_t kpm_probe_count(const kpm_lattice* lat, const kpm_probes* probes);
 int kpm_build_H(const kpm_lattice* lat, const kpm_model* model, const double* n,
                 const double* chi, const double* delta, double* h, void* stream);
 
+/* Build h for a collinear spin-density-wave state (App. A at m_i != 0,
+ * magnetisation along z): per spin s = up/down the densities n_s [N], bond
+ * variables chi_s = <c^dag_{i s} c_{j s}> [4][N] and Delta_s = s <c_{i s} c_{j -s}>
+ * [4][N] (complex; both pairing components are nearest-neighbour only in W).
+ * h_IJ = dW/drho_IJ (Wirtinger) with rho_{i0,j0} = chi_up, rho_{i1,j1} =
+ * -conj(chi_dn), rho_{i0,j1} = -conj(Delta_up), rho_{i1,j0} = -Delta_dn,
+ * rho_{i0,i0} = n_up, rho_{i1,i1} = 1 - n_dn, for
+ *   W = - sum_bonds sum_s g^t_{i s} g^t_{j s} 2 Re(t_ij chi_s)
+ *       + J sum_nn [g^z_ij (m_i m_j - (1/4) sum_s (|chi_s|^2 + |Delta_s|^2))
+ *                   - g^xy_ij Re(chi_up conj(chi_dn) + conj(Delta_up) Delta_dn)]
+ *       - mu sum_i n_i,
+ * the energy of the renormalised Hamiltonian of App. A in the BdG Slater
+ * determinant (Wick's theorem), with the printed g^t_{i s}, g^xy_i, X_ij and
+ * g^z_ij = g^xy_ij [2(|Dbar|^2 - |chibar|^2) - 4 m_i m_j X^2] / [2(|Dbar|^2 -
+ * |chibar|^2) - 4 m_i m_j] (squares read as moduli; chibar, Dbar the spin
+ * means).  Its derivatives are the printed eqs. Tij, Dij and mu_i.  At m = 0
+ * with equal spins it is kpm_build_H.  The g^z ratio is singular where its
+ * denominator vanishes; h is then non-finite (no check here; the recursion
+ * reports it). */
+int kpm_build_H_sdw(const kpm_lattice* lat, const kpm_model* model, const double* n_up,
+                    const double* n_dn, const double* chi_up, const double* chi_dn,
+                    const double* delta_up, const double* delta_dn, double* h, void* stream);
+
 /* Vector-Jacobian product of kpm_build_H: given rho = dOmega/dh on the
  * stencil ([19][N] complex), writes dOmega/dtheta = sum_IJ rho_IJ dh_IJ/dtheta
  * over all matrix elements (both halves).  Complex gradients use the

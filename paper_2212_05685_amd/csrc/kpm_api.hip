@@ -19,6 +19,8 @@ hipError_t launch_build_h(const ModelDev&, const double*, const double*, const d
                           hipStream_t);
 hipError_t launch_build_vjp(const ModelDev&, const double*, const double*, const double*,
                             const double*, double*, double*, double*, hipStream_t);
+hipError_t launch_build_sdw(const ModelDev&, const double*, const double*, const double*,
+                            const double*, const double*, const double*, double*, hipStream_t);
 hipError_t launch_bounds(int, int, const double*, double*, hipStream_t);
 hipError_t launch_rescale(const InstDev*, const int4*, int, bool, hipStream_t);
 hipError_t launch_coeffs(int, int, double, const double*, double*, hipStream_t);
@@ -506,6 +508,19 @@ int kpm_build_H(const kpm_lattice* lat, const kpm_model* model, const double* n,
   ModelDev md{lat->Lx, lat->Ly, lat->n_vortex, lat->Lx * lat->Ly, model->t, model->tp, model->J,
               model->mu};
   KPM_HIP(launch_build_h(md, n, chi, delta, h, static_cast<hipStream_t>(stream)));
+  return KPM_OK;
+}
+
+int kpm_build_H_sdw(const kpm_lattice* lat, const kpm_model* model, const double* n_up,
+                    const double* n_dn, const double* chi_up, const double* chi_dn,
+                    const double* delta_up, const double* delta_dn, double* h, void* stream) {
+  if (!valid_lattice(lat) || !model || !n_up || !n_dn || !chi_up || !chi_dn || !delta_up ||
+      !delta_dn || !h)
+    return KPM_EINVAL;
+  ModelDev md{lat->Lx, lat->Ly, lat->n_vortex, lat->Lx * lat->Ly, model->t, model->tp, model->J,
+              model->mu};
+  KPM_HIP(launch_build_sdw(md, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, h,
+                           static_cast<hipStream_t>(stream)));
   return KPM_OK;
 }
 

@@ -123,6 +123,170 @@ __global__ __launch_bounds__(kBlock) void k_build_h(ModelDev md, const double* _
   h[(long long)18 * N + i] = make_double2(0.0, 0.0);
 }
 
+// ------------------------------------------------ spin-polarised builder
+// Collinear magnetisation (App. A at m_i != 0).  Per spin s = +1 (up), -1
+// (down): n_s, chi_s, Delta_s = s <c_s c_-s>.  With delta = 1 - n,
+// m = (n_up - n_dn)/2, A = 1 - delta^2 + 4 m^2, the energy of one bond is
+//   W_b = - sum_s g^t_{i s} g^t_{j s} 2 Re(t chi_s)
+//         + J [g^z Szz + g^xy_ij Sxy]                 (nearest neighbours only),
+//   Szz = m_i m_j - (1/4) sum_s (|chi_s|^2 + |Delta_s|^2),
+//   Sxy = - Re(chi_up conj(chi_dn) + conj(Delta_up) Delta_dn),
+//   g^z = g^xy_ij R,  R = (b - 4 mm X^2)/(b - 4 mm),  mm = m_i m_j,
+//   b = 2 (|Dbar|^2 - |chibar|^2),  X = 1 + 12 n_i n_j / sqrt(A_i A_j),
+// plus -mu sum_i n_i.  h_IJ = dW/drho_IJ as for kpm_build_H, written out by
+// the chain rule through (delta, m) of each site.
+struct SiteS {
+  double n, m, A, gxy, gt[2];        // gt[0] spin up, gt[1] spin down
+  double dA[2], dgxy[2], dgt[2][2];  // d/dn_up (index 0), d/dn_dn (index 1)
+};
+
+__device__ __forceinline__ SiteS site_s(double nu, double nd) {
+  SiteS f;
+  f.n = nu + nd;
+  const double dl = 1.0 - f.n;
+  f.m = 0.5 * (nu - nd);
+  f.A = 1.0 - dl * dl + 4.0 * f.m * f.m;
+  f.gxy = 2.0 * f.n / f.A;
+  const double B = 2.0 * dl * (1.0 - dl) / f.A;
+  for (int q = 0; q < 2; ++q) {                         // derivative w.r.t. n_up (q = 0) or n_dn
+    const double sq = q == 0 ? 1.0 : -1.0;
+    f.dA[q] = 2.0 * dl + 4.0 * sq * f.m;
+    f.dgxy[q] = (2.0 * f.A - 2.0 * f.n * f.dA[q]) / (f.A * f.A);
+  }
+  for (int s = 0; s < 2; ++s) {
+    const double ss = s == 0 ? 1.0 : -1.0;
+    const double p = 1.0 + dl + 2.0 * ss * f.m, qd = 1.0 + dl - 2.0 * ss * f.m;
+    const double Q = p / qd;
+    f.gt[s] = sqrt(B * Q);
+    for (int q = 0; q < 2; ++q) {
+      const double sq = q == 0 ? 1.0 : -1.0;
+      const double dB = (2.0 * (2.0 * dl - 1.0) * f.A - 2.0 * dl * (1.0 - dl) * f.dA[q]) / (f.A * f.A);
+      const double dp = -1.0 + ss * sq, dq = -1.0 - ss * sq;
+      const double dQ = (dp * qd - p * dq) / (qd * qd);
+      f.dgt[s][q] = (dB * Q + B * dQ) / (2.0 * f.gt[s]);
+    }
+  }
+  return f;
+}
+
+struct BondIn {
+  double2 t, cu, cd, du, dd;
+};
+
+// dW_b/dn_{a q} for the end a of a bond whose other end is b (W_b is
+// symmetric in its two ends).
+__device__ __forceinline__ void bond_dn(const SiteS& a, const SiteS& b, const BondIn& v, bool nn,
+                                        double J, double out[2]) {
+  const double Ru = v.t.x * v.cu.x - v.t.y * v.cu.y, Rd = v.t.x * v.cd.x - v.t.y * v.cd.y;
+  for (int q = 0; q < 2; ++q)
+    out[q] = -2.0 * (Ru * b.gt[0] * a.dgt[0][q] + Rd * b.gt[1] * a.dgt[1][q]);
+  if (!nn) return;
+  const double cbx = 0.5 * (v.cu.x + v.cd.x), cby = 0.5 * (v.cu.y + v.cd.y);
+  const double dbx = 0.5 * (v.du.x + v.dd.x), dby = 0.5 * (v.du.y + v.dd.y);
+  const double bb = 2.0 * (dbx * dbx + dby * dby - cbx * cbx - cby * cby);
+  const double mm = a.m * b.m;
+  const double sAB = sqrt(a.A * b.A);
+  const double X = 1.0 + 12.0 * a.n * b.n / sAB;
+  const double den = bb - 4.0 * mm;
+  const double R = (bb - 4.0 * mm * X * X) / den;
+  const double dRdmm = 4.0 * bb * (1.0 - X * X) / (den * den);
+  const double dRdX = -8.0 * mm * X / den;
+  const double gxy = a.gxy * b.gxy, gz = gxy * R;
+  const double q2 = v.cu.x * v.cu.x + v.cu.y * v.cu.y + v.cd.x * v.cd.x + v.cd.y * v.cd.y +
+                    v.du.x * v.du.x + v.du.y * v.du.y + v.dd.x * v.dd.x + v.dd.y * v.dd.y;
+  const double Szz = mm - 0.25 * q2;
+  const double Sxy = -((v.cu.x * v.cd.x + v.cu.y * v.cd.y) + (v.du.x * v.dd.x + v.du.y * v.dd.y));
+  for (int q = 0; q < 2; ++q) {
+    const double sq = q == 0 ? 1.0 : -1.0;
+    const double dmm = 0.5 * sq * b.m;
+    const double dX = 12.0 * b.n * (1.0 / sAB - a.n * a.dA[q] / (2.0 * a.A * sAB));
+    const double dgxy = b.gxy * a.dgxy[q];
+    const double dgz = dgxy * R + gxy * (dRdmm * dmm + dRdX * dX);
+    out[q] += J * (dgz * Szz + gz * dmm + dgxy * Sxy);
+  }
+}
+
+// Wirtinger derivatives dW_b/dz of the bond variables z = chi_up, chi_dn,
+// Delta_up, Delta_dn (order of `g`).
+__device__ __forceinline__ void bond_dz(const SiteS& a, const SiteS& b, const BondIn& v, bool nn,
+                                        double J, double2 g[4]) {
+  g[0] = make_double2(-a.gt[0] * b.gt[0] * v.t.x, -a.gt[0] * b.gt[0] * v.t.y);
+  g[1] = make_double2(-a.gt[1] * b.gt[1] * v.t.x, -a.gt[1] * b.gt[1] * v.t.y);
+  g[2] = make_double2(0.0, 0.0);
+  g[3] = make_double2(0.0, 0.0);
+  if (!nn) return;
+  const double cbx = 0.5 * (v.cu.x + v.cd.x), cby = 0.5 * (v.cu.y + v.cd.y);
+  const double dbx = 0.5 * (v.du.x + v.dd.x), dby = 0.5 * (v.du.y + v.dd.y);
+  const double bb = 2.0 * (dbx * dbx + dby * dby - cbx * cbx - cby * cby);
+  const double mm = a.m * b.m;
+  const double X = 1.0 + 12.0 * a.n * b.n / sqrt(a.A * b.A);
+  const double den = bb - 4.0 * mm;
+  const double R = (bb - 4.0 * mm * X * X) / den;
+  const double dRdb = 4.0 * mm * (X * X - 1.0) / (den * den);
+  const double gxy = a.gxy * b.gxy, gz = gxy * R;
+  const double q2 = v.cu.x * v.cu.x + v.cu.y * v.cu.y + v.cd.x * v.cd.x + v.cd.y * v.cd.y +
+                    v.du.x * v.du.x + v.du.y * v.du.y + v.dd.x * v.dd.x + v.dd.y * v.dd.y;
+  const double Szz = mm - 0.25 * q2;
+  // d b/d chi_s = -conj(chibar), d b/d Delta_s = conj(Dbar)
+  const double k = J * gxy * dRdb * Szz;
+  g[0].x += k * (-cbx) + J * (-0.25 * gz * v.cu.x - 0.5 * gxy * v.cd.x);
+  g[0].y += k * (cby) + J * (0.25 * gz * v.cu.y + 0.5 * gxy * v.cd.y);
+  g[1].x += k * (-cbx) + J * (-0.25 * gz * v.cd.x - 0.5 * gxy * v.cu.x);
+  g[1].y += k * (cby) + J * (0.25 * gz * v.cd.y + 0.5 * gxy * v.cu.y);
+  g[2].x += k * (dbx) + J * (-0.25 * gz * v.du.x - 0.5 * gxy * v.dd.x);
+  g[2].y += k * (-dby) + J * (0.25 * gz * v.du.y + 0.5 * gxy * v.dd.y);
+  g[3].x += k * (dbx) + J * (-0.25 * gz * v.dd.x - 0.5 * gxy * v.du.x);
+  g[3].y += k * (-dby) + J * (0.25 * gz * v.dd.y + 0.5 * gxy * v.du.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_build_sdw(ModelDev md, const double* __restrict__ nu,
+                                                      const double* __restrict__ nd,
+                                                      const double* __restrict__ cu,
+                                                      const double* __restrict__ cd,
+                                                      const double* __restrict__ du,
+                                                      const double* __restrict__ dd,
+                                                      double2* __restrict__ h) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= md.N) return;
+  const int N = md.N;
+  const SiteS fi = site_s(nu[i], nd[i]);
+  double eu = -md.mu, ed = -md.mu;
+  for (int d = 0; d < 4; ++d) {
+    const bool nn = d < 2;
+    // forward bond (i, j = i + d), stored here
+    {
+      const int j = nbr_of(i, d, +1, md.Lx, md.Ly);
+      const SiteS fj = site_s(nu[j], nd[j]);
+      const long long e = (long long)d * N + i;
+      const BondIn v{hop(md, i, d), ld2(cu, e), ld2(cd, e), ld2(du, e), ld2(dd, e)};
+      double2 g[4];
+      bond_dz(fi, fj, v, nn, md.J, g);
+      h[(long long)(4 * d + 0) * N + i] = g[0];                               // dW/dchi_up
+      h[(long long)(4 * d + 1) * N + i] = make_double2(-g[2].x, g[2].y);      // -conj dW/dDelta_up
+      h[(long long)(4 * d + 2) * N + i] = make_double2(-g[3].x, -g[3].y);     // -dW/dDelta_dn
+      h[(long long)(4 * d + 3) * N + i] = make_double2(-g[1].x, g[1].y);      // -conj dW/dchi_dn
+      double o[2];
+      bond_dn(fi, fj, v, nn, md.J, o);
+      eu += o[0];
+      ed += o[1];
+    }
+    // backward bond (k = i - d, i), stored at k
+    {
+      const int k = nbr_of(i, d, -1, md.Lx, md.Ly);
+      const SiteS fk = site_s(nu[k], nd[k]);
+      const long long e = (long long)d * N + k;
+      const BondIn v{hop(md, k, d), ld2(cu, e), ld2(cd, e), ld2(du, e), ld2(dd, e)};
+      double o[2];
+      bond_dn(fi, fk, v, nn, md.J, o);
+      eu += o[0];
+      ed += o[1];
+    }
+  }
+  h[(long long)16 * N + i] = make_double2(eu, 0.0);
+  h[(long long)17 * N + i] = make_double2(-ed, 0.0);
+  h[(long long)18 * N + i] = make_double2(0.0, 0.0);
+}
+
 // Per-site pieces of the VJP that every neighbour needs: w_i = Re rho16 -
 // Re rho17 (weight of eps_i in the linearised energy).
 __device__ __forceinline__ double onsite_w(const double2* rho, int N, int i) {
@@ -370,6 +534,15 @@ hipError_t launch_build_h(const ModelDev& md, const double* n, const double* chi
                           const double* dlt, double* h, hipStream_t s) {
   dim3 grid((md.N + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_build_h, grid, dim3(kBlock), 0, s, md, n, chi, dlt,
+                     reinterpret_cast<double2*>(h));
+  return hipGetLastError();
+}
+
+hipError_t launch_build_sdw(const ModelDev& md, const double* nu, const double* nd, const double* cu,
+                            const double* cd, const double* du, const double* dd, double* h,
+                            hipStream_t s) {
+  dim3 grid((md.N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_build_sdw, grid, dim3(kBlock), 0, s, md, nu, nd, cu, cd, du, dd,
                      reinterpret_cast<double2*>(h));
   return hipGetLastError();
 }

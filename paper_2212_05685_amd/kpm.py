@@ -37,7 +37,7 @@ EXPORTS = (
     "kpm_density_matrix", "kpm_status_read", "kpm_batch_create", "kpm_batch_energy_grad",
     "kpm_batch_destroy", "kpm_set_probe_block", "kpm_profile_begin", "kpm_profile_end",
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
-    "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos",
+    "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
 )
 
 
@@ -86,6 +86,7 @@ def _load():
         "kpm_probe_count": (c_int32, [POINTER(Lattice), POINTER(Probes)]),
         "kpm_build_H": (c_int32, [POINTER(Lattice), POINTER(Model), P, P, P, P, P]),
         "kpm_build_H_vjp": (c_int32, [POINTER(Lattice), POINTER(Model), P, P, P, P, P, P, P, P]),
+        "kpm_build_H_sdw": (c_int32, [POINTER(Lattice), POINTER(Model), P, P, P, P, P, P, P, P]),
         "kpm_bounds": (c_int32, [POINTER(Lattice), P, P, P]),
         "kpm_coefficients": (c_int32, [c_int32, c_double, P, c_int32, P, P]),
         "kpm_workspace_size": (c_size_t, [POINTER(Lattice), c_int32, c_int32, c_int32, c_int32]),
@@ -205,6 +206,17 @@ def kpm_build_H(lat, mdl, n, chi, delta, h, stream=None):
                             _ptr(chi, torch.complex128, 4 * N, "chi"),
                             _ptr(delta, torch.complex128, 4 * N, "delta"),
                             _ptr(h, torch.complex128, NENT * N, "h"), _stream(stream)), "kpm_build_H")
+
+
+def kpm_build_H_sdw(lat, mdl, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, h, stream=None):
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_build_H_sdw(ctypes.byref(lat), ctypes.byref(mdl),
+                                _ptr(n_up, torch.float64, N, "n_up"), _ptr(n_dn, torch.float64, N, "n_dn"),
+                                _ptr(chi_up, torch.complex128, 4 * N, "chi_up"),
+                                _ptr(chi_dn, torch.complex128, 4 * N, "chi_dn"),
+                                _ptr(delta_up, torch.complex128, 4 * N, "delta_up"),
+                                _ptr(delta_dn, torch.complex128, 4 * N, "delta_dn"),
+                                _ptr(h, torch.complex128, NENT * N, "h"), _stream(stream)), "kpm_build_H_sdw")
 
 
 def kpm_build_H_vjp(lat, mdl, n, chi, delta, rho, dn, dchi, ddelta, stream=None):

@@ -1,0 +1,57 @@
+"""GPU parity of the spin-polarised builder (kpm_build_H_sdw) against the
+oracle (oracle/sdw.py: autograd of the reconstructed W), through the C ABI.
+
+* 17 x 19 (ragged 256-site chunks) and 100 x 100 with two vortices, staggered
+  magnetisation m = 0, 0.03, 0.06 and spin-dependent bond noise: every
+  stencil entry to 1e-12 of max |h|;
+* the SDW h through the rest of the path: FP64 energy + gradient of a small
+  lattice against the oracle's plain KPM on the oracle's own h, 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import builder, chebyshev, sdw
+from tests import helpers as H
+from tests.gpu_helpers import dev, host, problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_h(cfg, th):
+    from paper_2212_05685_amd import kpm
+    lat = kpm.lattice(cfg.Lx, cfg.Ly, cfg.n_v)
+    mdl = kpm.model(cfg.t, cfg.tp, cfg.J, cfg.mu)
+    h = torch.zeros(19, cfg.N, dtype=torch.complex128, device="cuda")
+    kpm.kpm_build_H_sdw(lat, mdl, *(dev(x) for x in th), h)
+    return h
+
+
+@pytest.mark.parametrize("Lx,Ly", [(17, 19), (100, 100)])
+@pytest.mark.parametrize("m_amp", [0.0, 0.03, 0.06])
+def test_sdw_builder_against_oracle(Lx, Ly, m_amp):
+    cfg = wl.Config("s", Lx, Ly, 2, 0.15, 8, (wl.ProbeSpec("unit", 1),), vortex=True,
+                    complex_noise=0.02, seed=Lx + 3)
+    th = wl.make_theta_sdw(cfg, m_amp)
+    ref = sdw.build_stencil_sdw(Lx, Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, *th)
+    got = host(_gpu_h(cfg, th))
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_sdw_energy_grad_against_oracle():
+    cfg = wl.Config("s", 12, 10, 2, 0.15, 64, (wl.ProbeSpec("colored_z4", 1, 9, 4, 5, 1, 0, 1.0),),
+                    "fp64", ckpt_k=8, vortex=True, complex_noise=0.02)
+    th = wl.make_theta_sdw(cfg, 0.05)
+    st = sdw.build_stencil_sdw(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, *th)
+    a, b = H.bounds(cfg, st)
+    C = chebyshev.kpm_coefficients(cfg.M, cfg.T, a, b)
+    ref = H.plain(cfg, st, a, b, C)
+    pb = problem(cfg, precision="fp64")
+    h = _gpu_h(cfg, th)
+    ab = pb.bounds(h)
+    assert np.allclose(host(ab), [a, b], rtol=1e-12)
+    out = pb.density_matrix(h, ab, dev(C))
+    assert pb.status() == 0
+    assert abs(float(host(out["omega"])[0]) - ref["omega"]) < 1e-10 * abs(ref["omega"])
+    assert H.rel_err(host(out["rho"]), ref["rho"]) < 1e-10

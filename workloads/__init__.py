@@ -170,6 +170,27 @@ def make_theta(cfg: Config):
     return n, chi, dlt
 
 
+def make_theta_sdw(cfg: Config, m_amp: float = 0.03, spin_noise: float = 0.01):
+    """Per-spin inputs of a collinear SDW state: the seed of ``make_theta``
+    with a staggered magnetisation m_i = m_amp (-1)^(x+y) (1 + 0.2 u_i), u_i
+    uniform in [-1, 1], split as n_up/dn = n/2 +- m_i, and seeded complex
+    spin-dependent noise of amplitude spin_noise on chi and Delta.
+    Returns (n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn)."""
+    n, chi, dlt = make_theta(cfg)
+    rng = np.random.default_rng(cfg.seed + 77)
+    N = cfg.N
+    x = np.arange(N) % cfg.Lx
+    y = np.arange(N) // cfg.Lx
+    m = m_amp * np.where((x + y) % 2 == 0, 1.0, -1.0) * (1.0 + 0.2 * rng.uniform(-1, 1, N))
+
+    def noise():
+        a = spin_noise
+        return rng.uniform(-a, a, (4, N)) + 1j * rng.uniform(-a, a, (4, N))
+
+    mask = np.array([1.0, 1.0, 0.0, 0.0])[:, None]
+    return (n / 2 + m, n / 2 - m, chi + noise(), chi + noise(), dlt + mask * noise(), dlt + mask * noise())
+
+
 def _seed(idx: int) -> int:
     return BASE_SEED + idx
 
