@@ -435,6 +435,34 @@ def ldos_form(steps: int, prob, th, cfg):
             "finite": bool(torch.isfinite(out).all().item()), "min": float(out.min().item())}
 
 
+def sdw_form(reps: int, cfg):
+    """The spin-polarised builder against the singlet one on the 100x100
+    lattice (staggered m = 0.03 seed); per-call time from HIP events."""
+    import torch
+    from paper_2212_05685_amd import kpm
+    import workloads as wl
+
+    lat = kpm.lattice(cfg.Lx, cfg.Ly, cfg.n_v)
+    mdl = kpm.model(cfg.t, cfg.tp, cfg.J, cfg.mu)
+    th = [torch.from_numpy(x).cuda() for x in wl.make_theta_sdw(cfg, 0.03)]
+    n, chi, dlt = (torch.from_numpy(x).cuda() for x in wl.make_theta(cfg))
+    h = torch.zeros(19, cfg.N, dtype=torch.complex128, device="cuda")
+    out = {}
+    for name, fn in (("singlet", lambda: kpm.kpm_build_H(lat, mdl, n, chi, dlt, h)),
+                     ("sdw", lambda: kpm.kpm_build_H_sdw(lat, mdl, *th, h))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps * 1e3
+    log(f"builders: singlet {out['singlet']:.1f} us, sdw {out['sdw']:.1f} us")
+    return {"us_build_singlet": out["singlet"], "us_build_sdw": out["sdw"],
+            "h_bytes_written": 19 * 16 * cfg.N}
+
+
 def cpu_baseline(cfg, quiet=False):
     """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
     probe of the same workload, single thread."""
@@ -584,6 +612,7 @@ def main():
         result["direct_form"] = direct_form(args.steps, prob, th, dt)
         result["doubling_form"] = doubling_form(args.steps, prob, th)
         result["ldos_form"] = ldos_form(args.steps, prob, th, cfg)
+        result["sdw_form"] = sdw_form(50, cfg)
 
     if not args.no_fp64_form:
         del prob
