@@ -35,6 +35,11 @@ readings used here, step by step:
    (dX_j + mix dF_j); the first iteration of a call, and any iteration whose
    differences are all zero, is a linear step.
 
+A spin-polarised theta (six arrays: n_up, n_dn, chi_up, chi_dn, Delta_up,
+Delta_dn, for the builder of ``sdw``) takes the same steps with the per-spin map
+of ``sdw.order_parameters_sdw`` in place of step 1 (no spin average), the
+mean density from n_up + n_dn.
+
 ``rho_fn(theta, mu) -> (omega, rho)`` supplies the density matrix: the plain
 KPM of ``kpm_plain`` (the path's own truncation and probes; the adjoint), the
 direct probing estimate of ``kpm_direct``, or the exact dense Fermi-function
@@ -46,7 +51,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import builder, chebyshev, dense, kpm_direct, kpm_plain, mapping
+from . import builder, chebyshev, dense, kpm_direct, kpm_plain, mapping, sdw
 
 
 class NoConvergence(RuntimeError):
@@ -81,36 +86,53 @@ def singlet_theta(rho):
     return n, chi, dlt
 
 
+def spin_theta(rho):
+    """Step 1 for a spin-polarised theta: the per-spin order parameters."""
+    op = sdw.order_parameters_sdw(rho)
+    return (op["n_up"], op["n_dn"], op["chi_up"], op["chi_dn"], op["delta_up"], op["delta_dn"])
+
+
+def mapped(rho, theta):
+    return spin_theta(rho) if len(theta) == 6 else singlet_theta(rho)
+
+
 def measure(rho, theta):
     """Step 2: (nbar, residual) of rho against the current theta."""
-    n1, c1, d1 = singlet_theta(rho)
-    n0, c0, d0 = theta
-    res = max(np.max(np.abs(n1 - n0)), np.max(np.abs(c1 - c0)), np.max(np.abs(d1 - d0)))
-    return float(np.mean(n1)), float(res)
+    new = mapped(rho, theta)
+    res = max(np.max(np.abs(a - b)) for a, b in zip(new, theta))
+    nbar = np.mean(new[0] + new[1]) if len(theta) == 6 else np.mean(new[0])
+    return float(nbar), float(res)
 
 
 def update(rho, theta, mix):
     """Step 4: theta + mix (theta' - theta), with (nbar, residual) of step 2."""
-    n1, c1, d1 = singlet_theta(rho)
-    n0, c0, d0 = theta
+    new = mapped(rho, theta)
     nbar, res = measure(rho, theta)
-    new = (n0 + mix * (n1 - n0), c0 + mix * (c1 - c0), d0 + mix * (d1 - d0))
-    return new, nbar, res
+    return tuple(a + mix * (b - a) for a, b in zip(theta, new)), nbar, res
 
 
 def pack(theta):
-    """Flat real vector (n, chi as interleaved re/im, Delta as interleaved re/im)."""
-    n, chi, dlt = theta
-    return np.concatenate([np.asarray(n, dtype=np.float64),
-                           np.ascontiguousarray(chi, dtype=np.complex128).ravel().view(np.float64),
-                           np.ascontiguousarray(dlt, dtype=np.complex128).ravel().view(np.float64)])
+    """Flat real vector of theta's arrays in order (real arrays as they are,
+    complex ones as interleaved re/im): (n, chi, Delta) or (n_up, n_dn,
+    chi_up, chi_dn, Delta_up, Delta_dn)."""
+    parts = []
+    for a in theta:
+        a = np.asarray(a)
+        parts.append(np.ascontiguousarray(a, dtype=np.complex128).ravel().view(np.float64)
+                     if np.iscomplexobj(a) else np.asarray(a, dtype=np.float64).ravel())
+    return np.concatenate(parts)
 
 
-def unpack(x, N):
-    n = x[:N].copy()
-    chi = x[N:9 * N].copy().view(np.complex128).reshape(4, N)
-    dlt = x[9 * N:].copy().view(np.complex128).reshape(4, N)
-    return n, chi, dlt
+def unpack(x, N, spin=False):
+    nreal = 2 if spin else 1
+    out, o = [], 0
+    for _ in range(nreal):
+        out.append(x[o:o + N].copy())
+        o += N
+    for _ in range(4 if spin else 2):
+        out.append(x[o:o + 8 * N].copy().view(np.complex128).reshape(4, N))
+        o += 8 * N
+    return tuple(out)
 
 
 class Anderson:
@@ -217,7 +239,7 @@ def iterate(rho_fn, theta, mu, prm: Params, n_iter: int):
             theta, _, _ = update(rho, theta, prm.mix)
         else:
             x = pack(theta)
-            theta = unpack(acc.step(x, pack(singlet_theta(rho)) - x), len(theta[0]))
+            theta = unpack(acc.step(x, pack(mapped(rho, theta)) - x), len(theta[0]), len(theta) == 6)
         hist.append({"mu": mu, "nbar": nbar, "residual": res, "omega": omega, "evals": evals})
         if prm.tol_residual > 0.0 and res <= prm.tol_residual:
             break
@@ -249,6 +271,28 @@ def direct_rho_fn(Lx, Ly, n_v, t, tp, J, T, M, probes, weights, K=None):
         C = chebyshev.kpm_coefficients(M, T, a, b, K)
         out = kpm_direct.direct_rho(Hs, a, b, probes, weights, C, Lx, Ly)
         return float(out["omega"]), out["rho"]
+    return fn
+
+
+def sdw_kpm_rho_fn(Lx, Ly, n_v, t, tp, J, T, M, probes, weights, K=None):
+    """Plain KPM on the spin-polarised builder's h (theta of six arrays)."""
+    def fn(theta, mu):
+        st = sdw.build_stencil_sdw(Lx, Ly, n_v, t, tp, J, mu, *theta)
+        Hs = builder.sparse_from_stencil(st, Lx, Ly)
+        a, b = chebyshev.rescale(*chebyshev.gershgorin_sparse(Hs))
+        C = chebyshev.kpm_coefficients(M, T, a, b, K)
+        out = kpm_plain.plain_kpm(Hs, a, b, probes, weights, C, Lx, Ly, want_grad=True)
+        return float(out["omega"]), out["rho"]
+    return fn
+
+
+def sdw_exact_rho_fn(Lx, Ly, n_v, t, tp, J, T):
+    """Exact Fermi-function rho of the spin-polarised builder's h."""
+    def fn(theta, mu):
+        st = sdw.build_stencil_sdw(Lx, Ly, n_v, t, tp, J, mu, *theta)
+        H = builder.dense_from_stencil(st, Lx, Ly)
+        omega, rho = dense.exact(H, T)
+        return omega, builder.stencil_from_dense(rho, Lx, Ly)
     return fn
 
 

@@ -230,3 +230,33 @@ def test_anderson_loop_converges_faster(fixed_point):
     _, _, h_lin = rmft.iterate(fn, th, mu_k, rmft.Params(**base), 12)
     _, _, h_and = rmft.iterate(fn, th, mu_k, rmft.Params(**base, anderson=5), 12)
     assert h_and[-1]["residual"] < 0.3 * h_lin[-1]["residual"], (h_and[-1], h_lin[-1])
+
+
+def test_spin_loop_reduces_to_singlet_loop():
+    """A spin-polarised theta with equal spins follows the singlet iteration:
+    the per-spin map of an SU(2)-symmetric h returns equal spins, and the
+    singlet average of equal spins is each of them."""
+    cfg = wl.Config("v", 6, 4, 2, 0.16, 32, (wl.ProbeSpec("unit", 48),), vortex=True, complex_noise=0.01,
+                    chi0=0.0)
+    n, chi, dlt = wl.make_theta(cfg)
+    prm = rmft.Params(doping=0.16, mix=0.3, tol_n=1e-9, tol_mu=1e-12, mu_step=0.01, max_evals=80)
+    fs = rmft.exact_rho_fn(6, 4, 2, T_, TP, J, TEMP)
+    fp = rmft.sdw_exact_rho_fn(6, 4, 2, T_, TP, J, TEMP)
+    th_s, mu_s, h_s = rmft.iterate(fs, (n, chi, dlt), cfg.mu, prm, 2)
+    th_p, mu_p, h_p = rmft.iterate(fp, (n / 2, n / 2, chi, chi, dlt, dlt), cfg.mu, prm, 2)
+    assert abs(mu_s - mu_p) < 1e-9
+    assert np.abs(th_p[0] + th_p[1] - th_s[0]).max() < 1e-9
+    for a, b in ((th_p[2], th_s[1]), (th_p[3], th_s[1]), (th_p[4], th_s[2]), (th_p[5], th_s[2])):
+        assert np.abs(a - b).max() < 1e-9
+    assert [x["evals"] for x in h_s] == [x["evals"] for x in h_p]
+
+
+def test_pack_six_arrays():
+    rng = np.random.default_rng(3)
+    N = 5
+    th = (rng.normal(size=N), rng.normal(size=N)) + tuple(
+        rng.normal(size=(4, N)) + 1j * rng.normal(size=(4, N)) for _ in range(4))
+    x = rmft.pack(th)
+    assert x.shape == (34 * N,)
+    for a, b in zip(rmft.unpack(x, N, spin=True), th):
+        assert np.array_equal(a, b)
