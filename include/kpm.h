@@ -371,8 +371,10 @@ typedef struct {      /* one completed iteration (host memory)                  
   int32_t pad;
 } kpm_rmft_record;
 
-/* Workspace bytes of kpm_rmft_iterate (the kpm_workspace_size region first,
- * then h, rho, ab, C and stats).  0 on invalid arguments. */
+/* Workspace bytes of kpm_rmft_iterate and kpm_rmft_iterate_sdw (the
+ * kpm_workspace_size region first, then h, rho, ab, C, stats and the Anderson
+ * vectors, sized for the 34 N doubles of a spin-polarised theta).  0 on
+ * invalid arguments. */
 size_t kpm_rmft_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int32_t ckpt_k,
                                int32_t precision);
 
@@ -415,6 +417,34 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
                      const kpm_rmft_params* params, int32_t n_iter, double* n, double* chi,
                      double* delta, double* mu, kpm_rmft_record* history, int32_t* n_done,
                      void* ws, size_t ws_bytes, void* stream);
+
+/* Per-spin map for a collinear spin-polarised theta (App. A at m_i != 0, the
+ * inverse of the rho entries of kpm_build_H_sdw; no spin average), for every
+ * site i and bond (i, j = i + d), d = 0..3:
+ *   n'_up = rho_{i0,i0},           n'_dn = 1 - rho_{i1,i1},
+ *   chi'_up = rho_{i0,j0},         chi'_dn = -conj(rho_{i1,j1}),
+ *   delta'_up = -conj(rho_{i0,j1}), delta'_dn = -rho_{i1,j0},
+ * then theta <- theta + mix (theta' - theta) in place, as kpm_rmft_update:
+ * stats [0] = (1/N) sum_i (n'_up + n'_dn), [1] = max over all components of
+ * |theta' - theta| (theta before the update).  For equal spins the spin
+ * means of theta' are the singlet map of kpm_rmft_update.  Layouts of
+ * kpm_build_H_sdw. */
+int kpm_rmft_update_sdw(const kpm_lattice* lat, const double* rho, double mix, double* n_up,
+                        double* n_dn, double* chi_up, double* chi_dn, double* delta_up,
+                        double* delta_dn, double* stats, void* stream);
+
+/* kpm_rmft_iterate for a spin-polarised theta: each evaluation builds h with
+ * kpm_build_H_sdw and measures with kpm_rmft_update_sdw (mix = 0); the update
+ * is kpm_rmft_update_sdw with `mix`, or Anderson mixing on the flat vector
+ * x = (n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn as interleaved re/im),
+ * 34 N doubles.  The mu search, arguments, workspace and returns are those
+ * of kpm_rmft_iterate. */
+int kpm_rmft_iterate_sdw(const kpm_lattice* lat, const kpm_model* model, const kpm_probes* probes,
+                         int32_t M, double T, int32_t precision, int32_t ckpt_k,
+                         const kpm_rmft_params* params, int32_t n_iter, double* n_up,
+                         double* n_dn, double* chi_up, double* chi_dn, double* delta_up,
+                         double* delta_dn, double* mu, kpm_rmft_record* history, int32_t* n_done,
+                         void* ws, size_t ws_bytes, void* stream);
 
 /* ---- measurement ----------------------------------------------------------
  * Between kpm_profile_begin and kpm_profile_end, one in `sample_every`

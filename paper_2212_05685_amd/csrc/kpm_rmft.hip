@@ -122,6 +122,82 @@ __global__ __launch_bounds__(kRB) void k_and_resid(int N, const double2* __restr
   }
 }
 
+// Spin-polarised theta: the per-spin map (no spin average),
+//   n'_up = rho_{i0,i0}, n'_dn = 1 - rho_{i1,i1}, chi'_up = rho_{i0,j0},
+//   chi'_dn = -conj rho_{i1,j1}, Delta'_up = -conj rho_{i0,j1}, Delta'_dn = -rho_{i1,j0},
+// with the mixing, mean density and residual of k_rmft_map.
+__global__ __launch_bounds__(kRB) void k_rmft_map_sdw(int N, const double2* __restrict__ rho, double mix,
+                                                      double* __restrict__ nu, double* __restrict__ nd,
+                                                      double2* __restrict__ cu, double2* __restrict__ cd,
+                                                      double2* __restrict__ du, double2* __restrict__ dd,
+                                                      double* __restrict__ part) {
+  double nsum = 0.0, res = 0.0;
+  const bool write = mix != 0.0;
+  for (int i = blockIdx.x * kRB + threadIdx.x; i < N; i += gridDim.x * kRB) {
+    const double u1 = rho[(size_t)16 * N + i].x, d1 = 1.0 - rho[(size_t)17 * N + i].x;
+    const double u0 = nu[i], d0 = nd[i];
+    nsum += u1 + d1;
+    res = nan_max(res, nan_max(fabs(u1 - u0), fabs(d1 - d0)));
+    if (write) {
+      nu[i] = u0 + mix * (u1 - u0);
+      nd[i] = d0 + mix * (d1 - d0);
+    }
+    for (int d = 0; d < 4; ++d) {
+      const double2 r0 = rho[(size_t)(4 * d + 0) * N + i], r1 = rho[(size_t)(4 * d + 1) * N + i];
+      const double2 r2 = rho[(size_t)(4 * d + 2) * N + i], r3 = rho[(size_t)(4 * d + 3) * N + i];
+      const double2 nw[4] = {r0, make_double2(-r3.x, r3.y), make_double2(-r1.x, r1.y),
+                             make_double2(-r2.x, -r2.y)};
+      double2* dst[4] = {cu, cd, du, dd};
+      const size_t k = (size_t)d * N + i;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 o = dst[q][k];
+        const double2 df = make_double2(nw[q].x - o.x, nw[q].y - o.y);
+        res = nan_max(res, cabs(df));
+        if (write) dst[q][k] = make_double2(o.x + mix * df.x, o.y + mix * df.y);
+      }
+    }
+  }
+  __shared__ double s_sum[kRB], s_max[kRB];
+  s_sum[threadIdx.x] = nsum;
+  s_max[threadIdx.x] = res;
+  __syncthreads();
+  for (unsigned s = kRB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      s_sum[threadIdx.x] += s_sum[threadIdx.x + s];
+      s_max[threadIdx.x] = nan_max(s_max[threadIdx.x], s_max[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s_sum[0];
+    part[kMaxBlocks + blockIdx.x] = s_max[0];
+  }
+}
+
+// Residual of the per-spin flat vector: n_up [N], n_dn [N], then chi_up,
+// chi_dn, Delta_up, Delta_dn as [4][N] interleaved (re, im), 34 N doubles.
+__global__ __launch_bounds__(kRB) void k_and_resid_sdw(int N, const double2* __restrict__ rho,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ f) {
+  const int i = blockIdx.x * kRB + threadIdx.x;
+  if (i >= N) return;
+  f[i] = rho[(size_t)16 * N + i].x - x[i];
+  f[N + i] = 1.0 - rho[(size_t)17 * N + i].x - x[N + i];
+  for (int d = 0; d < 4; ++d) {
+    const double2 r0 = rho[(size_t)(4 * d + 0) * N + i], r1 = rho[(size_t)(4 * d + 1) * N + i];
+    const double2 r2 = rho[(size_t)(4 * d + 2) * N + i], r3 = rho[(size_t)(4 * d + 3) * N + i];
+    const double2 nw[4] = {r0, make_double2(-r3.x, r3.y), make_double2(-r1.x, r1.y),
+                           make_double2(-r2.x, -r2.y)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const size_t c = 2 * (size_t)N + (size_t)q * 8 * N + 2 * ((size_t)d * N + i);
+      f[c] = nw[q].x - x[c];
+      f[c + 1] = nw[q].y - x[c + 1];
+    }
+  }
+}
+
 // dX = x - x_prev, dF = f - f_prev (when have_prev), then x_prev = x, f_prev = f.
 __global__ __launch_bounds__(kRB) void k_and_hist(long long L, const double* __restrict__ x,
                                                   const double* __restrict__ f,
@@ -237,7 +313,7 @@ RmftLayout rmft_layout(const kpm_lattice* L, int R, int M, int ckpt_k, int preci
   z.C = off;     off += align_up((size_t)M * sizeof(double));
   z.stats = off; off += align_up(KPM_RMFT_STATS_LEN * sizeof(double));
   // Anderson: x, f, x_prev, f_prev, then kMaxAnd dX and kMaxAnd dF vectors
-  const size_t Lv = 17 * N;
+  const size_t Lv = 34 * N;                       // sized for a spin-polarised theta
   const size_t nchunk = (Lv + kDotChunk - 1) / kDotChunk;
   const size_t npair = (size_t)kMaxAnd * (kMaxAnd + 1) / 2 + kMaxAnd;
   z.and_vec = off;  off += align_up((4 + 2 * (size_t)kMaxAnd) * Lv * sizeof(double));
@@ -272,18 +348,66 @@ bool solve_small(std::vector<double>& A, std::vector<double>& b, int n) {
   return true;
 }
 
+// The parameter arrays of the iteration: singlet (n, chi, delta) or
+// spin-polarised (n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn); each array
+// is one segment of the flat Anderson vector, in this order.
+struct ThetaSet {
+  bool spin;
+  int nseg;
+  double* p[6];
+  size_t len[6];                 // doubles per segment
+  long long total() const {
+    long long t = 0;
+    for (int k = 0; k < nseg; ++k) t += (long long)len[k];
+    return t;
+  }
+};
+
+int copy_segments(const ThetaSet& th, double* flat, bool to_flat, hipStream_t s) {
+  size_t o = 0;
+  for (int k = 0; k < th.nseg; ++k) {
+    const size_t b = th.len[k] * sizeof(double);
+    const hipError_t e = to_flat ? hipMemcpyAsync(flat + o, th.p[k], b, hipMemcpyDeviceToDevice, s)
+                                 : hipMemcpyAsync(th.p[k], flat + o, b, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return KPM_EDEVICE;
+    o += th.len[k];
+  }
+  return KPM_OK;
+}
+
+// The map with mixing (mix = 0: measurement only) and its two reductions.
+int map_update(const kpm_lattice* lat, const double* rho, double mix, const ThetaSet& th,
+               double* stats, hipStream_t s) {
+  const int N = lat->Lx * lat->Ly;
+  const int nb = std::min((N + kRB - 1) / kRB, kMaxBlocks);
+  const double2* r = reinterpret_cast<const double2*>(rho);
+  if (th.spin)
+    hipLaunchKernelGGL(k_rmft_map_sdw, dim3(nb), dim3(kRB), 0, s, N, r, mix, th.p[0], th.p[1],
+                       reinterpret_cast<double2*>(th.p[2]), reinterpret_cast<double2*>(th.p[3]),
+                       reinterpret_cast<double2*>(th.p[4]), reinterpret_cast<double2*>(th.p[5]),
+                       stats + kHead);
+  else
+    hipLaunchKernelGGL(k_rmft_map, dim3(nb), dim3(kRB), 0, s, N, r, mix, th.p[0],
+                       reinterpret_cast<double2*>(th.p[1]), reinterpret_cast<double2*>(th.p[2]),
+                       stats + kHead);
+  if (hipGetLastError() != hipSuccess) return KPM_EDEVICE;
+  hipLaunchKernelGGL(k_rmft_finish, dim3(1), dim3(kRB), 0, s, N, nb, stats);
+  if (hipGetLastError() != hipSuccess) return KPM_EDEVICE;
+  return KPM_OK;
+}
+
 // One Anderson update of theta from the accepted rho (see kpm_rmft_params).
-int anderson_step(const kpm_rmft_params* prm, int N, long long Lv, const double* rho, double* n,
-                  double* chi, double* delta, double* ax, double* af, double* axp, double* afp,
+int anderson_step(const kpm_rmft_params* prm, int N, long long Lv, const double* rho,
+                  const ThetaSet& th, double* ax, double* af, double* axp, double* afp,
                   double* adX, double* adF, double* apart, double* adots, int nchunk, int vgrid,
                   std::vector<int>& order, bool& have_prev, hipStream_t s) {
-  const size_t nb = (size_t)N * sizeof(double);
-  if (hipMemcpyAsync(ax, n, nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(ax + N, chi, 8 * nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(ax + 9 * (size_t)N, delta, 8 * nb, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return KPM_EDEVICE;
-  hipLaunchKernelGGL(k_and_resid, dim3((N + kRB - 1) / kRB), dim3(kRB), 0, s, N,
-                     reinterpret_cast<const double2*>(rho), ax, af);
+  if (copy_segments(th, ax, true, s) != KPM_OK) return KPM_EDEVICE;
+  if (th.spin)
+    hipLaunchKernelGGL(k_and_resid_sdw, dim3((N + kRB - 1) / kRB), dim3(kRB), 0, s, N,
+                       reinterpret_cast<const double2*>(rho), ax, af);
+  else
+    hipLaunchKernelGGL(k_and_resid, dim3((N + kRB - 1) / kRB), dim3(kRB), 0, s, N,
+                       reinterpret_cast<const double2*>(rho), ax, af);
   int slot = -1;
   if (have_prev) {
     if ((int)order.size() < prm->anderson) {
@@ -332,12 +456,38 @@ int anderson_step(const kpm_rmft_params* prm, int N, long long Lv, const double*
   hipLaunchKernelGGL(k_and_update, dim3(vgrid), dim3(kRB), 0, s, Lv, ax, af, adX, adF, sl, gm, mk,
                      prm->mix);
   if (hipGetLastError() != hipSuccess) return KPM_EDEVICE;
-  if (hipMemcpyAsync(n, ax, nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(chi, ax + N, 8 * nb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(delta, ax + 9 * (size_t)N, 8 * nb, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return KPM_EDEVICE;
-  return KPM_OK;
+  return copy_segments(th, ax, false, s);
 }
+
+ThetaSet singlet_set(const kpm_lattice* lat, double* n, double* chi, double* delta) {
+  const size_t N = (size_t)lat->Lx * lat->Ly;
+  ThetaSet t{};
+  t.spin = false;
+  t.nseg = 3;
+  t.p[0] = n;   t.len[0] = N;
+  t.p[1] = chi; t.len[1] = 8 * N;
+  t.p[2] = delta; t.len[2] = 8 * N;
+  return t;
+}
+
+ThetaSet spin_set(const kpm_lattice* lat, double* nu, double* nd, double* cu, double* cd,
+                  double* du, double* dd) {
+  const size_t N = (size_t)lat->Lx * lat->Ly;
+  ThetaSet t{};
+  t.spin = true;
+  t.nseg = 6;
+  double* p[6] = {nu, nd, cu, cd, du, dd};
+  for (int k = 0; k < 6; ++k) {
+    t.p[k] = p[k];
+    t.len[k] = k < 2 ? N : 8 * N;
+  }
+  return t;
+}
+
+int rmft_loop(const kpm_lattice* lat, const kpm_model* model, const kpm_probes* probes, int32_t M,
+              double T, int32_t precision, int32_t ckpt_k, const kpm_rmft_params* prm,
+              int32_t n_iter, const ThetaSet& th, double* mu, kpm_rmft_record* history,
+              int32_t* n_done, void* ws, size_t ws_bytes, void* stream);
 
 }  // namespace
 
@@ -347,17 +497,19 @@ int kpm_rmft_update(const kpm_lattice* lat, const double* rho, double mix, doubl
                     double* delta, double* stats, void* stream) {
   if (!valid_lattice(lat) || !rho || !n || !chi || !delta || !stats) return KPM_EINVAL;
   if (!(mix >= 0.0 && mix <= 1.0)) return KPM_EINVAL;
-  const int N = lat->Lx * lat->Ly;
-  const int nb = std::min((N + kRB - 1) / kRB, kMaxBlocks);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_rmft_map, dim3(nb), dim3(kRB), 0, s, N,
-                     reinterpret_cast<const double2*>(rho), mix, n,
-                     reinterpret_cast<double2*>(chi), reinterpret_cast<double2*>(delta),
-                     stats + kHead);
-  if (hipGetLastError() != hipSuccess) return KPM_EDEVICE;
-  hipLaunchKernelGGL(k_rmft_finish, dim3(1), dim3(kRB), 0, s, N, nb, stats);
-  if (hipGetLastError() != hipSuccess) return KPM_EDEVICE;
-  return KPM_OK;
+  return map_update(lat, rho, mix, singlet_set(lat, n, chi, delta), stats,
+                    static_cast<hipStream_t>(stream));
+}
+
+int kpm_rmft_update_sdw(const kpm_lattice* lat, const double* rho, double mix, double* n_up,
+                        double* n_dn, double* chi_up, double* chi_dn, double* delta_up,
+                        double* delta_dn, double* stats, void* stream) {
+  if (!valid_lattice(lat) || !rho || !n_up || !n_dn || !chi_up || !chi_dn || !delta_up ||
+      !delta_dn || !stats)
+    return KPM_EINVAL;
+  if (!(mix >= 0.0 && mix <= 1.0)) return KPM_EINVAL;
+  return map_update(lat, rho, mix, spin_set(lat, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn),
+                    stats, static_cast<hipStream_t>(stream));
 }
 
 size_t kpm_rmft_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int32_t ckpt_k,
@@ -371,9 +523,35 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
                      const kpm_rmft_params* prm, int32_t n_iter, double* n, double* chi,
                      double* delta, double* mu, kpm_rmft_record* history, int32_t* n_done,
                      void* ws, size_t ws_bytes, void* stream) {
-  if (!valid_lattice(lat) || !model || !probes || !prm || !n || !chi || !delta || !mu ||
-      !n_done || !ws || n_iter < 0)
+  if (!valid_lattice(lat)) return KPM_EINVAL;
+  return rmft_loop(lat, model, probes, M, T, precision, ckpt_k, prm, n_iter,
+                   singlet_set(lat, n, chi, delta), mu, history, n_done, ws, ws_bytes, stream);
+}
+
+int kpm_rmft_iterate_sdw(const kpm_lattice* lat, const kpm_model* model, const kpm_probes* probes,
+                         int32_t M, double T, int32_t precision, int32_t ckpt_k,
+                         const kpm_rmft_params* prm, int32_t n_iter, double* n_up, double* n_dn,
+                         double* chi_up, double* chi_dn, double* delta_up, double* delta_dn,
+                         double* mu, kpm_rmft_record* history, int32_t* n_done, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (!valid_lattice(lat)) return KPM_EINVAL;
+  return rmft_loop(lat, model, probes, M, T, precision, ckpt_k, prm, n_iter,
+                   spin_set(lat, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn), mu, history, n_done,
+                   ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+int rmft_loop(const kpm_lattice* lat, const kpm_model* model, const kpm_probes* probes, int32_t M,
+              double T, int32_t precision, int32_t ckpt_k, const kpm_rmft_params* prm,
+              int32_t n_iter, const ThetaSet& th, double* mu, kpm_rmft_record* history,
+              int32_t* n_done, void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_lattice(lat) || !model || !probes || !prm || !mu || !n_done || !ws || n_iter < 0)
     return KPM_EINVAL;
+  for (int k = 0; k < th.nseg; ++k)
+    if (!th.p[k]) return KPM_EINVAL;
   if (!(prm->doping > 0.0 && prm->doping < 1.0) || !(prm->mix > 0.0 && prm->mix <= 1.0) ||
       !(prm->tol_n >= 0.0) || !(prm->tol_mu >= 0.0) || !(prm->mu_step > 0.0) ||
       !std::isfinite(prm->mu_step) || !(prm->tol_residual >= 0.0) || prm->max_evals < 1 ||
@@ -398,7 +576,7 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double target = 1.0 - prm->doping;
   const int N = lat->Lx * lat->Ly;
-  const long long Lv = 17LL * N;
+  const long long Lv = th.total();
   double* ax = reinterpret_cast<double*>(base + z.and_vec);
   double* af = ax + Lv;
   double* axp = af + Lv;
@@ -418,7 +596,10 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
     kpm_model md = *model;
     md.mu = m;
     int st;
-    if ((st = kpm_build_H(lat, &md, n, chi, delta, h, stream)) != KPM_OK) return st;
+    st = th.spin ? kpm_build_H_sdw(lat, &md, th.p[0], th.p[1], th.p[2], th.p[3], th.p[4], th.p[5], h,
+                                   stream)
+                 : kpm_build_H(lat, &md, th.p[0], th.p[1], th.p[2], h, stream);
+    if (st != KPM_OK) return st;
     if ((st = kpm_bounds(lat, h, ab, stream)) != KPM_OK) return st;
     if ((st = kpm_coefficients(M, T, ab, prm->coef_K, C, stream)) != KPM_OK) return st;
     if (prm->estimator == KPM_RMFT_DIRECT) {
@@ -433,7 +614,7 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
                                          ws, z.kws, stream)) != KPM_OK)
         return st;
     }
-    if ((st = kpm_rmft_update(lat, rho, 0.0, n, chi, delta, stats, stream)) != KPM_OK) return st;
+    if ((st = map_update(lat, rho, 0.0, th, stats, s)) != KPM_OK) return st;
     int32_t dev = KPM_OK;
     if ((st = kpm_status_read(ws, &dev, stream)) != KPM_OK) return st;
     if (dev != KPM_OK) return dev;
@@ -495,8 +676,8 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
       }
     }
     if (prm->anderson == 0) {
-      if ((st = kpm_rmft_update(lat, rho, prm->mix, n, chi, delta, stats, stream)) != KPM_OK) return st;
-    } else if ((st = anderson_step(prm, N, Lv, rho, n, chi, delta, ax, af, axp, afp, adX, adF, apart,
+      if ((st = map_update(lat, rho, prm->mix, th, stats, s)) != KPM_OK) return st;
+    } else if ((st = anderson_step(prm, N, Lv, rho, th, ax, af, axp, afp, adX, adF, apart,
                                    adots, nchunk, vgrid, order, have_prev, s)) != KPM_OK) {
       return st;
     }
@@ -518,4 +699,4 @@ int kpm_rmft_iterate(const kpm_lattice* lat, const kpm_model* model, const kpm_p
   return KPM_OK;
 }
 
-}  // extern "C"
+}  // namespace

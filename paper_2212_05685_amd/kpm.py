@@ -38,6 +38,7 @@ EXPORTS = (
     "kpm_batch_destroy", "kpm_set_probe_block", "kpm_profile_begin", "kpm_profile_end",
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
     "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
+    "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw",
 )
 
 
@@ -121,6 +122,11 @@ def _load():
                                        c_double, c_int32, c_int32, POINTER(RmftParams), c_int32, P, P,
                                        P, POINTER(c_double), POINTER(RmftRecord), POINTER(c_int32),
                                        P, c_size_t, P]),
+        "kpm_rmft_update_sdw": (c_int32, [POINTER(Lattice), P, c_double, P, P, P, P, P, P, P, P]),
+        "kpm_rmft_iterate_sdw": (c_int32, [POINTER(Lattice), POINTER(Model), POINTER(Probes), c_int32,
+                                           c_double, c_int32, c_int32, POINTER(RmftParams), c_int32, P,
+                                           P, P, P, P, P, POINTER(c_double), POINTER(RmftRecord),
+                                           POINTER(c_int32), P, c_size_t, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -365,6 +371,23 @@ def kpm_rmft_update(lat, rho, mix, n, chi, delta, stats, stream=None):
                                 _stream(stream)), "kpm_rmft_update")
 
 
+def _spin_ptrs(lat, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn):
+    N = lat.Lx * lat.Ly
+    return (_ptr(n_up, torch.float64, N, "n_up"), _ptr(n_dn, torch.float64, N, "n_dn"),
+            _ptr(chi_up, torch.complex128, 4 * N, "chi_up"), _ptr(chi_dn, torch.complex128, 4 * N, "chi_dn"),
+            _ptr(delta_up, torch.complex128, 4 * N, "delta_up"),
+            _ptr(delta_dn, torch.complex128, 4 * N, "delta_dn"))
+
+
+def kpm_rmft_update_sdw(lat, rho, mix, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, stats, stream=None):
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_rmft_update_sdw(ctypes.byref(lat), _ptr(rho, torch.complex128, NENT * N, "rho"),
+                                    float(mix), *_spin_ptrs(lat, n_up, n_dn, chi_up, chi_dn, delta_up,
+                                                            delta_dn),
+                                    _ptr(stats, torch.float64, KPM_RMFT_STATS_LEN, "stats"),
+                                    _stream(stream)), "kpm_rmft_update_sdw")
+
+
 def kpm_rmft_workspace_size(lat, R, M, ckpt_k, precision) -> int:
     n = _lib.kpm_rmft_workspace_size(ctypes.byref(lat), R, M, ckpt_k, precision)
     if n == 0:
@@ -432,3 +455,22 @@ def workspace(lat, R, M, ckpt_k, precision, device="cuda") -> torch.Tensor:
     ws = torch.empty(n + 256, dtype=torch.uint8, device=device)
     off = (-ws.data_ptr()) % 256
     return ws[off:off + n]
+
+
+def kpm_rmft_iterate_sdw(lat, mdl, probes, M, T, precision, ckpt_k, params, n_iter, n_up, n_dn, chi_up,
+                         chi_dn, delta_up, delta_dn, mu, ws, stream=None):
+    """kpm_rmft_iterate on a spin-polarised theta, in place.  Returns
+    (mu, history, status) as kpm_rmft_iterate."""
+    mu_c = c_double(mu)
+    hist = (RmftRecord * max(n_iter, 1))()
+    done = c_int32(0)
+    st = _lib.kpm_rmft_iterate_sdw(ctypes.byref(lat), ctypes.byref(mdl), ctypes.byref(_probes(probes)),
+                                   M, T, precision, ckpt_k, ctypes.byref(params), n_iter,
+                                   *_spin_ptrs(lat, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn),
+                                   ctypes.byref(mu_c), hist, ctypes.byref(done),
+                                   _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream))
+    if st not in (KPM_OK, KPM_ENOCONV):
+        raise KpmError(st, "kpm_rmft_iterate_sdw")
+    out = [{"mu": r.mu, "nbar": r.nbar, "residual": r.residual, "omega": r.omega, "evals": r.evals}
+           for r in hist[:done.value]]
+    return mu_c.value, out, st

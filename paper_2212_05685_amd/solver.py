@@ -140,6 +140,12 @@ class KPMProblem:
                                     self.ckpt_k, params, n_iter, n, chi, delta, mu,
                                     self.rmft_workspace())
 
+    def rmft_iterate_sdw(self, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, mu, params, n_iter):
+        """rmft_iterate on a spin-polarised theta (kpm_rmft_iterate_sdw)."""
+        return kpm.kpm_rmft_iterate_sdw(self.lat, self.mdl, self.probes, self.M, self.T, self.precision,
+                                        self.ckpt_k, params, n_iter, n_up, n_dn, chi_up, chi_dn,
+                                        delta_up, delta_dn, mu, self.rmft_workspace())
+
 
 def save_rmft_state(path, n, chi, delta, mu, history=()):
     """Writes theta, mu and the iteration history to an .npz file (a restart

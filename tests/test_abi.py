@@ -119,6 +119,24 @@ def test_rmft_host_validation():
     assert done.value == -1                     # nothing ran
     assert kpm.strerror(kpm.KPM_ENOCONV).startswith("chemical-potential")
 
+    # the spin-polarised entries: same checks, plus a missing spin array
+    for mix in (-0.1, 1.5, float("nan")):
+        assert kpm._lib.kpm_rmft_update_sdw(ctypes.byref(lat), fake, mix, fake, fake, fake, fake, fake,
+                                            fake, fake, None) == kpm.KPM_EINVAL
+    assert kpm._lib.kpm_rmft_update_sdw(ctypes.byref(lat), fake, 0.5, fake, None, fake, fake, fake,
+                                        fake, fake, None) == kpm.KPM_EINVAL
+
+    def call_sdw(prm, dn=fake, ws_bytes=full):
+        return kpm._lib.kpm_rmft_iterate_sdw(ctypes.byref(lat), ctypes.byref(mdl), ctypes.byref(pr), 64,
+                                             0.005, kpm.KPM_FP64, 8, ctypes.byref(prm), 1, fake, dn, fake,
+                                             fake, fake, fake, ctypes.byref(mu), None, ctypes.byref(done),
+                                             ctypes.c_void_p(1 << 20), ws_bytes, None)
+
+    assert call_sdw(kpm.rmft_params(0.16, anderson=9)) == kpm.KPM_EINVAL
+    assert call_sdw(good, dn=None) == kpm.KPM_EINVAL
+    assert call_sdw(good, ws_bytes=full - 1) == kpm.KPM_EWORKSPACE
+    assert done.value == -1
+
 
 def test_rmft_state_round_trip(tmp_path):
     import numpy as np

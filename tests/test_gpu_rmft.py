@@ -15,7 +15,12 @@ kpm_rmft_iterate) against the oracle's loop (oracle/rmft.py), through the C ABI.
   on rho propagates to at most ~1e-5 absolute on theta per iteration;
 * the search's budget error leaves theta untouched;
 * the 48 x 96 plain-vortex workload: two iterations whose accepted states meet
-  the density constraint and stay physical.
+  the density constraint and stay physical;
+* the spin-polarised loop (kpm_rmft_update_sdw, kpm_rmft_iterate_sdw): the
+  per-spin map kernel against ``oracle.rmft.update`` on a six-array theta to
+  1e-14, and whole FP64 iterations (linear and Anderson, both searches) on a
+  staggered-moment seed against the oracle loop on the spin-polarised
+  builder, to the same bars as the singlet loop.
 """
 import numpy as np
 import pytest
@@ -166,3 +171,63 @@ def test_rmft_workload_48x96():
     amp = np.abs(dlt[0])
     far = amp > 0.5 * amp.max()
     assert np.median(np.real(dlt[0][far] * np.conj(dlt[1][far]))) < 0.0
+
+
+@pytest.mark.parametrize("Lx,Ly", [(13, 7), (300, 300)])
+@pytest.mark.parametrize("mix", [0.0, 0.3, 1.0])
+def test_update_sdw_kernel_parity(Lx, Ly, mix):
+    from paper_2212_05685_amd import kpm
+
+    cfg = wl.Config("u", Lx, Ly, 2, 0.16, 8, (wl.ProbeSpec("unit", 1),), vortex=True,
+                    complex_noise=0.05, seed=Lx * 1000 + Ly + 1)
+    th = wl.make_theta_sdw(cfg, m_amp=0.05, spin_noise=0.03)
+    rho = wl.random_stencil(cfg.N, seed=Lx + 7 * Ly + 1)
+    new_ref, nbar_ref, res_ref = ormft.update(rho, th, mix)
+    d = [dev(a) for a in th]
+    stats = torch.zeros(kpm.KPM_RMFT_STATS_LEN, dtype=torch.float64, device="cuda")
+    kpm.kpm_rmft_update_sdw(kpm.lattice(Lx, Ly, 2), dev(rho), mix, *d, stats)
+    s = host(stats)
+    assert abs(s[0] - nbar_ref) < 1e-14
+    assert abs(s[1] - res_ref) <= 1e-15 * res_ref
+    for got, ref in zip(d, new_ref):
+        assert np.abs(host(got) - ref).max() < 1e-14
+
+
+def _sdw_cfg():
+    # zero field, real chi seed; staggered moment m_i ~ 0.01 on top
+    return wl.Config("s", 12, 8, 0, 0.16, 128, (wl.ProbeSpec("colored_z4", 1, 515, 4, 4, 1, 0, 1.0),),
+                     "fp64", ckpt_k=16, vortex=False, complex_noise=0.01, seed=4242)
+
+
+@pytest.mark.parametrize("search,anderson", [("illinois", 0), ("bisection", 0), ("illinois", 2)])
+def test_iterate_sdw_parity_fp64(search, anderson):
+    from paper_2212_05685_amd import kpm
+
+    cfg = _sdw_cfg()
+    p = ormft.Params(doping=0.16, mix=0.1, tol_n=1e-5, tol_mu=1e-10, mu_step=0.004, max_evals=60,
+                     search=search, anderson=anderson)
+    n_it = 4 if anderson else 3
+    th0 = wl.make_theta_sdw(cfg, m_amp=0.01)
+    R, w = H.probe_matrix(cfg)
+    fn = ormft.sdw_kpm_rho_fn(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.T, cfg.M, R, w)
+    th_ref, mu_ref, hist_ref = ormft.iterate(fn, th0, cfg.mu, p, n_it)
+
+    pb = problem(cfg)
+    d = [dev(a) for a in th0]
+    prm = kpm.rmft_params(p.doping, p.mix, p.tol_n, p.tol_mu, p.mu_step, p.tol_residual, p.max_evals,
+                          search={"bisection": kpm.KPM_RMFT_BISECTION, "illinois": kpm.KPM_RMFT_ILLINOIS}[search],
+                          anderson=anderson)
+    mu, hist, st = pb.rmft_iterate_sdw(*d, cfg.mu, prm, n_it)
+    assert st == 0 and len(hist) == len(hist_ref) == n_it
+    for g, r in zip(hist, hist_ref):
+        assert g["evals"] == r["evals"], (hist, hist_ref)
+        assert abs(g["mu"] - r["mu"]) < 1e-12
+        assert abs(g["nbar"] - r["nbar"]) < 1e-10
+        assert abs(g["residual"] - r["residual"]) < 1e-10 * max(r["residual"], 1.0)
+        assert abs(g["omega"] - r["omega"]) < 1e-10 * abs(r["omega"])
+        assert abs(g["nbar"] - 0.84) <= 1e-5
+    assert abs(mu - mu_ref) < 1e-12
+    for a, b in zip(d, th_ref):
+        assert np.abs(host(a) - b).max() < 1e-10
+    m = (th_ref[0] - th_ref[1]) / 2
+    assert np.abs(m).max() > 0.02                 # the staggered moment grew: not the singlet path
