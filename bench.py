@@ -463,6 +463,37 @@ def sdw_form(reps: int, cfg):
             "h_bytes_written": 19 * 16 * cfg.N}
 
 
+def supercell_form(k_count: int = 2):
+    """Magnetic super-cell ED + broadened LDOS on the paper's smallest cell,
+    48 x 48 with two vortices, on an 8 x 8 k grid (8 x 48 = 384): k_count k
+    points of the grid, all 2304 sites, 201 energies in [-0.25 t, 0.25 t]
+    (+-100 meV at t = 400 meV), Gamma = 0.25 |omega| + 3e-4.  Wall clock of the
+    synchronous call (one warm-up call with one k point first)."""
+    import torch
+    import workloads as wl
+
+    cfg = wl.Config("sc48", 48, 48, 2, 0.16, 8, (wl.ProbeSpec("unit", 1),), vortex=True,
+                    complex_noise=0.02, seed=4848)
+    prob, th = make_problem(cfg, "fp64")
+    h = prob.build_H(*th)
+    om = torch.linspace(-0.25 * cfg.t, 0.25 * cfg.t, 201, dtype=torch.float64, device="cuda")
+    sites = list(range(cfg.N))
+    prob.supercell_ldos(h, 8, 8, sites, om, 0.25, 3e-4, k_first=0, k_count=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, ev = prob.supercell_ldos(h, 8, 8, sites, om, 0.25, 3e-4, k_first=9, k_count=k_count,
+                                  want_evals=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / k_count
+    log(f"supercell ED: {dt * 1e3:.0f} ms per k point (2N = {2 * cfg.N})")
+    del prob
+    torch.cuda.empty_cache()
+    return {"workload": "48x48 cell, 2 vortices, 8x8 k grid, all 2304 sites, 201 energies, FP64, "
+                        "rocSOLVER zheevd per k", "k_points_timed": k_count,
+            "ms_per_k": dt * 1e3, "s_full_grid_est": dt * 64,
+            "finite": bool(torch.isfinite(out).all().item()), "min": float(out.min().item())}
+
+
 def cpu_baseline(cfg, quiet=False):
     """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
     probe of the same workload, single thread."""
@@ -505,6 +536,9 @@ def main():
     ap.add_argument("--no-batched-form", action="store_true")
     ap.add_argument("--no-rmft-form", action="store_true")
     ap.add_argument("--no-direct-form", action="store_true")
+    ap.add_argument("--no-supercell-form", action="store_true")
+    ap.add_argument("--only-supercell-form", action="store_true",
+                    help="run only the magnetic super-cell ED form and print its JSON")
     ap.add_argument("--only-rmft-form", action="store_true",
                     help="run only the self-consistent iteration timing and print its JSON (profiling)")
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -547,6 +581,9 @@ def main():
         kpm.kpm_set_probe_block(args.probe_block)
     if args.only_rmft_form:
         print(json.dumps({"rmft_form": rmft_form(args.steps, args.warmup)}), flush=True)
+        return
+    if args.only_supercell_form:
+        print(json.dumps({"supercell_form": supercell_form()}), flush=True)
         return
     cfg = wl.C5("fp32")
     if args.moments:
@@ -613,6 +650,8 @@ def main():
         result["doubling_form"] = doubling_form(args.steps, prob, th)
         result["ldos_form"] = ldos_form(args.steps, prob, th, cfg)
         result["sdw_form"] = sdw_form(50, cfg)
+    if not args.no_supercell_form and not args.moments:
+        result["supercell_form"] = supercell_form()
 
     if not args.no_fp64_form:
         del prob

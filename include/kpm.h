@@ -446,6 +446,55 @@ int kpm_rmft_iterate_sdw(const kpm_lattice* lat, const kpm_model* model, const k
                          double* delta_dn, double* mu, kpm_rmft_record* history, int32_t* n_done,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* ---- magnetic super-cell exact diagonalisation and LDOS -------------------
+ * App. on the local density of states and the magnetic super-cell method.
+ * The converged h of one magnetic unit cell (the [19][N] stencil on the
+ * torus; its wrap-around bonds carry the field's magnetic boundary phases)
+ * is repeated over Mx x My cells.  By the magnetic Bloch theorem (eq.
+ * matrixeqn) both Nambu amplitudes of a quasiparticle pick up the same factor
+ * exp(-i k.R) from cell to cell, with k = 2 pi (m_x/(Mx Lx), m_y/(My Ly)), so
+ * the enlarged lattice splits into Mx My cell-sized Bloch matrices H(k). */
+
+#define KPM_SUPERCELL_MAX_N 16384   /* sites per cell (dense matrices of (2N)^2) */
+#define KPM_SUPERCELL_MAX_K 4096    /* Mx * My                                   */
+
+/* Dense Bloch matrix H(k) for twist angles phi = (k_x Lx, k_y Ly): the torus h
+ * with every element of a bond whose head lies in the neighbouring cell
+ * (s_x, s_y) (s = -1, 0, +1) multiplied by exp(-i (s_x phi_x + s_y phi_y)),
+ * its Hermitian partner by the conjugate.  Hk: device complex, column-major,
+ * 2N columns of leading dimension ld >= 2N (Nambu index I = 2i + a); rows
+ * 0..2N-1 of every column are overwritten.  Lx, Ly >= 3. */
+int kpm_bloch_H(const kpm_lattice* lat, const double* h, double phi_x, double phi_y, double* Hk,
+                int64_t ld, void* stream);
+
+/* Workspace bytes of kpm_supercell_ldos (one dense matrix of (2N)^2 complex
+ * values, eigenvalues, the site list and per-k solver flags).  0 on invalid
+ * arguments. */
+size_t kpm_supercell_workspace_size(const kpm_lattice* lat);
+
+/* Broadened LDOS of eqs. N_i and Gij over the k grid, for the k indices
+ * q = k_first .. k_first + k_count - 1 (q = m_y Mx + m_x; phi = 2 pi (m_x/Mx,
+ * m_y/My)).  For each k: H(k) (kpm_bloch_H), its eigenpairs (E_q, (u, v)) by
+ * rocSOLVER zheevd, then for every listed site i and energy omega
+ *   ldos[s][e] += 1/(Mx My) sum_q [w_up_i |u_i^q|^2 L(omega - E_q)
+ *                                + w_dn_i |v_i^q|^2 L(omega + E_q)],
+ *   L(x) = (Gamma/pi) / (x^2 + Gamma^2),  Gamma = alpha |omega| + gamma0,
+ * the spin-up electron weight at +E and the spin-down one (hole amplitude) at
+ * -E.  Splitting the k grid over calls (accumulate = 1) sums the same result.
+ * h: device [19][N] stencil.  sites: HOST int32 [n_sites] site indices in
+ * [0, N) (validated here).  omega: device [n_omega].  alpha >= 0, gamma0 > 0.
+ * w_up, w_dn: device [N] weights (the g^t factors at i = j of eq. Gij) or
+ * NULL for 1.  accumulate: 0 overwrites ldos, 1 adds to it.  ldos: device
+ * [n_sites][n_omega].  evals: device [k_count][2N] ascending eigenvalues, or
+ * NULL.  ws: kpm_supercell_workspace_size bytes, 256-byte aligned.  Returns
+ * after the stream has drained (it reads the solver flags); KPM_EDEVICE when
+ * the eigensolver fails or does not converge for some k. */
+int kpm_supercell_ldos(const kpm_lattice* lat, const double* h, int32_t Mx, int32_t My,
+                       int32_t k_first, int32_t k_count, const int32_t* sites, int32_t n_sites,
+                       const double* omega, int32_t n_omega, double alpha, double gamma0,
+                       const double* w_up, const double* w_dn, int32_t accumulate, double* ldos,
+                       double* evals, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- measurement ----------------------------------------------------------
  * Between kpm_profile_begin and kpm_profile_end, one in `sample_every`
  * forward-step and adjoint-step kernel launches of this library (not inside a

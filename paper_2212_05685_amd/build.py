@@ -11,7 +11,9 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["kpm_build.hip", "kpm_cheb.hip", "kpm_api.hip", "kpm_rmft.hip", "kpm_ldos.hip"]
+SRC = ["kpm_build.hip", "kpm_cheb.hip", "kpm_api.hip", "kpm_rmft.hip", "kpm_ldos.hip",
+       "kpm_supercell.hip"]
+ROCM_LIB = "/opt/rocm/lib"
 LIB = os.path.join(HERE, "libkpm.so")
 
 
@@ -26,7 +28,8 @@ def command(out: str = LIB, extra=()) -> list:
     srcs = [os.path.join(HERE, "csrc", s) for s in SRC]
     return [hipcc(), "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wno-unused-command-line-argument", *extra, *srcs, "-o", out]
+            "-Wno-unused-command-line-argument", *extra, *srcs,
+            f"-L{ROCM_LIB}", f"-Wl,-rpath,{ROCM_LIB}", "-lrocsolver", "-lrocblas", "-o", out]
 
 
 def build(verbose: bool = False) -> str:

@@ -38,7 +38,8 @@ EXPORTS = (
     "kpm_batch_destroy", "kpm_set_probe_block", "kpm_profile_begin", "kpm_profile_end",
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
     "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
-    "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw",
+    "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_bloch_H", "kpm_supercell_workspace_size",
+    "kpm_supercell_ldos",
 )
 
 
@@ -127,6 +128,11 @@ def _load():
                                            c_double, c_int32, c_int32, POINTER(RmftParams), c_int32, P,
                                            P, P, P, P, P, POINTER(c_double), POINTER(RmftRecord),
                                            POINTER(c_int32), P, c_size_t, P]),
+        "kpm_bloch_H": (c_int32, [POINTER(Lattice), P, c_double, c_double, P, ctypes.c_int64, P]),
+        "kpm_supercell_workspace_size": (c_size_t, [POINTER(Lattice)]),
+        "kpm_supercell_ldos": (c_int32, [POINTER(Lattice), P, c_int32, c_int32, c_int32, c_int32,
+                                         POINTER(c_int32), c_int32, P, c_int32, c_double, c_double, P, P,
+                                         c_int32, P, P, P, c_size_t, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -474,3 +480,42 @@ def kpm_rmft_iterate_sdw(lat, mdl, probes, M, T, precision, ckpt_k, params, n_it
     out = [{"mu": r.mu, "nbar": r.nbar, "residual": r.residual, "omega": r.omega, "evals": r.evals}
            for r in hist[:done.value]]
     return mu_c.value, out, st
+
+
+KPM_SUPERCELL_MAX_N = 16384
+KPM_SUPERCELL_MAX_K = 4096
+
+
+def kpm_bloch_H(lat, h, phi_x, phi_y, Hk, ld=None, stream=None):
+    """Dense Bloch matrix H(k) into Hk (complex128, column-major: a [2N, ld]
+    tensor whose row q is column q of the matrix)."""
+    N = lat.Lx * lat.Ly
+    ld = 2 * N if ld is None else int(ld)
+    _check(_lib.kpm_bloch_H(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"), float(phi_x),
+                            float(phi_y), _ptr(Hk, torch.complex128, 2 * N * ld, "Hk"), ld,
+                            _stream(stream)), "kpm_bloch_H")
+
+
+def kpm_supercell_workspace_size(lat) -> int:
+    n = _lib.kpm_supercell_workspace_size(ctypes.byref(lat))
+    if n == 0:
+        raise KpmError(KPM_EINVAL, "kpm_supercell_workspace_size")
+    return int(n)
+
+
+def kpm_supercell_ldos(lat, h, Mx, My, k_first, k_count, sites, omega, alpha, gamma0, w_up, w_dn,
+                       accumulate, ldos, evals, ws, stream=None):
+    N = lat.Lx * lat.Ly
+    sites = [int(i) for i in sites]
+    arr = (c_int32 * max(len(sites), 1))(*sites)
+    W = int(omega.numel())
+    _check(_lib.kpm_supercell_ldos(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"), Mx, My,
+                                   k_first, k_count, arr, len(sites), _ptr(omega, torch.float64, W, "omega"),
+                                   W, float(alpha), float(gamma0),
+                                   None if w_up is None else _ptr(w_up, torch.float64, N, "w_up"),
+                                   None if w_dn is None else _ptr(w_dn, torch.float64, N, "w_dn"),
+                                   int(bool(accumulate)), _ptr(ldos, torch.float64, len(sites) * W, "ldos"),
+                                   None if evals is None else _ptr(evals, torch.float64, k_count * 2 * N,
+                                                                   "evals"),
+                                   _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream)),
+           "kpm_supercell_ldos")

@@ -30,6 +30,7 @@ class KPMProblem:
     device: str = "cuda"
     _ws: torch.Tensor = field(default=None, repr=False)
     _rmft_ws: torch.Tensor = field(default=None, repr=False)
+    _sc_ws: torch.Tensor = field(default=None, repr=False)
 
     def __post_init__(self):
         self.lat = kpm.lattice(self.Lx, self.Ly, self.n_vortex)
@@ -139,6 +140,23 @@ class KPMProblem:
         return kpm.kpm_rmft_iterate(self.lat, self.mdl, self.probes, self.M, self.T, self.precision,
                                     self.ckpt_k, params, n_iter, n, chi, delta, mu,
                                     self.rmft_workspace())
+
+    # -- magnetic super-cell ED and broadened LDOS (kpm_supercell_ldos)
+    def supercell_ldos(self, h, Mx, My, sites, omega, alpha=0.25, gamma0=3e-4, w_up=None, w_dn=None,
+                       k_first=0, k_count=None, want_evals=False):
+        """N_i(omega) for the listed sites over the Mx x My k grid (or the slice
+        k_first .. k_first + k_count - 1 of it).  Returns (ldos [S, W],
+        eigenvalues [k_count, 2N] or None)."""
+        if self._sc_ws is None:
+            nb = kpm.kpm_supercell_workspace_size(self.lat)
+            self._sc_ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        k_count = Mx * My - k_first if k_count is None else k_count
+        N = self.lat.Lx * self.lat.Ly
+        out = torch.empty(len(sites), omega.numel(), dtype=torch.float64, device=self.device)
+        ev = torch.empty(k_count, 2 * N, dtype=torch.float64, device=self.device) if want_evals else None
+        kpm.kpm_supercell_ldos(self.lat, h, Mx, My, k_first, k_count, sites, omega, alpha, gamma0, w_up,
+                               w_dn, False, out, ev, self._sc_ws)
+        return out, ev
 
     def rmft_iterate_sdw(self, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, mu, params, n_iter):
         """rmft_iterate on a spin-polarised theta (kpm_rmft_iterate_sdw)."""

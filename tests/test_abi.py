@@ -154,3 +154,32 @@ def test_rmft_state_round_trip(tmp_path):
     n2, c2, d2, mu2, h2 = load_rmft_state(p, device="cpu")
     assert torch.equal(n, n2) and torch.equal(chi, c2) and torch.equal(dlt, d2)
     assert mu2 == 1.625 and h2 == hist
+
+
+def test_supercell_host_validation():
+    """kpm_bloch_H / kpm_supercell_ldos reject bad arguments before any device
+    work (placeholder pointers are never dereferenced)."""
+    from paper_2212_05685_amd import kpm
+
+    lat = kpm.lattice(6, 5, 2)
+    N = 30
+    fake = ctypes.c_void_p(256)
+    L = kpm._lib
+    assert L.kpm_bloch_H(ctypes.byref(lat), fake, 0.1, 0.2, fake, 2 * N - 1, None) == kpm.KPM_EINVAL
+    assert L.kpm_bloch_H(ctypes.byref(kpm.lattice(2, 5, 0)), fake, 0.0, 0.0, fake, 20, None) == kpm.KPM_EINVAL
+    assert L.kpm_bloch_H(ctypes.byref(lat), fake, float("nan"), 0.0, fake, 2 * N, None) == kpm.KPM_EINVAL
+    full = kpm.kpm_supercell_workspace_size(lat)
+    assert full >= (2 * N) ** 2 * 16
+    assert L.kpm_supercell_workspace_size(ctypes.byref(kpm.lattice(130, 130, 0))) == 0
+
+    def call(Mx=2, My=2, k0=0, kc=4, sites=(0, 29), alpha=0.25, g0=3e-4, acc=0, ws_bytes=full,
+             ws=ctypes.c_void_p(1 << 20)):
+        arr = (ctypes.c_int32 * len(sites))(*sites)
+        return L.kpm_supercell_ldos(ctypes.byref(lat), fake, Mx, My, k0, kc, arr, len(sites), fake, 5,
+                                    alpha, g0, None, None, acc, fake, None, ws, ws_bytes, None)
+
+    for kw in ({"Mx": 0}, {"kc": 5}, {"k0": 3, "kc": 2}, {"kc": 0}, {"sites": (0, 30)}, {"sites": (-1,)},
+               {"alpha": -0.1}, {"g0": 0.0}, {"acc": 2}, {"Mx": 4097, "My": 1}):
+        assert call(**kw) == kpm.KPM_EINVAL, kw
+    assert call(ws_bytes=full - 1) == kpm.KPM_EWORKSPACE
+    assert call(ws=ctypes.c_void_p((1 << 20) + 8)) == kpm.KPM_EWORKSPACE

@@ -1,0 +1,110 @@
+"""GPU parity of the magnetic super-cell ED and broadened LDOS (kpm_bloch_H,
+kpm_supercell_ldos) against the oracle (oracle/supercell.py), through the C ABI.
+
+* H(k) element by element against ``bloch_dense`` (FP64; the twist factor is
+  one complex product, so 4 ulp of max|h|), ragged and field lattices, zero
+  and generic twists, and a leading dimension above 2N (padding untouched);
+* eigenvalues per k (1e-12 of the spectral radius) and the LDOS (1e-10 of its
+  maximum) against the oracle's dense eigh on 12 x 8 (2 x 2 grid, weights,
+  repeated sites, 37 energies: a ragged energy block) and 24 x 12 (288 sites:
+  two site blocks);
+* the k grid split over two calls (accumulate) equals one call;
+* 48 x 48 (the paper's smallest cell, 8 x 8 grid) at one k point: eigenvalues
+  and the LDOS along a line cut against the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import supercell
+from tests import helpers as H
+from tests.gpu_helpers import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _cfg(Lx, Ly, nv=2, seed=31):
+    return wl.Config("sc", Lx, Ly, nv, 0.15, 8, (wl.ProbeSpec("unit", 1),), vortex=nv > 0,
+                     complex_noise=0.04, seed=seed)
+
+
+def _problem(cfg):
+    from paper_2212_05685_amd import kpm
+    from paper_2212_05685_amd.solver import KPMProblem
+
+    return KPMProblem(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, cfg.T, 8,
+                      [kpm.ProbeSpec(kpm.KPM_PROBE_UNIT, 1)], kpm.KPM_FP64, 8)
+
+
+@pytest.mark.parametrize("Lx,Ly,nv", [(13, 7, 2), (4, 3, 2), (6, 5, 0)])
+@pytest.mark.parametrize("phi", [(0.0, 0.0), (0.7, -1.9), (2 * np.pi * 3 / 8, 2 * np.pi / 4)])
+def test_bloch_matrix_against_oracle(Lx, Ly, nv, phi):
+    from paper_2212_05685_amd import kpm
+
+    cfg = _cfg(Lx, Ly, nv)
+    st, _, _, _ = H.oracle_inputs(cfg)
+    n = 2 * cfg.N
+    ld = n + 5
+    Hk = torch.full((n, ld), 7.0 + 3.0j, dtype=torch.complex128, device="cuda")
+    kpm.kpm_bloch_H(kpm.lattice(Lx, Ly, nv), dev(st), phi[0], phi[1], Hk, ld)
+    got = host(Hk)
+    ref = supercell.bloch_dense(st, Lx, Ly, *phi)
+    assert np.max(np.abs(got[:, :n].T - ref)) <= 4 * np.finfo(float).eps * np.max(np.abs(ref))
+    assert np.all(got[:, n:] == 7.0 + 3.0j)
+
+
+def _compare(cfg, Mx, My, sites, om, w=True, ks=None):
+    st, _, _, _ = H.oracle_inputs(cfg)
+    rng = np.random.default_rng(cfg.N)
+    wu, wd = (rng.uniform(0.2, 1.0, cfg.N), rng.uniform(0.2, 1.0, cfg.N)) if w else (None, None)
+    ref, ev_ref = supercell.supercell_ldos(st, cfg.Lx, cfg.Ly, Mx, My, sites, om, 0.25, 3e-2, wu, wd, ks=ks)
+    pb = _problem(cfg)
+    k_first = 0 if ks is None else ks[0]
+    k_count = Mx * My if ks is None else len(ks)
+    got, ev = pb.supercell_ldos(dev(st), Mx, My, sites, dev(om), 0.25, 3e-2,
+                                None if wu is None else dev(wu), None if wd is None else dev(wd),
+                                k_first=k_first, k_count=k_count, want_evals=True)
+    got, ev = host(got), host(ev)
+    scale = np.max(np.abs(ev_ref))
+    assert np.max(np.abs(ev - ev_ref)) < 1e-12 * scale
+    assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
+    return got
+
+
+def test_supercell_ldos_small():
+    cfg = _cfg(12, 8)
+    sites = [0, 17, 17, 50, 95, 3]
+    _compare(cfg, 2, 2, sites, np.linspace(-3.0, 3.0, 37))
+
+
+def test_supercell_ldos_two_site_blocks():
+    cfg = _cfg(24, 12, seed=5)
+    _compare(cfg, 2, 1, list(range(cfg.N)), np.linspace(-2.0, 2.0, 16), w=False)
+
+
+def test_k_split_accumulates():
+    from paper_2212_05685_amd import kpm
+
+    cfg = _cfg(12, 8, seed=9)
+    st, _, _, _ = H.oracle_inputs(cfg)
+    pb = _problem(cfg)
+    om = dev(np.linspace(-2.5, 2.5, 21))
+    sites = list(range(0, cfg.N, 5))
+    full, _ = pb.supercell_ldos(dev(st), 3, 2, sites, om, 0.25, 3e-2)
+    part = torch.empty_like(full)
+    ws = torch.empty(kpm.kpm_supercell_workspace_size(pb.lat), dtype=torch.uint8, device="cuda")
+    h = dev(st)
+    kpm.kpm_supercell_ldos(pb.lat, h, 3, 2, 0, 2, sites, om, 0.25, 3e-2, None, None, 0, part, None, ws)
+    kpm.kpm_supercell_ldos(pb.lat, h, 3, 2, 2, 4, sites, om, 0.25, 3e-2, None, None, 1, part, None, ws)
+    f, p = host(full), host(part)
+    assert np.max(np.abs(f - p)) <= 1e-14 * np.max(np.abs(f))
+
+
+def test_supercell_fullsize_one_k():
+    """48 x 48 cell, 8 x 8 grid, the k point (m_x, m_y) = (1, 1): all 4608
+    eigenvalues and the LDOS along the line cut y = 24."""
+    cfg = _cfg(48, 48, seed=48)
+    q = 1 * 8 + 1
+    sites = [24 * 48 + x for x in range(48)]
+    _compare(cfg, 8, 8, sites, np.linspace(-1.0, 1.0, 33), ks=[q])
