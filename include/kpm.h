@@ -457,6 +457,7 @@ int kpm_rmft_iterate_sdw(const kpm_lattice* lat, const kpm_model* model, const k
 
 #define KPM_SUPERCELL_MAX_N 16384   /* sites per cell (dense matrices of (2N)^2) */
 #define KPM_SUPERCELL_MAX_K 4096    /* Mx * My                                   */
+#define KPM_SUPERCELL_MAX_BATCH 16  /* k points per batched eigensolver call      */
 
 /* Dense Bloch matrix H(k) for twist angles phi = (k_x Lx, k_y Ly): the torus h
  * with every element of a bond whose head lies in the neighbouring cell
@@ -467,15 +468,17 @@ int kpm_rmft_iterate_sdw(const kpm_lattice* lat, const kpm_model* model, const k
 int kpm_bloch_H(const kpm_lattice* lat, const double* h, double phi_x, double phi_y, double* Hk,
                 int64_t ld, void* stream);
 
-/* Workspace bytes of kpm_supercell_ldos (one dense matrix of (2N)^2 complex
- * values, eigenvalues, the site list and per-k solver flags).  0 on invalid
- * arguments. */
-size_t kpm_supercell_workspace_size(const kpm_lattice* lat);
+/* Workspace bytes of kpm_supercell_ldos with k_batch (1..KPM_SUPERCELL_MAX_BATCH)
+ * k points per eigensolver call: k_batch dense matrices of (2N)^2 complex
+ * values, their eigenvalues, the site list and per-k solver flags.  0 on
+ * invalid arguments. */
+size_t kpm_supercell_workspace_size(const kpm_lattice* lat, int32_t k_batch);
 
 /* Broadened LDOS of eqs. N_i and Gij over the k grid, for the k indices
  * q = k_first .. k_first + k_count - 1 (q = m_y Mx + m_x; phi = 2 pi (m_x/Mx,
  * m_y/My)).  For each k: H(k) (kpm_bloch_H), its eigenpairs (E_q, (u, v)) by
- * rocSOLVER zheevd, then for every listed site i and energy omega
+ * rocSOLVER zheevd (k_batch k points per strided-batched call; the workspace
+ * must be sized for that k_batch), then for every listed site i and energy omega
  *   ldos[s][e] += 1/(Mx My) sum_q [w_up_i |u_i^q|^2 L(omega - E_q)
  *                                + w_dn_i |v_i^q|^2 L(omega + E_q)],
  *   L(x) = (Gamma/pi) / (x^2 + Gamma^2),  Gamma = alpha |omega| + gamma0,
@@ -490,7 +493,8 @@ size_t kpm_supercell_workspace_size(const kpm_lattice* lat);
  * after the stream has drained (it reads the solver flags); KPM_EDEVICE when
  * the eigensolver fails or does not converge for some k. */
 int kpm_supercell_ldos(const kpm_lattice* lat, const double* h, int32_t Mx, int32_t My,
-                       int32_t k_first, int32_t k_count, const int32_t* sites, int32_t n_sites,
+                       int32_t k_first, int32_t k_count, int32_t k_batch, const int32_t* sites,
+                       int32_t n_sites,
                        const double* omega, int32_t n_omega, double alpha, double gamma0,
                        const double* w_up, const double* w_dn, int32_t accumulate, double* ldos,
                        double* evals, void* ws, size_t ws_bytes, void* stream);

@@ -22,7 +22,8 @@
 namespace {
 
 constexpr int kZB = 256;                  // fill / scatter threads per block
-constexpr int kLB = 256;                  // LDOS: sites per block
+constexpr int kLS = 64;                   // LDOS: sites per block (one per lane)
+constexpr int kQL = 8;                    // LDOS: waves per block, splitting the eigenvectors
 constexpr int kEC = 16;                   // LDOS: energies per block (registers per thread)
 constexpr int kNT = 64;                   // LDOS: eigenvectors per LDS tile
 
@@ -74,18 +75,24 @@ __global__ __launch_bounds__(kZB) void k_bloch_scatter(int Lx, int Ly, const dou
 }
 
 // N_i(omega_e) += wk * sum_q [wu_i |U_{2i,q}|^2 L(omega_e - E_q) + wd_i |U_{2i+1,q}|^2 L(omega_e + E_q)],
-// L(x) = (G/pi)/(x^2 + G^2), G = alpha |omega_e| + gamma0.  Thread = one site
-// of the list (loads coalesced along a column), block.y = kEC energies; the
-// Lorentzians of kNT eigenvalues x kEC energies are staged in LDS per tile.
-__global__ __launch_bounds__(kLB) void k_sc_ldos(int n, long long ld, const double2* __restrict__ U,
-                                                 const double* __restrict__ E,
-                                                 const int* __restrict__ sites, int S,
-                                                 const double* __restrict__ omega, int W, double alpha,
-                                                 double gamma0, const double* __restrict__ wu,
-                                                 const double* __restrict__ wd, double wk,
-                                                 double* __restrict__ out) {
+// L(x) = (G/pi)/(x^2 + G^2), G = alpha |omega_e| + gamma0.  A block owns kLS
+// sites of the list and kEC energies (block.y); its kQL waves split the
+// eigenvector index q (wave w takes q = w mod kQL), each lane one site, so a
+// wave's loads of one column are coalesced.  The Lorentzians of kNT
+// eigenvalues x kEC energies are staged in LDS per tile; the kQL partial sums
+// are added in a fixed order at the end (bitwise reproducible).
+__global__ __launch_bounds__(kLS * kQL) void k_sc_ldos(int n, long long ld, const double2* __restrict__ U,
+                                                       const double* __restrict__ E,
+                                                       const int* __restrict__ sites, int S,
+                                                       const double* __restrict__ omega, int W,
+                                                       double alpha, double gamma0,
+                                                       const double* __restrict__ wu,
+                                                       const double* __restrict__ wd, double wk,
+                                                       double* __restrict__ out) {
   __shared__ double Lm[kNT][kEC], Lp[kNT][kEC];
-  const int s = blockIdx.x * kLB + threadIdx.x;
+  __shared__ double red[kQL][kEC][kLS];
+  const int sl = threadIdx.x % kLS, ql = threadIdx.x / kLS;
+  const int s = blockIdx.x * kLS + sl;
   const int site = sites[min(s, S - 1)];
   const int e0 = blockIdx.y * kEC;
   const double pu = wu ? wu[site] : 1.0, pd = wd ? wd[site] : 1.0;
@@ -95,7 +102,7 @@ __global__ __launch_bounds__(kLB) void k_sc_ldos(int n, long long ld, const doub
   const double2* urow = U + 2LL * site;
   for (int q0 = 0; q0 < n; q0 += kNT) {
     __syncthreads();
-    for (int t = threadIdx.x; t < kNT * kEC; t += kLB) {
+    for (int t = threadIdx.x; t < kNT * kEC; t += kLS * kQL) {
       const int q = t / kEC, e = t % kEC;
       double lm = 0.0, lp = 0.0;
       if (q0 + q < n && e0 + e < W) {
@@ -110,7 +117,7 @@ __global__ __launch_bounds__(kLB) void k_sc_ldos(int n, long long ld, const doub
     }
     __syncthreads();
     const int qn = min(kNT, n - q0);
-    for (int q = 0; q < qn; ++q) {
+    for (int q = ql; q < qn; q += kQL) {
       const double2* col = urow + (long long)(q0 + q) * ld;
       const double2 u = col[0], v = col[1];
       const double au = pu * (u.x * u.x + u.y * u.y), av = pd * (v.x * v.x + v.y * v.y);
@@ -118,10 +125,17 @@ __global__ __launch_bounds__(kLB) void k_sc_ldos(int n, long long ld, const doub
       for (int e = 0; e < kEC; ++e) acc[e] = fma(au, Lm[q][e], fma(av, Lp[q][e], acc[e]));
     }
   }
-  if (s >= S) return;
 #pragma unroll
-  for (int e = 0; e < kEC; ++e)
-    if (e0 + e < W) out[(size_t)s * W + e0 + e] += wk * acc[e];
+  for (int e = 0; e < kEC; ++e) red[ql][e][sl] = acc[e];
+  __syncthreads();
+  for (int t = threadIdx.x; t < kEC * kLS; t += kLS * kQL) {
+    const int e = t / kLS, l = t % kLS;
+    const int so = blockIdx.x * kLS + l;
+    if (so >= S || e0 + e >= W) continue;
+    double sum = 0.0;
+    for (int w = 0; w < kQL; ++w) sum += red[w][e][l];
+    out[(size_t)so * W + e0 + e] += wk * sum;
+  }
 }
 
 __global__ __launch_bounds__(kZB) void k_fill0(long long len, double* __restrict__ p) {
@@ -140,12 +154,12 @@ struct ScLayout {
   size_t H, E, sites, info, total;
 };
 
-ScLayout sc_layout(long long N) {
+ScLayout sc_layout(long long N, int kb) {
   const long long n = 2 * N;
   ScLayout z{};
   size_t off = 0;
-  z.H = off;     off += align_up((size_t)n * n * sizeof(double2));
-  z.E = off;     off += align_up((size_t)n * sizeof(double) * 2);   // eigenvalues + tridiagonal scratch
+  z.H = off;     off += align_up((size_t)kb * n * n * sizeof(double2));
+  z.E = off;     off += align_up((size_t)kb * n * sizeof(double) * 2);   // eigenvalues + tridiagonal scratch
   z.sites = off; off += align_up((size_t)N * sizeof(int));
   z.info = off;  off += align_up((size_t)KPM_SUPERCELL_MAX_K * sizeof(int));
   z.total = off;
@@ -177,19 +191,21 @@ int kpm_bloch_H(const kpm_lattice* lat, const double* h, double phi_x, double ph
                       static_cast<hipStream_t>(stream));
 }
 
-size_t kpm_supercell_workspace_size(const kpm_lattice* lat) {
-  if (!valid_cell(lat)) return 0;
-  return sc_layout((long long)lat->Lx * lat->Ly).total;
+size_t kpm_supercell_workspace_size(const kpm_lattice* lat, int32_t k_batch) {
+  if (!valid_cell(lat) || k_batch < 1 || k_batch > KPM_SUPERCELL_MAX_BATCH) return 0;
+  return sc_layout((long long)lat->Lx * lat->Ly, k_batch).total;
 }
 
 int kpm_supercell_ldos(const kpm_lattice* lat, const double* h, int32_t Mx, int32_t My,
-                       int32_t k_first, int32_t k_count, const int32_t* sites, int32_t n_sites,
+                       int32_t k_first, int32_t k_count, int32_t k_batch, const int32_t* sites,
+                       int32_t n_sites,
                        const double* omega, int32_t n_omega, double alpha, double gamma0,
                        const double* w_up, const double* w_dn, int32_t accumulate, double* ldos,
                        double* evals, void* ws, size_t ws_bytes, void* stream) {
   if (!valid_cell(lat) || !h || !sites || !omega || !ldos || !ws) return KPM_EINVAL;
   if (Mx < 1 || My < 1 || (long long)Mx * My > KPM_SUPERCELL_MAX_K) return KPM_EINVAL;
   if (k_first < 0 || k_count < 1 || (long long)k_first + k_count > (long long)Mx * My) return KPM_EINVAL;
+  if (k_batch < 1 || k_batch > KPM_SUPERCELL_MAX_BATCH) return KPM_EINVAL;
   if (n_sites < 1 || n_omega < 1 || !(alpha >= 0.0) || !(gamma0 > 0.0) || !std::isfinite(alpha) ||
       !std::isfinite(gamma0) || (accumulate != 0 && accumulate != 1))
     return KPM_EINVAL;
@@ -198,13 +214,13 @@ int kpm_supercell_ldos(const kpm_lattice* lat, const double* h, int32_t Mx, int3
     return KPM_EINVAL;
   for (int s = 0; s < n_sites; ++s)
     if (sites[s] < 0 || sites[s] >= N) return KPM_EINVAL;
-  const ScLayout z = sc_layout(N);
+  const ScLayout z = sc_layout(N, k_batch);
   if (ws_bytes < z.total || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return KPM_EWORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   double2* H = reinterpret_cast<double2*>(base + z.H);
   double* Ebuf = reinterpret_cast<double*>(base + z.E);
-  double* Etri = Ebuf + n;
+  double* Etri = Ebuf + (size_t)k_batch * n;
   int* dsites = reinterpret_cast<int*>(base + z.sites);
   int* dinfo = reinterpret_cast<int*>(base + z.info);
 
@@ -221,21 +237,35 @@ int kpm_supercell_ldos(const kpm_lattice* lat, const double* h, int32_t Mx, int3
   int st = KPM_OK;
   if (rocblas_set_stream(hb, s) != rocblas_status_success) st = KPM_EDEVICE;
   const double wk = 1.0 / ((double)Mx * My);
-  const dim3 lgrid((unsigned)((n_sites + kLB - 1) / kLB), (unsigned)((n_omega + kEC - 1) / kEC));
-  for (int q = k_first; st == KPM_OK && q < k_first + k_count; ++q) {
-    const int mx = q % Mx, my = q / Mx;
-    const double phx = 2.0 * M_PI * mx / Mx, phy = 2.0 * M_PI * my / My;
-    if ((st = launch_bloch(lat, h, phx, phy, H, n, s)) != KPM_OK) break;
-    double* D = evals ? evals + (size_t)(q - k_first) * n : Ebuf;
-    if (rocsolver_zheevd(hb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n,
-                         reinterpret_cast<rocblas_double_complex*>(H), (rocblas_int)n, D, Etri,
-                         dinfo + (q - k_first)) != rocblas_status_success) {
+  const dim3 lgrid((unsigned)((n_sites + kLS - 1) / kLS), (unsigned)((n_omega + kEC - 1) / kEC));
+  // k points in groups of up to k_batch: one batched eigensolver call per group
+  // (its many small panel kernels then serve the whole group), then the LDOS
+  // of each member in k order.
+  for (int q0 = k_first; st == KPM_OK && q0 < k_first + k_count; q0 += k_batch) {
+    const int kb = std::min(k_batch, k_first + k_count - q0);
+    for (int j = 0; j < kb && st == KPM_OK; ++j) {
+      const int q = q0 + j, mx = q % Mx, my = q / Mx;
+      st = launch_bloch(lat, h, 2.0 * M_PI * mx / Mx, 2.0 * M_PI * my / My, H + (size_t)j * n * n, n, s);
+    }
+    if (st != KPM_OK) break;
+    double* D = evals ? evals + (size_t)(q0 - k_first) * n : Ebuf;
+    if (rocsolver_zheevd_strided_batched(hb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n,
+                                         reinterpret_cast<rocblas_double_complex*>(H), (rocblas_int)n,
+                                         (rocblas_stride)n * n, D, (rocblas_stride)n, Etri,
+                                         (rocblas_stride)n, dinfo + (q0 - k_first),
+                                         kb) != rocblas_status_success) {
       st = KPM_EDEVICE;
       break;
     }
-    hipLaunchKernelGGL(k_sc_ldos, lgrid, dim3(kLB), 0, s, (int)n, n, H, D, dsites, n_sites, omega,
-                       n_omega, alpha, gamma0, w_up, w_dn, wk, ldos);
-    if (hipGetLastError() != hipSuccess) st = KPM_EDEVICE;
+    for (int j = 0; j < kb; ++j) {
+      hipLaunchKernelGGL(k_sc_ldos, lgrid, dim3(kLS * kQL), 0, s, (int)n, n, H + (size_t)j * n * n,
+                         D + (size_t)j * n, dsites, n_sites, omega, n_omega, alpha, gamma0, w_up, w_dn,
+                         wk, ldos);
+      if (hipGetLastError() != hipSuccess) {
+        st = KPM_EDEVICE;
+        break;
+      }
+    }
   }
   std::vector<int> info(k_count, 0);
   if (hipMemcpyAsync(info.data(), dinfo, (size_t)k_count * sizeof(int), hipMemcpyDeviceToHost, s) !=

@@ -129,8 +129,8 @@ def _load():
                                            P, P, P, P, P, POINTER(c_double), POINTER(RmftRecord),
                                            POINTER(c_int32), P, c_size_t, P]),
         "kpm_bloch_H": (c_int32, [POINTER(Lattice), P, c_double, c_double, P, ctypes.c_int64, P]),
-        "kpm_supercell_workspace_size": (c_size_t, [POINTER(Lattice)]),
-        "kpm_supercell_ldos": (c_int32, [POINTER(Lattice), P, c_int32, c_int32, c_int32, c_int32,
+        "kpm_supercell_workspace_size": (c_size_t, [POINTER(Lattice), c_int32]),
+        "kpm_supercell_ldos": (c_int32, [POINTER(Lattice), P, c_int32, c_int32, c_int32, c_int32, c_int32,
                                          POINTER(c_int32), c_int32, P, c_int32, c_double, c_double, P, P,
                                          c_int32, P, P, P, c_size_t, P]),
     }
@@ -484,6 +484,7 @@ def kpm_rmft_iterate_sdw(lat, mdl, probes, M, T, precision, ckpt_k, params, n_it
 
 KPM_SUPERCELL_MAX_N = 16384
 KPM_SUPERCELL_MAX_K = 4096
+KPM_SUPERCELL_MAX_BATCH = 16
 
 
 def kpm_bloch_H(lat, h, phi_x, phi_y, Hk, ld=None, stream=None):
@@ -496,21 +497,22 @@ def kpm_bloch_H(lat, h, phi_x, phi_y, Hk, ld=None, stream=None):
                             _stream(stream)), "kpm_bloch_H")
 
 
-def kpm_supercell_workspace_size(lat) -> int:
-    n = _lib.kpm_supercell_workspace_size(ctypes.byref(lat))
+def kpm_supercell_workspace_size(lat, k_batch=1) -> int:
+    n = _lib.kpm_supercell_workspace_size(ctypes.byref(lat), k_batch)
     if n == 0:
         raise KpmError(KPM_EINVAL, "kpm_supercell_workspace_size")
     return int(n)
 
 
 def kpm_supercell_ldos(lat, h, Mx, My, k_first, k_count, sites, omega, alpha, gamma0, w_up, w_dn,
-                       accumulate, ldos, evals, ws, stream=None):
+                       accumulate, ldos, evals, ws, k_batch=1, stream=None):
     N = lat.Lx * lat.Ly
     sites = [int(i) for i in sites]
     arr = (c_int32 * max(len(sites), 1))(*sites)
     W = int(omega.numel())
     _check(_lib.kpm_supercell_ldos(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"), Mx, My,
-                                   k_first, k_count, arr, len(sites), _ptr(omega, torch.float64, W, "omega"),
+                                   k_first, k_count, k_batch, arr, len(sites),
+                                   _ptr(omega, torch.float64, W, "omega"),
                                    W, float(alpha), float(gamma0),
                                    None if w_up is None else _ptr(w_up, torch.float64, N, "w_up"),
                                    None if w_dn is None else _ptr(w_dn, torch.float64, N, "w_dn"),

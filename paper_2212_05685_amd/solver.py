@@ -143,19 +143,21 @@ class KPMProblem:
 
     # -- magnetic super-cell ED and broadened LDOS (kpm_supercell_ldos)
     def supercell_ldos(self, h, Mx, My, sites, omega, alpha=0.25, gamma0=3e-4, w_up=None, w_dn=None,
-                       k_first=0, k_count=None, want_evals=False):
+                       k_first=0, k_count=None, want_evals=False, k_batch=1):
         """N_i(omega) for the listed sites over the Mx x My k grid (or the slice
-        k_first .. k_first + k_count - 1 of it).  Returns (ldos [S, W],
-        eigenvalues [k_count, 2N] or None)."""
-        if self._sc_ws is None:
-            nb = kpm.kpm_supercell_workspace_size(self.lat)
+        k_first .. k_first + k_count - 1 of it), k_batch k points per
+        eigensolver call.  Returns (ldos [S, W], eigenvalues [k_count, 2N] or
+        None)."""
+        nb = kpm.kpm_supercell_workspace_size(self.lat, k_batch)
+        if self._sc_ws is None or self._sc_ws.numel() < nb:
+            self._sc_ws = None
             self._sc_ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
         k_count = Mx * My - k_first if k_count is None else k_count
         N = self.lat.Lx * self.lat.Ly
         out = torch.empty(len(sites), omega.numel(), dtype=torch.float64, device=self.device)
         ev = torch.empty(k_count, 2 * N, dtype=torch.float64, device=self.device) if want_evals else None
         kpm.kpm_supercell_ldos(self.lat, h, Mx, My, k_first, k_count, sites, omega, alpha, gamma0, w_up,
-                               w_dn, False, out, ev, self._sc_ws)
+                               w_dn, False, out, ev, self._sc_ws, k_batch)
         return out, ev
 
     def rmft_iterate_sdw(self, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, mu, params, n_iter):

@@ -168,18 +168,22 @@ def test_supercell_host_validation():
     assert L.kpm_bloch_H(ctypes.byref(lat), fake, 0.1, 0.2, fake, 2 * N - 1, None) == kpm.KPM_EINVAL
     assert L.kpm_bloch_H(ctypes.byref(kpm.lattice(2, 5, 0)), fake, 0.0, 0.0, fake, 20, None) == kpm.KPM_EINVAL
     assert L.kpm_bloch_H(ctypes.byref(lat), fake, float("nan"), 0.0, fake, 2 * N, None) == kpm.KPM_EINVAL
-    full = kpm.kpm_supercell_workspace_size(lat)
+    full = kpm.kpm_supercell_workspace_size(lat, 1)
     assert full >= (2 * N) ** 2 * 16
-    assert L.kpm_supercell_workspace_size(ctypes.byref(kpm.lattice(130, 130, 0))) == 0
+    assert kpm.kpm_supercell_workspace_size(lat, 3) >= 3 * (2 * N) ** 2 * 16
+    assert L.kpm_supercell_workspace_size(ctypes.byref(kpm.lattice(130, 130, 0)), 1) == 0
+    assert L.kpm_supercell_workspace_size(ctypes.byref(lat), 0) == 0
+    assert L.kpm_supercell_workspace_size(ctypes.byref(lat), kpm.KPM_SUPERCELL_MAX_BATCH + 1) == 0
 
-    def call(Mx=2, My=2, k0=0, kc=4, sites=(0, 29), alpha=0.25, g0=3e-4, acc=0, ws_bytes=full,
+    def call(Mx=2, My=2, k0=0, kc=4, kb=1, sites=(0, 29), alpha=0.25, g0=3e-4, acc=0, ws_bytes=full,
              ws=ctypes.c_void_p(1 << 20)):
         arr = (ctypes.c_int32 * len(sites))(*sites)
-        return L.kpm_supercell_ldos(ctypes.byref(lat), fake, Mx, My, k0, kc, arr, len(sites), fake, 5,
+        return L.kpm_supercell_ldos(ctypes.byref(lat), fake, Mx, My, k0, kc, kb, arr, len(sites), fake, 5,
                                     alpha, g0, None, None, acc, fake, None, ws, ws_bytes, None)
 
     for kw in ({"Mx": 0}, {"kc": 5}, {"k0": 3, "kc": 2}, {"kc": 0}, {"sites": (0, 30)}, {"sites": (-1,)},
-               {"alpha": -0.1}, {"g0": 0.0}, {"acc": 2}, {"Mx": 4097, "My": 1}):
+               {"alpha": -0.1}, {"g0": 0.0}, {"acc": 2}, {"Mx": 4097, "My": 1}, {"kb": 0}, {"kb": 17}):
         assert call(**kw) == kpm.KPM_EINVAL, kw
     assert call(ws_bytes=full - 1) == kpm.KPM_EWORKSPACE
+    assert call(kb=2) == kpm.KPM_EWORKSPACE                 # workspace sized for one matrix
     assert call(ws=ctypes.c_void_p((1 << 20) + 8)) == kpm.KPM_EWORKSPACE

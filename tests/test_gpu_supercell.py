@@ -8,6 +8,8 @@ kpm_supercell_ldos) against the oracle (oracle/supercell.py), through the C ABI.
   maximum) against the oracle's dense eigh on 12 x 8 (2 x 2 grid, weights,
   repeated sites, 37 energies: a ragged energy block) and 24 x 12 (288 sites:
   two site blocks);
+* k points in batches (one batched eigensolver call per group, a ragged last
+  group) against the oracle;
 * the k grid split over two calls (accumulate) equals one call;
 * 48 x 48 (the paper's smallest cell, 8 x 8 grid) at one k point: eigenvalues
   and the LDOS along a line cut against the oracle.
@@ -54,7 +56,7 @@ def test_bloch_matrix_against_oracle(Lx, Ly, nv, phi):
     assert np.all(got[:, n:] == 7.0 + 3.0j)
 
 
-def _compare(cfg, Mx, My, sites, om, w=True, ks=None):
+def _compare(cfg, Mx, My, sites, om, w=True, ks=None, k_batch=1):
     st, _, _, _ = H.oracle_inputs(cfg)
     rng = np.random.default_rng(cfg.N)
     wu, wd = (rng.uniform(0.2, 1.0, cfg.N), rng.uniform(0.2, 1.0, cfg.N)) if w else (None, None)
@@ -64,7 +66,7 @@ def _compare(cfg, Mx, My, sites, om, w=True, ks=None):
     k_count = Mx * My if ks is None else len(ks)
     got, ev = pb.supercell_ldos(dev(st), Mx, My, sites, dev(om), 0.25, 3e-2,
                                 None if wu is None else dev(wu), None if wd is None else dev(wd),
-                                k_first=k_first, k_count=k_count, want_evals=True)
+                                k_first=k_first, k_count=k_count, want_evals=True, k_batch=k_batch)
     got, ev = host(got), host(ev)
     scale = np.max(np.abs(ev_ref))
     assert np.max(np.abs(ev - ev_ref)) < 1e-12 * scale
@@ -76,6 +78,12 @@ def test_supercell_ldos_small():
     cfg = _cfg(12, 8)
     sites = [0, 17, 17, 50, 95, 3]
     _compare(cfg, 2, 2, sites, np.linspace(-3.0, 3.0, 37))
+
+
+def test_supercell_ldos_batched():
+    """Five k points of a 3 x 2 grid in batches of 3 (one full, one ragged)."""
+    cfg = _cfg(12, 8, seed=13)
+    _compare(cfg, 3, 2, [1, 40, 77], np.linspace(-3.0, 3.0, 19), ks=[1, 2, 3, 4, 5], k_batch=3)
 
 
 def test_supercell_ldos_two_site_blocks():
@@ -93,7 +101,7 @@ def test_k_split_accumulates():
     sites = list(range(0, cfg.N, 5))
     full, _ = pb.supercell_ldos(dev(st), 3, 2, sites, om, 0.25, 3e-2)
     part = torch.empty_like(full)
-    ws = torch.empty(kpm.kpm_supercell_workspace_size(pb.lat), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(kpm.kpm_supercell_workspace_size(pb.lat, 1), dtype=torch.uint8, device="cuda")
     h = dev(st)
     kpm.kpm_supercell_ldos(pb.lat, h, 3, 2, 0, 2, sites, om, 0.25, 3e-2, None, None, 0, part, None, ws)
     kpm.kpm_supercell_ldos(pb.lat, h, 3, 2, 2, 4, sites, om, 0.25, 3e-2, None, None, 1, part, None, ws)
