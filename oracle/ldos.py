@@ -25,16 +25,21 @@ from .kpm_plain import plain_kpm
 
 
 def series_at(mu, a, b, energies):
-    """A(E) for moment rows mu [R, M] at the given energies -> [R, len(E)]."""
+    """A(E) for moment rows mu [R, M] at the given energies -> [R, len(E)].
+    The expansion lives on the open interval -1 < x < 1 of the rescaled
+    spectrum; A is 0 at energies outside it."""
     mu = np.atleast_2d(np.asarray(mu, dtype=np.float64))
     M = mu.shape[1]
     g = jackson(M)
     x = (np.asarray(energies, dtype=np.float64) - b) / a
-    th = np.arccos(x)
-    Tm = np.cos(np.multiply.outer(np.arange(M), th))          # [M, E]
+    inside = np.abs(x) < 1.0
+    xi = x[inside]
+    Tm = np.cos(np.multiply.outer(np.arange(M), np.arccos(xi)))   # [M, E inside]
     wts = 2.0 * g
     wts[0] = g[0]
-    return (mu * wts[None, :]) @ Tm / (np.pi * a * np.sqrt(1.0 - x ** 2))[None, :]
+    out = np.zeros((mu.shape[0], len(x)))
+    out[:, inside] = (mu * wts[None, :]) @ Tm / (np.pi * a * np.sqrt(1.0 - xi ** 2))[None, :]
+    return out
 
 
 def ldos(Hs, a, b, first, count, M, energies, Lx, Ly):
@@ -53,11 +58,15 @@ def ldos_from_eigen(H, a, b, first, count, M, energies):
     g = jackson(M)
     xn = np.clip((E - b) / a, -1.0, 1.0)
     x = (np.asarray(energies, dtype=np.float64) - b) / a
+    inside = np.abs(x) < 1.0                                   # A is 0 outside the interval
+    xi = x[inside]
     m = np.arange(M)
-    Tx = np.cos(np.multiply.outer(m, np.arccos(x)))           # [M, E]
+    Tx = np.cos(np.multiply.outer(m, np.arccos(xi)))          # [M, E inside]
     Tn = np.cos(np.multiply.outer(m, np.arccos(xn)))          # [M, n]
     wts = 2.0 * g
     wts[0] = g[0]
-    kern = (Tn.T * wts[None, :]) @ Tx                          # [n, E]
+    kern = (Tn.T * wts[None, :]) @ Tx                          # [n, E inside]
     w = np.abs(U[first:first + count, :]) ** 2                 # [I, n]
-    return (w @ kern) / (np.pi * a * np.sqrt(1.0 - x ** 2))[None, :]
+    out = np.zeros((count, len(x)))
+    out[:, inside] = (w @ kern) / (np.pi * a * np.sqrt(1.0 - xi ** 2))[None, :]
+    return out
