@@ -96,8 +96,10 @@ def test_moments_fp64_probe_blocks(P):
     assert np.max(np.abs(mu - ref)) < TOL * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("M,k,P", [(2, 2, 4), (3, 2, 1), (4, 3, 2), (48, 5, 4), (64, 64, 8), (33, 2, 16)])
+@pytest.mark.parametrize("M,k,P", [(2, 2, 4), (3, 2, 1), (4, 3, 2), (48, 5, 4), (64, 64, 8), (33, 2, 16),
+                                   (257, 2, 8)])
 def test_energy_grad_fp64(M, k, P):
+    """Checkpoint intervals 2 (every adjoint step at an anchor) to 64."""
     cfg = _cfg(M=M, ckpt_k=k)
     p, h, ab, C = _run_forward(cfg, P=P)
     omega, mu = p.grand_potential(h, ab, C, want_mu=True)
@@ -154,7 +156,7 @@ def test_general_stencil_full_rows_fp32(P):
 
 
 @pytest.mark.parametrize("M,k,P", [(2, 2, 4), (3, 2, 1), (4, 3, 2), (5, 2, 8), (48, 5, 4), (33, 2, 16),
-                                   (40, 6, 32)])
+                                   (40, 6, 32), (257, 2, 32), (40, 3, 8)])
 def test_energy_grad_fp32(M, k, P):
     """FP32 recursion, FP64 reductions: Omega, moments and rho against the FP64
     oracle to 1e-5 relative, over step counts of both parities, checkpoint
@@ -260,10 +262,13 @@ def test_grad_requires_forward():
     assert e.value.status == kpm.KPM_EWORKSPACE
 
 
-def test_batch_matches_single():
+@pytest.mark.parametrize("k", [8, 2])
+def test_batch_matches_single(k):
+    """Batch plan (plain and graph-replayed) against single lattices, at
+    checkpoint intervals 8 and 2."""
     from paper_2212_05685_amd import kpm
-    cfgs = [_cfg(9, 7, 2, M=40, ckpt_k=8), _cfg(16, 16, 4, M=40, ckpt_k=8),
-            _cfg(5, 6, 0, M=40, ckpt_k=8, probes=(wl.ProbeSpec("unit", 60),))]
+    cfgs = [_cfg(9, 7, 2, M=40, ckpt_k=k), _cfg(16, 16, 4, M=40, ckpt_k=k),
+            _cfg(5, 6, 0, M=40, ckpt_k=k, probes=(wl.ProbeSpec("unit", 60),))]
     singles, hs, abs_, Cs, rhos = [], [], [], [], []
     for cfg in cfgs:
         p, h, ab, C = _run_forward(cfg)
@@ -273,7 +278,7 @@ def test_batch_matches_single():
         Cs.append(C)
         rhos.append(torch.zeros_like(h))
     probs = [problem(c) for c in cfgs]
-    plan = kpm.kpm_batch_create([q.lat for q in probs], [q.probes for q in probs], 40, kpm.KPM_FP64, 8)
+    plan = kpm.kpm_batch_create([q.lat for q in probs], [q.probes for q in probs], 40, kpm.KPM_FP64, k)
     try:
         for use_graph in (False, True, True):
             omega = torch.zeros(len(cfgs), dtype=torch.float64, device="cuda")
