@@ -115,6 +115,34 @@ def build_stencil_sdw(Lx, Ly, n_v, t, tp, J, mu, n_up, n_dn, chi_up, chi_dn, dlt
     return st
 
 
+def vjp_sdw(Lx, Ly, n_v, t, tp, J, mu, n_up, n_dn, chi_up, chi_dn, dlt_up, dlt_dn, rho):
+    """dOmega/dtheta = sum_IJ rho_IJ dh_IJ/dtheta over both halves of the h of
+    ``build_stencil_sdw`` (kpm_build_H_sdw_vjp).  With h and rho Hermitian the
+    sum is the linearisation
+        S = sum_fwd 2 Re(rho_e h_e) + Re(rho_16) h_16 + Re(rho_17) h_17
+    (h_18 = 0), differentiated by autograd through the first derivatives of W
+    (second derivatives of W).  Complex gradients: dOmega/dRe z + i dOmega/dIm z.
+    Returns (d n_up, d n_dn, d chi_up, d chi_dn, d delta_up, d delta_dn)."""
+    def leaf(x, dt):
+        return torch.tensor(np.asarray(x, dtype=dt), requires_grad=True)
+
+    leaves = (leaf(n_up, np.float64), leaf(n_dn, np.float64), leaf(chi_up, np.complex128),
+              leaf(chi_dn, np.complex128), leaf(dlt_up, np.complex128), leaf(dlt_dn, np.complex128))
+    hop = torch.tensor(lattice.hopping(Lx, Ly, n_v, t, tp))
+    nbr = torch.tensor(np.stack([lattice.neighbour(Lx, Ly, d) for d in range(4)]))
+    W = energy_W_sdw(*leaves, hop, nbr, J, mu)
+    gnu, gnd, gcu, gcd, gdu, gdd = torch.autograd.grad(W, leaves, create_graph=True)
+    r = torch.tensor(np.asarray(rho, dtype=np.complex128))
+    S = 0.0
+    for d in range(4):
+        ents = (gcu[d].conj() / 2.0, -gdu[d] / 2.0, -gdd[d].conj() / 2.0, -gcd[d] / 2.0)
+        for q, h_e in enumerate(ents):
+            S = S + 2.0 * (r[4 * d + q] * h_e).real.sum()
+    S = S + (r[16].real * gnu).sum() + (r[17].real * (-gnd)).sum()
+    g = torch.autograd.grad(S, leaves, allow_unused=True)
+    return tuple((torch.zeros_like(x) if gi is None else gi).detach().numpy() for gi, x in zip(g, leaves))
+
+
 def order_parameters_sdw(rho):
     """Per-spin theta from a [19, N] density-matrix stencil (the inverse of
     the rho entries listed above)."""

@@ -10,7 +10,11 @@
   latter from the printed g^z alone;
 * the onsite entries are the density derivatives of W (finite differences),
   with no spin splitting at m = 0;
-* W is invariant under the global spin flip (up <-> down, m -> -m).
+* W is invariant under the global spin flip (up <-> down, m -> -m);
+* the VJP (sum_IJ rho_IJ dh_IJ/dtheta) against central finite differences of
+  the linearisation built from the first-order stencil, at m != 0, and at
+  m = 0 with equal spins against the singlet builder's VJP (itself pinned by
+  finite differences) through the chain rule of the spin embedding.
 """
 import numpy as np
 import pytest
@@ -135,3 +139,46 @@ def test_spin_flip_invariance():
     W1 = sdw.energy_W_sdw(t(nu), t(nd), t(cu), t(cd), t(du), t(dd), hop, nbr, J, MU)
     W2 = sdw.energy_W_sdw(t(nd), t(nu), t(cd), t(cu), t(dd), t(du), hop, nbr, J, MU)
     assert abs(float(W1) - float(W2)) < 1e-12 * abs(float(W1))
+
+
+def _lin(args, rho, th):
+    st = sdw.build_stencil_sdw(*args, *th)
+    return (2 * (rho[:16] * st[:16]).real.sum() + (rho[16].real * st[16].real).sum()
+            + (rho[17].real * st[17].real).sum())
+
+
+def test_vjp_matches_finite_differences():
+    Lx, Ly, nv = 4, 4, 2
+    th = list(_theta(Lx, Ly, 9, 0.05))
+    rng = np.random.default_rng(4)
+    rho = rng.normal(size=(19, Lx * Ly)) + 1j * rng.normal(size=(19, Lx * Ly))
+    args = (Lx, Ly, nv, T_, TP, J, MU)
+    g = sdw.vjp_sdw(*args, *th, rho)
+    e = 1e-6
+    rng2 = np.random.default_rng(8)
+    for trial in range(6):
+        dirs = []
+        for a in th:
+            dz = rng2.normal(size=a.shape) + (1j * rng2.normal(size=a.shape) if np.iscomplexobj(a) else 0)
+            dirs.append(dz)
+        plus = [a + e * dz for a, dz in zip(th, dirs)]
+        minus = [a - e * dz for a, dz in zip(th, dirs)]
+        fd = (_lin(args, rho, plus) - _lin(args, rho, minus)) / (2 * e)
+        an = sum(float(np.sum((np.conj(gk) * dz).real)) for gk, dz in zip(g, dirs))
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (trial, fd, an)
+
+
+def test_vjp_reduces_to_singlet():
+    Lx, Ly, nv = 5, 4, 2
+    cfg = wl.Config("s", Lx, Ly, nv, 0.15, 8, (wl.ProbeSpec("unit", 1),), vortex=True, complex_noise=0.03)
+    n, chi, dlt = wl.make_theta(cfg)
+    rng = np.random.default_rng(6)
+    rho = rng.normal(size=(19, cfg.N)) + 1j * rng.normal(size=(19, cfg.N))
+    rho[18] = 0.0                               # h_18 = 0 in the spin-polarised form
+    args = (Lx, Ly, nv, T_, TP, J, MU)
+    gn, gc, gd = builder.build_vjp(*args, n, chi, dlt, rho)
+    gu, gdn, gcu, gcd, gdu, gdd = sdw.vjp_sdw(*args, n / 2, n / 2, chi, chi, dlt, dlt, rho)
+    scale = max(np.max(np.abs(gn)), np.max(np.abs(gc)))
+    assert np.max(np.abs(0.5 * (gu + gdn) - gn)) < 1e-11 * scale
+    assert np.max(np.abs(gcu + gcd - gc)) < 1e-11 * scale
+    assert np.max(np.abs(gdu + gdd - gd)) < 1e-11 * scale
