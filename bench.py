@@ -447,9 +447,12 @@ def sdw_form(reps: int, cfg):
     th = [torch.from_numpy(x).cuda() for x in wl.make_theta_sdw(cfg, 0.03)]
     n, chi, dlt = (torch.from_numpy(x).cuda() for x in wl.make_theta(cfg))
     h = torch.zeros(19, cfg.N, dtype=torch.complex128, device="cuda")
+    rho = torch.from_numpy(wl.random_stencil(cfg.N, seed=3)).cuda()
+    grads = [torch.empty_like(x) for x in th]
     out = {}
     for name, fn in (("singlet", lambda: kpm.kpm_build_H(lat, mdl, n, chi, dlt, h)),
-                     ("sdw", lambda: kpm.kpm_build_H_sdw(lat, mdl, *th, h))):
+                     ("sdw", lambda: kpm.kpm_build_H_sdw(lat, mdl, *th, h)),
+                     ("sdw_vjp", lambda: kpm.kpm_build_H_sdw_vjp(lat, mdl, th, rho, grads))):
         fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -458,8 +461,8 @@ def sdw_form(reps: int, cfg):
         e1.record()
         torch.cuda.synchronize()
         out[name] = e0.elapsed_time(e1) / reps * 1e3
-    log(f"builders: singlet {out['singlet']:.1f} us, sdw {out['sdw']:.1f} us")
-    return {"us_build_singlet": out["singlet"], "us_build_sdw": out["sdw"],
+    log(f"builders: singlet {out['singlet']:.1f} us, sdw {out['sdw']:.1f} us, sdw vjp {out['sdw_vjp']:.1f} us")
+    return {"us_build_singlet": out["singlet"], "us_build_sdw": out["sdw"], "us_vjp_sdw": out["sdw_vjp"],
             "h_bytes_written": 19 * 16 * cfg.N}
 
 

@@ -145,6 +145,20 @@ int kpm_build_H_sdw(const kpm_lattice* lat, const kpm_model* model, const double
                     const double* n_dn, const double* chi_up, const double* chi_dn,
                     const double* delta_up, const double* delta_dn, double* h, void* stream);
 
+/* Vector-Jacobian product of kpm_build_H_sdw, as kpm_build_H_vjp: given rho
+ * = dOmega/dh ([19][N] complex, Hermitian), writes dOmega/dtheta = sum_IJ
+ * rho_IJ dh_IJ/dtheta over all matrix elements for the per-spin parameters
+ * (second derivatives of the W of kpm_build_H_sdw, App. A).  Complex
+ * gradients use dOmega/dRe z + i dOmega/dIm z.  dn_up, dn_dn [N] and dchi_up,
+ * dchi_dn, ddelta_up, ddelta_dn [4][N] complex are overwritten (ddelta is 0 on
+ * the diagonal directions).  rho_{i0,i1} (entry 18) does not enter: that
+ * element of h is 0 for every theta. */
+int kpm_build_H_sdw_vjp(const kpm_lattice* lat, const kpm_model* model, const double* n_up,
+                        const double* n_dn, const double* chi_up, const double* chi_dn,
+                        const double* delta_up, const double* delta_dn, const double* rho,
+                        double* dn_up, double* dn_dn, double* dchi_up, double* dchi_dn,
+                        double* ddelta_up, double* ddelta_dn, void* stream);
+
 /* Vector-Jacobian product of kpm_build_H: given rho = dOmega/dh on the
  * stencil ([19][N] complex), writes dOmega/dtheta = sum_IJ rho_IJ dh_IJ/dtheta
  * over all matrix elements (both halves).  Complex gradients use the

@@ -21,6 +21,9 @@ hipError_t launch_build_vjp(const ModelDev&, const double*, const double*, const
                             const double*, double*, double*, double*, hipStream_t);
 hipError_t launch_build_sdw(const ModelDev&, const double*, const double*, const double*,
                             const double*, const double*, const double*, double*, hipStream_t);
+hipError_t launch_build_sdw_vjp(const ModelDev&, const double*, const double*, const double*,
+                                const double*, const double*, const double*, const double*, double*,
+                                double*, double*, double*, double*, double*, hipStream_t);
 hipError_t launch_bounds(int, int, const double*, double*, hipStream_t);
 hipError_t launch_rescale(const InstDev*, const int4*, int, bool, hipStream_t);
 hipError_t launch_coeffs(int, int, double, const double*, double*, hipStream_t);
@@ -521,6 +524,21 @@ int kpm_build_H_sdw(const kpm_lattice* lat, const kpm_model* model, const double
               model->mu};
   KPM_HIP(launch_build_sdw(md, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, h,
                            static_cast<hipStream_t>(stream)));
+  return KPM_OK;
+}
+
+int kpm_build_H_sdw_vjp(const kpm_lattice* lat, const kpm_model* model, const double* n_up,
+                        const double* n_dn, const double* chi_up, const double* chi_dn,
+                        const double* delta_up, const double* delta_dn, const double* rho,
+                        double* dn_up, double* dn_dn, double* dchi_up, double* dchi_dn,
+                        double* ddelta_up, double* ddelta_dn, void* stream) {
+  if (!valid_lattice(lat) || !model || !n_up || !n_dn || !chi_up || !chi_dn || !delta_up ||
+      !delta_dn || !rho || !dn_up || !dn_dn || !dchi_up || !dchi_dn || !ddelta_up || !ddelta_dn)
+    return KPM_EINVAL;
+  ModelDev md{lat->Lx, lat->Ly, lat->n_vortex, lat->Lx * lat->Ly, model->t, model->tp, model->J,
+              model->mu};
+  KPM_HIP(launch_build_sdw_vjp(md, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, rho, dn_up, dn_dn,
+                               dchi_up, dchi_dn, ddelta_up, ddelta_dn, static_cast<hipStream_t>(stream)));
   return KPM_OK;
 }
 

@@ -135,19 +135,50 @@ __global__ __launch_bounds__(kBlock) void k_build_h(ModelDev md, const double* _
 //   b = 2 (|Dbar|^2 - |chibar|^2),  X = 1 + 12 n_i n_j / sqrt(A_i A_j),
 // plus -mu sum_i n_i.  h_IJ = dW/drho_IJ as for kpm_build_H, written out by
 // the chain rule through (delta, m) of each site.
-struct SiteS {
-  double n, m, A, gxy, gt[2];        // gt[0] spin up, gt[1] spin down
-  double dA[2], dgxy[2], dgt[2][2];  // d/dn_up (index 0), d/dn_dn (index 1)
+// Scalar with one tangent (forward-mode derivative): the VJP of this builder
+// runs the same code on (value, tangent) pairs.
+struct Dual {
+  double v, d;
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)};
+}
+__device__ __forceinline__ Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
+__device__ __forceinline__ Dual operator+(double a, Dual b) { return {a + b.v, b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, double b) { return {a.v - b, a.d}; }
+__device__ __forceinline__ Dual operator-(double a, Dual b) { return {a - b.v, -b.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ Dual operator/(Dual a, double b) { return {a.v / b, a.d / b}; }
+__device__ __forceinline__ Dual operator/(double a, Dual b) { return {a / b.v, -a * b.d / (b.v * b.v)}; }
+__device__ __forceinline__ Dual sqrt_t(Dual a) {
+  const double r = ::sqrt(a.v);
+  return {r, a.d / (2.0 * r)};
+}
+__device__ __forceinline__ double sqrt_t(double a) { return ::sqrt(a); }
+
+template <typename T> struct CxT {
+  T x, y;
 };
 
-__device__ __forceinline__ SiteS site_s(double nu, double nd) {
-  SiteS f;
+template <typename T> struct SiteS {
+  T n, m, A, gxy, gt[2];        // gt[0] spin up, gt[1] spin down
+  T dA[2], dgxy[2], dgt[2][2];  // d/dn_up (index 0), d/dn_dn (index 1)
+};
+
+template <typename T>
+__device__ __forceinline__ SiteS<T> site_s(T nu, T nd) {
+  SiteS<T> f;
   f.n = nu + nd;
-  const double dl = 1.0 - f.n;
+  const T dl = 1.0 - f.n;
   f.m = 0.5 * (nu - nd);
   f.A = 1.0 - dl * dl + 4.0 * f.m * f.m;
   f.gxy = 2.0 * f.n / f.A;
-  const double B = 2.0 * dl * (1.0 - dl) / f.A;
+  const T B = 2.0 * dl * (1.0 - dl) / f.A;
   for (int q = 0; q < 2; ++q) {                         // derivative w.r.t. n_up (q = 0) or n_dn
     const double sq = q == 0 ? 1.0 : -1.0;
     f.dA[q] = 2.0 * dl + 4.0 * sq * f.m;
@@ -155,88 +186,97 @@ __device__ __forceinline__ SiteS site_s(double nu, double nd) {
   }
   for (int s = 0; s < 2; ++s) {
     const double ss = s == 0 ? 1.0 : -1.0;
-    const double p = 1.0 + dl + 2.0 * ss * f.m, qd = 1.0 + dl - 2.0 * ss * f.m;
-    const double Q = p / qd;
-    f.gt[s] = sqrt(B * Q);
+    const T p = 1.0 + dl + 2.0 * ss * f.m, qd = 1.0 + dl - 2.0 * ss * f.m;
+    const T Q = p / qd;
+    f.gt[s] = sqrt_t(B * Q);
     for (int q = 0; q < 2; ++q) {
       const double sq = q == 0 ? 1.0 : -1.0;
-      const double dB = (2.0 * (2.0 * dl - 1.0) * f.A - 2.0 * dl * (1.0 - dl) * f.dA[q]) / (f.A * f.A);
+      const T dB = (2.0 * (2.0 * dl - 1.0) * f.A - 2.0 * dl * (1.0 - dl) * f.dA[q]) / (f.A * f.A);
       const double dp = -1.0 + ss * sq, dq = -1.0 - ss * sq;
-      const double dQ = (dp * qd - p * dq) / (qd * qd);
+      const T dQ = (dp * qd - p * dq) / (qd * qd);
       f.dgt[s][q] = (dB * Q + B * dQ) / (2.0 * f.gt[s]);
     }
   }
   return f;
 }
 
-struct BondIn {
-  double2 t, cu, cd, du, dd;
+template <typename T> struct BondIn {
+  double2 t;                     // bare Peierls hopping (no tangent)
+  CxT<T> cu, cd, du, dd;
 };
 
 // dW_b/dn_{a q} for the end a of a bond whose other end is b (W_b is
 // symmetric in its two ends).
-__device__ __forceinline__ void bond_dn(const SiteS& a, const SiteS& b, const BondIn& v, bool nn,
-                                        double J, double out[2]) {
-  const double Ru = v.t.x * v.cu.x - v.t.y * v.cu.y, Rd = v.t.x * v.cd.x - v.t.y * v.cd.y;
+template <typename T>
+__device__ __forceinline__ void bond_dn(const SiteS<T>& a, const SiteS<T>& b, const BondIn<T>& v, bool nn,
+                                        double J, T out[2]) {
+  const T Ru = v.t.x * v.cu.x - v.t.y * v.cu.y, Rd = v.t.x * v.cd.x - v.t.y * v.cd.y;
   for (int q = 0; q < 2; ++q)
     out[q] = -2.0 * (Ru * b.gt[0] * a.dgt[0][q] + Rd * b.gt[1] * a.dgt[1][q]);
   if (!nn) return;
-  const double cbx = 0.5 * (v.cu.x + v.cd.x), cby = 0.5 * (v.cu.y + v.cd.y);
-  const double dbx = 0.5 * (v.du.x + v.dd.x), dby = 0.5 * (v.du.y + v.dd.y);
-  const double bb = 2.0 * (dbx * dbx + dby * dby - cbx * cbx - cby * cby);
-  const double mm = a.m * b.m;
-  const double sAB = sqrt(a.A * b.A);
-  const double X = 1.0 + 12.0 * a.n * b.n / sAB;
-  const double den = bb - 4.0 * mm;
-  const double R = (bb - 4.0 * mm * X * X) / den;
-  const double dRdmm = 4.0 * bb * (1.0 - X * X) / (den * den);
-  const double dRdX = -8.0 * mm * X / den;
-  const double gxy = a.gxy * b.gxy, gz = gxy * R;
-  const double q2 = v.cu.x * v.cu.x + v.cu.y * v.cu.y + v.cd.x * v.cd.x + v.cd.y * v.cd.y +
-                    v.du.x * v.du.x + v.du.y * v.du.y + v.dd.x * v.dd.x + v.dd.y * v.dd.y;
-  const double Szz = mm - 0.25 * q2;
-  const double Sxy = -((v.cu.x * v.cd.x + v.cu.y * v.cd.y) + (v.du.x * v.dd.x + v.du.y * v.dd.y));
+  const T cbx = 0.5 * (v.cu.x + v.cd.x), cby = 0.5 * (v.cu.y + v.cd.y);
+  const T dbx = 0.5 * (v.du.x + v.dd.x), dby = 0.5 * (v.du.y + v.dd.y);
+  const T bb = 2.0 * (dbx * dbx + dby * dby - cbx * cbx - cby * cby);
+  const T mm = a.m * b.m;
+  const T sAB = sqrt_t(a.A * b.A);
+  const T X = 1.0 + 12.0 * a.n * b.n / sAB;
+  const T den = bb - 4.0 * mm;
+  const T R = (bb - 4.0 * mm * X * X) / den;
+  const T dRdmm = 4.0 * bb * (1.0 - X * X) / (den * den);
+  const T dRdX = -8.0 * mm * X / den;
+  const T gxy = a.gxy * b.gxy, gz = gxy * R;
+  const T q2 = v.cu.x * v.cu.x + v.cu.y * v.cu.y + v.cd.x * v.cd.x + v.cd.y * v.cd.y +
+               v.du.x * v.du.x + v.du.y * v.du.y + v.dd.x * v.dd.x + v.dd.y * v.dd.y;
+  const T Szz = mm - 0.25 * q2;
+  const T Sxy = -((v.cu.x * v.cd.x + v.cu.y * v.cd.y) + (v.du.x * v.dd.x + v.du.y * v.dd.y));
   for (int q = 0; q < 2; ++q) {
     const double sq = q == 0 ? 1.0 : -1.0;
-    const double dmm = 0.5 * sq * b.m;
-    const double dX = 12.0 * b.n * (1.0 / sAB - a.n * a.dA[q] / (2.0 * a.A * sAB));
-    const double dgxy = b.gxy * a.dgxy[q];
-    const double dgz = dgxy * R + gxy * (dRdmm * dmm + dRdX * dX);
-    out[q] += J * (dgz * Szz + gz * dmm + dgxy * Sxy);
+    const T dmm = 0.5 * sq * b.m;
+    const T dX = 12.0 * b.n * (1.0 / sAB - a.n * a.dA[q] / (2.0 * a.A * sAB));
+    const T dgxy = b.gxy * a.dgxy[q];
+    const T dgz = dgxy * R + gxy * (dRdmm * dmm + dRdX * dX);
+    out[q] = out[q] + J * (dgz * Szz + gz * dmm + dgxy * Sxy);
   }
 }
 
 // Wirtinger derivatives dW_b/dz of the bond variables z = chi_up, chi_dn,
 // Delta_up, Delta_dn (order of `g`).
-__device__ __forceinline__ void bond_dz(const SiteS& a, const SiteS& b, const BondIn& v, bool nn,
-                                        double J, double2 g[4]) {
-  g[0] = make_double2(-a.gt[0] * b.gt[0] * v.t.x, -a.gt[0] * b.gt[0] * v.t.y);
-  g[1] = make_double2(-a.gt[1] * b.gt[1] * v.t.x, -a.gt[1] * b.gt[1] * v.t.y);
-  g[2] = make_double2(0.0, 0.0);
-  g[3] = make_double2(0.0, 0.0);
+template <typename T>
+__device__ __forceinline__ void bond_dz(const SiteS<T>& a, const SiteS<T>& b, const BondIn<T>& v, bool nn,
+                                        double J, CxT<T> g[4]) {
+  const T tt = a.gt[0] * b.gt[0], td = a.gt[1] * b.gt[1];
+  g[0] = CxT<T>{-tt * v.t.x, -tt * v.t.y};
+  g[1] = CxT<T>{-td * v.t.x, -td * v.t.y};
+  g[2] = CxT<T>{T{}, T{}};
+  g[3] = CxT<T>{T{}, T{}};
   if (!nn) return;
-  const double cbx = 0.5 * (v.cu.x + v.cd.x), cby = 0.5 * (v.cu.y + v.cd.y);
-  const double dbx = 0.5 * (v.du.x + v.dd.x), dby = 0.5 * (v.du.y + v.dd.y);
-  const double bb = 2.0 * (dbx * dbx + dby * dby - cbx * cbx - cby * cby);
-  const double mm = a.m * b.m;
-  const double X = 1.0 + 12.0 * a.n * b.n / sqrt(a.A * b.A);
-  const double den = bb - 4.0 * mm;
-  const double R = (bb - 4.0 * mm * X * X) / den;
-  const double dRdb = 4.0 * mm * (X * X - 1.0) / (den * den);
-  const double gxy = a.gxy * b.gxy, gz = gxy * R;
-  const double q2 = v.cu.x * v.cu.x + v.cu.y * v.cu.y + v.cd.x * v.cd.x + v.cd.y * v.cd.y +
-                    v.du.x * v.du.x + v.du.y * v.du.y + v.dd.x * v.dd.x + v.dd.y * v.dd.y;
-  const double Szz = mm - 0.25 * q2;
+  const T cbx = 0.5 * (v.cu.x + v.cd.x), cby = 0.5 * (v.cu.y + v.cd.y);
+  const T dbx = 0.5 * (v.du.x + v.dd.x), dby = 0.5 * (v.du.y + v.dd.y);
+  const T bb = 2.0 * (dbx * dbx + dby * dby - cbx * cbx - cby * cby);
+  const T mm = a.m * b.m;
+  const T X = 1.0 + 12.0 * a.n * b.n / sqrt_t(a.A * b.A);
+  const T den = bb - 4.0 * mm;
+  const T R = (bb - 4.0 * mm * X * X) / den;
+  const T dRdb = 4.0 * mm * (X * X - 1.0) / (den * den);
+  const T gxy = a.gxy * b.gxy, gz = gxy * R;
+  const T q2 = v.cu.x * v.cu.x + v.cu.y * v.cu.y + v.cd.x * v.cd.x + v.cd.y * v.cd.y +
+               v.du.x * v.du.x + v.du.y * v.du.y + v.dd.x * v.dd.x + v.dd.y * v.dd.y;
+  const T Szz = mm - 0.25 * q2;
   // d b/d chi_s = -conj(chibar), d b/d Delta_s = conj(Dbar)
-  const double k = J * gxy * dRdb * Szz;
-  g[0].x += k * (-cbx) + J * (-0.25 * gz * v.cu.x - 0.5 * gxy * v.cd.x);
-  g[0].y += k * (cby) + J * (0.25 * gz * v.cu.y + 0.5 * gxy * v.cd.y);
-  g[1].x += k * (-cbx) + J * (-0.25 * gz * v.cd.x - 0.5 * gxy * v.cu.x);
-  g[1].y += k * (cby) + J * (0.25 * gz * v.cd.y + 0.5 * gxy * v.cu.y);
-  g[2].x += k * (dbx) + J * (-0.25 * gz * v.du.x - 0.5 * gxy * v.dd.x);
-  g[2].y += k * (-dby) + J * (0.25 * gz * v.du.y + 0.5 * gxy * v.dd.y);
-  g[3].x += k * (dbx) + J * (-0.25 * gz * v.dd.x - 0.5 * gxy * v.du.x);
-  g[3].y += k * (-dby) + J * (0.25 * gz * v.dd.y + 0.5 * gxy * v.du.y);
+  const T k = J * gxy * dRdb * Szz;
+  g[0].x = g[0].x + k * (-cbx) + J * (-0.25 * gz * v.cu.x - 0.5 * gxy * v.cd.x);
+  g[0].y = g[0].y + k * (cby) + J * (0.25 * gz * v.cu.y + 0.5 * gxy * v.cd.y);
+  g[1].x = g[1].x + k * (-cbx) + J * (-0.25 * gz * v.cd.x - 0.5 * gxy * v.cu.x);
+  g[1].y = g[1].y + k * (cby) + J * (0.25 * gz * v.cd.y + 0.5 * gxy * v.cu.y);
+  g[2].x = g[2].x + k * (dbx) + J * (-0.25 * gz * v.du.x - 0.5 * gxy * v.dd.x);
+  g[2].y = g[2].y + k * (-dby) + J * (0.25 * gz * v.du.y + 0.5 * gxy * v.dd.y);
+  g[3].x = g[3].x + k * (dbx) + J * (-0.25 * gz * v.dd.x - 0.5 * gxy * v.du.x);
+  g[3].y = g[3].y + k * (-dby) + J * (0.25 * gz * v.dd.y + 0.5 * gxy * v.du.y);
+}
+
+__device__ __forceinline__ CxT<double> cx_in(const double* p, long long idx) {
+  const double2 v = ld2(p, idx);
+  return CxT<double>{v.x, v.y};
 }
 
 __global__ __launch_bounds__(kBlock) void k_build_sdw(ModelDev md, const double* __restrict__ nu,
@@ -249,19 +289,19 @@ __global__ __launch_bounds__(kBlock) void k_build_sdw(ModelDev md, const double*
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= md.N) return;
   const int N = md.N;
-  const SiteS fi = site_s(nu[i], nd[i]);
+  const SiteS<double> fi = site_s(nu[i], nd[i]);
   double eu = -md.mu, ed = -md.mu;
   for (int d = 0; d < 4; ++d) {
     const bool nn = d < 2;
     // forward bond (i, j = i + d), stored here
     {
       const int j = nbr_of(i, d, +1, md.Lx, md.Ly);
-      const SiteS fj = site_s(nu[j], nd[j]);
+      const SiteS<double> fj = site_s(nu[j], nd[j]);
       const long long e = (long long)d * N + i;
-      const BondIn v{hop(md, i, d), ld2(cu, e), ld2(cd, e), ld2(du, e), ld2(dd, e)};
-      double2 g[4];
+      const BondIn<double> v{hop(md, i, d), cx_in(cu, e), cx_in(cd, e), cx_in(du, e), cx_in(dd, e)};
+      CxT<double> g[4];
       bond_dz(fi, fj, v, nn, md.J, g);
-      h[(long long)(4 * d + 0) * N + i] = g[0];                               // dW/dchi_up
+      h[(long long)(4 * d + 0) * N + i] = make_double2(g[0].x, g[0].y);       // dW/dchi_up
       h[(long long)(4 * d + 1) * N + i] = make_double2(-g[2].x, g[2].y);      // -conj dW/dDelta_up
       h[(long long)(4 * d + 2) * N + i] = make_double2(-g[3].x, -g[3].y);     // -dW/dDelta_dn
       h[(long long)(4 * d + 3) * N + i] = make_double2(-g[1].x, g[1].y);      // -conj dW/dchi_dn
@@ -273,9 +313,9 @@ __global__ __launch_bounds__(kBlock) void k_build_sdw(ModelDev md, const double*
     // backward bond (k = i - d, i), stored at k
     {
       const int k = nbr_of(i, d, -1, md.Lx, md.Ly);
-      const SiteS fk = site_s(nu[k], nd[k]);
+      const SiteS<double> fk = site_s(nu[k], nd[k]);
       const long long e = (long long)d * N + k;
-      const BondIn v{hop(md, k, d), ld2(cu, e), ld2(cd, e), ld2(du, e), ld2(dd, e)};
+      const BondIn<double> v{hop(md, k, d), cx_in(cu, e), cx_in(cd, e), cx_in(du, e), cx_in(dd, e)};
       double o[2];
       bond_dn(fi, fk, v, nn, md.J, o);
       eu += o[0];
@@ -285,6 +325,85 @@ __global__ __launch_bounds__(kBlock) void k_build_sdw(ModelDev md, const double*
   h[(long long)16 * N + i] = make_double2(eu, 0.0);
   h[(long long)17 * N + i] = make_double2(-ed, 0.0);
   h[(long long)18 * N + i] = make_double2(0.0, 0.0);
+}
+
+// VJP of k_build_sdw: dOmega/dtheta = sum_IJ rho_IJ dh_IJ/dtheta.  Since
+// h_IJ = dW/drho_IJ, this is the derivative of the theta-gradient of W along
+// the theta-direction v that moves the rho-coordinates by rho (symmetry of
+// second derivatives): v = (Re rho_16, -Re rho_17, rho_e0, -conj rho_e3,
+// -conj rho_e1, -rho_e2).  k_build_sdw's own chain rule runs on Dual values
+// with those tangents; a complex parameter's output is 2 conj(tangent of
+// dW/dz) = d/dRe z + i d/dIm z.
+__device__ __forceinline__ Dual site_tan(const double* n, const double2* rho, int N, int j, int e,
+                                         double sgn) {
+  return Dual{n[j], sgn * rho[(long long)e * N + j].x};
+}
+
+__device__ __forceinline__ BondIn<Dual> bond_tan(const ModelDev& md, const double* cu, const double* cd,
+                                                 const double* du, const double* dd,
+                                                 const double2* rho, int k, int d) {
+  const int N = md.N;
+  const long long e = (long long)d * N + k;
+  const double2 r0 = rho[(long long)(4 * d + 0) * N + k], r1 = rho[(long long)(4 * d + 1) * N + k];
+  const double2 r2 = rho[(long long)(4 * d + 2) * N + k], r3 = rho[(long long)(4 * d + 3) * N + k];
+  const double2 a = ld2(cu, e), b = ld2(cd, e), c = ld2(du, e), f = ld2(dd, e);
+  BondIn<Dual> v;
+  v.t = hop(md, k, d);
+  v.cu = CxT<Dual>{Dual{a.x, r0.x}, Dual{a.y, r0.y}};      // + rho_e0
+  v.cd = CxT<Dual>{Dual{b.x, -r3.x}, Dual{b.y, r3.y}};     // - conj rho_e3
+  v.du = CxT<Dual>{Dual{c.x, -r1.x}, Dual{c.y, r1.y}};     // - conj rho_e1
+  v.dd = CxT<Dual>{Dual{f.x, -r2.x}, Dual{f.y, -r2.y}};    // - rho_e2
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_build_sdw_vjp(ModelDev md, const double* __restrict__ nu,
+                                                          const double* __restrict__ nd,
+                                                          const double* __restrict__ cu,
+                                                          const double* __restrict__ cd,
+                                                          const double* __restrict__ du,
+                                                          const double* __restrict__ dd,
+                                                          const double2* __restrict__ rho,
+                                                          double* __restrict__ gnu,
+                                                          double* __restrict__ gnd,
+                                                          double2* __restrict__ gcu,
+                                                          double2* __restrict__ gcd,
+                                                          double2* __restrict__ gdu,
+                                                          double2* __restrict__ gdd) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= md.N) return;
+  const int N = md.N;
+  const SiteS<Dual> fi = site_s(site_tan(nu, rho, N, i, 16, 1.0), site_tan(nd, rho, N, i, 17, -1.0));
+  double tu = 0.0, td = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    const bool nn = d < 2;
+    {
+      const int j = nbr_of(i, d, +1, md.Lx, md.Ly);
+      const SiteS<Dual> fj = site_s(site_tan(nu, rho, N, j, 16, 1.0), site_tan(nd, rho, N, j, 17, -1.0));
+      const BondIn<Dual> v = bond_tan(md, cu, cd, du, dd, rho, i, d);
+      CxT<Dual> g[4];
+      bond_dz(fi, fj, v, nn, md.J, g);
+      const long long e = (long long)d * N + i;
+      gcu[e] = make_double2(2.0 * g[0].x.d, -2.0 * g[0].y.d);
+      gcd[e] = make_double2(2.0 * g[1].x.d, -2.0 * g[1].y.d);
+      gdu[e] = make_double2(2.0 * g[2].x.d, -2.0 * g[2].y.d);
+      gdd[e] = make_double2(2.0 * g[3].x.d, -2.0 * g[3].y.d);
+      Dual o[2];
+      bond_dn(fi, fj, v, nn, md.J, o);
+      tu += o[0].d;
+      td += o[1].d;
+    }
+    {
+      const int k = nbr_of(i, d, -1, md.Lx, md.Ly);
+      const SiteS<Dual> fk = site_s(site_tan(nu, rho, N, k, 16, 1.0), site_tan(nd, rho, N, k, 17, -1.0));
+      const BondIn<Dual> v = bond_tan(md, cu, cd, du, dd, rho, k, d);
+      Dual o[2];
+      bond_dn(fi, fk, v, nn, md.J, o);
+      tu += o[0].d;
+      td += o[1].d;
+    }
+  }
+  gnu[i] = tu;
+  gnd[i] = td;
 }
 
 // Per-site pieces of the VJP that every neighbour needs: w_i = Re rho16 -
@@ -544,6 +663,18 @@ hipError_t launch_build_sdw(const ModelDev& md, const double* nu, const double* 
   dim3 grid((md.N + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_build_sdw, grid, dim3(kBlock), 0, s, md, nu, nd, cu, cd, du, dd,
                      reinterpret_cast<double2*>(h));
+  return hipGetLastError();
+}
+
+hipError_t launch_build_sdw_vjp(const ModelDev& md, const double* nu, const double* nd,
+                                const double* cu, const double* cd, const double* du,
+                                const double* dd, const double* rho, double* gnu, double* gnd,
+                                double* gcu, double* gcd, double* gdu, double* gdd, hipStream_t s) {
+  dim3 grid((md.N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_build_sdw_vjp, grid, dim3(kBlock), 0, s, md, nu, nd, cu, cd, du, dd,
+                     reinterpret_cast<const double2*>(rho), gnu, gnd, reinterpret_cast<double2*>(gcu),
+                     reinterpret_cast<double2*>(gcd), reinterpret_cast<double2*>(gdu),
+                     reinterpret_cast<double2*>(gdd));
   return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ EXPORTS = (
     "kpm_batch_destroy", "kpm_set_probe_block", "kpm_profile_begin", "kpm_profile_end",
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
     "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
-    "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_bloch_H", "kpm_supercell_workspace_size",
+    "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_build_H_sdw_vjp", "kpm_bloch_H", "kpm_supercell_workspace_size",
     "kpm_supercell_ldos",
 )
 
@@ -128,6 +128,7 @@ def _load():
                                            c_double, c_int32, c_int32, POINTER(RmftParams), c_int32, P,
                                            P, P, P, P, P, POINTER(c_double), POINTER(RmftRecord),
                                            POINTER(c_int32), P, c_size_t, P]),
+        "kpm_build_H_sdw_vjp": (c_int32, [POINTER(Lattice), POINTER(Model)] + [P] * 14),
         "kpm_bloch_H": (c_int32, [POINTER(Lattice), P, c_double, c_double, P, ctypes.c_int64, P]),
         "kpm_supercell_workspace_size": (c_size_t, [POINTER(Lattice), c_int32]),
         "kpm_supercell_ldos": (c_int32, [POINTER(Lattice), P, c_int32, c_int32, c_int32, c_int32, c_int32,
@@ -229,6 +230,15 @@ def kpm_build_H_sdw(lat, mdl, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, h,
                                 _ptr(delta_up, torch.complex128, 4 * N, "delta_up"),
                                 _ptr(delta_dn, torch.complex128, 4 * N, "delta_dn"),
                                 _ptr(h, torch.complex128, NENT * N, "h"), _stream(stream)), "kpm_build_H_sdw")
+
+
+def kpm_build_H_sdw_vjp(lat, mdl, theta, rho, grads, stream=None):
+    """theta, grads: (n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn) device
+    tensors (grads overwritten)."""
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_build_H_sdw_vjp(ctypes.byref(lat), ctypes.byref(mdl), *_spin_ptrs(lat, *theta),
+                                    _ptr(rho, torch.complex128, NENT * N, "rho"), *_spin_ptrs(lat, *grads),
+                                    _stream(stream)), "kpm_build_H_sdw_vjp")
 
 
 def kpm_build_H_vjp(lat, mdl, n, chi, delta, rho, dn, dchi, ddelta, stream=None):

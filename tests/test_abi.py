@@ -119,6 +119,13 @@ def test_rmft_host_validation():
     assert done.value == -1                     # nothing ran
     assert kpm.strerror(kpm.KPM_ENOCONV).startswith("chemical-potential")
 
+    mdl0 = kpm.model(1.0, -0.3, 0.3, 0.0)
+    # 13 pointers (6 parameters, rho, 6 outputs) then the stream; the last output missing
+    assert kpm._lib.kpm_build_H_sdw_vjp(ctypes.byref(lat), ctypes.byref(mdl0), *([fake] * 12), None,
+                                        None) == kpm.KPM_EINVAL
+    assert kpm._lib.kpm_build_H_sdw_vjp(ctypes.byref(kpm.lattice(2, 8, 0)), ctypes.byref(mdl0), *([fake] * 13),
+                                        None) == kpm.KPM_EINVAL
+
     # the spin-polarised entries: same checks, plus a missing spin array
     for mix in (-0.1, 1.5, float("nan")):
         assert kpm._lib.kpm_rmft_update_sdw(ctypes.byref(lat), fake, mix, fake, fake, fake, fake, fake,

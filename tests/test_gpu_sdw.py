@@ -5,7 +5,10 @@ oracle (oracle/sdw.py: autograd of the reconstructed W), through the C ABI.
   magnetisation m = 0, 0.03, 0.06 and spin-dependent bond noise: every
   stencil entry to 1e-12 of max |h|;
 * the SDW h through the rest of the path: FP64 energy + gradient of a small
-  lattice against the oracle's plain KPM on the oracle's own h, 1e-10.
+  lattice against the oracle's plain KPM on the oracle's own h, 1e-10;
+* the VJP (kpm_build_H_sdw_vjp) against the oracle's second derivatives of W
+  (autograd), on a seeded Hermitian stand-in rho, at the same lattices and
+  magnetisations: every output to 1e-11 of its largest entry.
 """
 import numpy as np
 import pytest
@@ -55,3 +58,23 @@ def test_sdw_energy_grad_against_oracle():
     assert pb.status() == 0
     assert abs(float(host(out["omega"])[0]) - ref["omega"]) < 1e-10 * abs(ref["omega"])
     assert H.rel_err(host(out["rho"]), ref["rho"]) < 1e-10
+
+
+@pytest.mark.parametrize("Lx,Ly", [(17, 19), (100, 100)])
+@pytest.mark.parametrize("m_amp", [0.0, 0.03, 0.06])
+def test_sdw_vjp_against_oracle(Lx, Ly, m_amp):
+    from paper_2212_05685_amd import kpm
+
+    cfg = wl.Config("s", Lx, Ly, 2, 0.15, 8, (wl.ProbeSpec("unit", 1),), vortex=True,
+                    complex_noise=0.02, seed=Lx + 5)
+    th = wl.make_theta_sdw(cfg, m_amp)
+    rho = wl.random_stencil(cfg.N, seed=Lx * 7 + 1)
+    rho[16:18] = rho[16:18].real
+    ref = sdw.vjp_sdw(Lx, Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, *th, rho)
+    lat = kpm.lattice(cfg.Lx, cfg.Ly, cfg.n_v)
+    mdl = kpm.model(cfg.t, cfg.tp, cfg.J, cfg.mu)
+    grads = [torch.full_like(dev(x), 7.0) for x in th]
+    kpm.kpm_build_H_sdw_vjp(lat, mdl, [dev(x) for x in th], dev(rho), grads)
+    for got, r in zip(grads, ref):
+        got = host(got)
+        assert np.max(np.abs(got - r)) < 1e-11 * max(np.max(np.abs(r)), 1e-300)
