@@ -60,6 +60,19 @@ class KPMProblem:
         kpm.kpm_build_H_vjp(self.lat, self.mdl, n, chi, delta, rho, dn, dchi, ddelta)
         return dn, dchi, ddelta
 
+    def build_H_sdw(self, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn):
+        h = self.zeros(kpm.NENT, self.N)
+        kpm.kpm_build_H_sdw(self.lat, self.mdl, n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn, h)
+        return h
+
+    def build_H_sdw_vjp(self, theta, rho):
+        """theta: (n_up, n_dn, chi_up, chi_dn, delta_up, delta_dn).  Returns the
+        six gradients in the same order."""
+        grads = [self.zeros(self.N, dtype=torch.float64), self.zeros(self.N, dtype=torch.float64)]
+        grads += [self.zeros(4, self.N) for _ in range(4)]
+        kpm.kpm_build_H_sdw_vjp(self.lat, self.mdl, list(theta), rho, grads)
+        return tuple(grads)
+
     def bounds(self, h):
         ab = self.zeros(2, dtype=torch.float64)
         kpm.kpm_bounds(self.lat, h, ab)

@@ -8,7 +8,10 @@ oracle (oracle/sdw.py: autograd of the reconstructed W), through the C ABI.
   lattice against the oracle's plain KPM on the oracle's own h, 1e-10;
 * the VJP (kpm_build_H_sdw_vjp) against the oracle's second derivatives of W
   (autograd), on a seeded Hermitian stand-in rho, at the same lattices and
-  magnetisations: every output to 1e-11 of its largest entry.
+  magnetisations: every output to 1e-11 of its largest entry;
+* dOmega/dtheta through autograd.GrandPotentialSDW (adjoint recursion, then
+  the VJP) against the oracle's plain-KPM rho pushed through the oracle's VJP
+  (1e-10), and against central differences of Omega along random directions.
 """
 import numpy as np
 import pytest
@@ -78,3 +81,41 @@ def test_sdw_vjp_against_oracle(Lx, Ly, m_amp):
     for got, r in zip(grads, ref):
         got = host(got)
         assert np.max(np.abs(got - r)) < 1e-11 * max(np.max(np.abs(r)), 1e-300)
+
+
+def test_sdw_autograd_against_oracle():
+    from paper_2212_05685_amd.autograd import GrandPotentialSDW
+
+    cfg = wl.Config("s", 8, 8, 2, 0.15, 64, (wl.ProbeSpec("colored_z4", 1, 3, 4, 4, 1, 0, 1.0),),
+                    "fp64", ckpt_k=8, vortex=True, complex_noise=0.02)
+    th = wl.make_theta_sdw(cfg, 0.04)
+    st = sdw.build_stencil_sdw(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, *th)
+    a, b = H.bounds(cfg, st)
+    C = chebyshev.kpm_coefficients(cfg.M, cfg.T, a, b)
+    rho_ref = H.plain(cfg, st, a, b, C)["rho"]
+    ref = sdw.vjp_sdw(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, *th, rho_ref)
+
+    pb = problem(cfg, precision="fp64")
+    leaves = [dev(x).requires_grad_(True) for x in th]
+    om = GrandPotentialSDW.apply(*leaves, pb)
+    om.backward()
+    for lf, r in zip(leaves, ref):
+        assert np.max(np.abs(host(lf.grad) - r)) < 1e-10 * np.max(np.abs(r))
+
+    # central differences of Omega with (a, b) and C frozen at the base point
+    base = [x.detach() for x in leaves]
+    h0 = pb.build_H_sdw(*base)
+    ab = pb.bounds(h0)
+    Cd = pb.coefficients(ab)
+
+    def omega(xs):
+        return float(host(pb.grand_potential(pb.build_H_sdw(*xs), ab, Cd))[0])
+
+    rng = np.random.default_rng(1)
+    e = 1e-6
+    for _ in range(3):
+        dirs = [dev(rng.normal(size=x.shape) + (1j * rng.normal(size=x.shape) if np.iscomplexobj(x) else 0))
+                for x in th]
+        fd = (omega([x + e * d for x, d in zip(base, dirs)]) - omega([x - e * d for x, d in zip(base, dirs)])) / (2 * e)
+        an = sum(float((host(lf.grad).conj() * host(d)).real.sum()) for lf, d in zip(leaves, dirs))
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(an))
