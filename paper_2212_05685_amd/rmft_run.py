@@ -114,6 +114,9 @@ def main(argv=None):
     ap.add_argument("--doping", type=float, default=0.16)
     ap.add_argument("--moments", type=int, default=1024)
     ap.add_argument("--core", type=float, default=3.0, help="tanh radius of the vortex seed")
+    ap.add_argument("--vortex-dx", type=float, default=0.0,
+                    help="shift of the seeded vortex centres along x (24.5 puts the 48-wide "
+                         "lattice's pair on the x seam, where the gauge's torus holonomy holds them)")
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--mix", type=float, default=0.1)
     ap.add_argument("--tol-n", type=float, default=1e-5)
@@ -128,7 +131,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     cfg = wl.scaled(wl.RMFT(args.precision), Lx=args.lx, Ly=args.ly, n_v=args.nv, doping=args.doping,
-                    M=args.moments, core=args.core)
+                    M=args.moments, core=args.core, vortex_dx=args.vortex_dx)
     kinds = {"unit": kpm.KPM_PROBE_UNIT, "dense_z4": kpm.KPM_PROBE_DENSE_Z4,
              "colored_z4": kpm.KPM_PROBE_COLORED_Z4}
     specs = [kpm.ProbeSpec(kinds[p.kind], p.count, p.seed, p.px, p.py, p.split_nambu, p.first, p.weight)

@@ -84,6 +84,7 @@ class Config:
     J: float = J_EX
     chi0: float = 0.2            # seed chi on nearest-neighbour bonds
     core: float = 3.0            # tanh radius of the vortex seed (lattice constants)
+    vortex_dx: float = 0.0       # shift of the seeded vortex centres along x (lattice constants)
 
     @property
     def N(self) -> int:
@@ -163,7 +164,7 @@ def make_theta(cfg: Config):
             amp = np.ones(N)
             phase = np.zeros(N)
             for (X, Y) in vortex_centres(Lx, Ly, cfg.n_v):
-                ux, uy = _min_image(xm - X, Lx), _min_image(ym - Y, Ly)
+                ux, uy = _min_image(xm - X - cfg.vortex_dx, Lx), _min_image(ym - Y, Ly)
                 amp *= np.tanh(np.hypot(ux, uy) / cfg.core)
                 phase += np.arctan2(uy, ux)
             dlt[d] *= amp * np.exp(1j * phase)
