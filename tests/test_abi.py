@@ -194,3 +194,21 @@ def test_supercell_host_validation():
     assert call(ws_bytes=full - 1) == kpm.KPM_EWORKSPACE
     assert call(kb=2) == kpm.KPM_EWORKSPACE                 # workspace sized for one matrix
     assert call(ws=ctypes.c_void_p((1 << 20) + 8)) == kpm.KPM_EWORKSPACE
+
+
+def test_vortex_seed_shift():
+    """workloads.Config.vortex_dx moves the seeded pairing minima along x only."""
+    import numpy as np
+    import workloads as wl
+
+    Lx, Ly = 24, 16
+    base = wl.Config("v", Lx, Ly, 2, 0.16, 8, (wl.ProbeSpec("unit", 1),), vortex=True)
+    x, y = np.arange(Lx * Ly) % Lx, np.arange(Lx * Ly) // Lx
+    for dx in (0.0, 6.0):
+        _, _, dlt = wl.make_theta(wl.scaled(base, vortex_dx=dx))
+        amp = np.abs(dlt[0])                      # +x bonds, midpoints (x + 1/2, y)
+        for k, (X, Y) in enumerate(wl.vortex_centres(Lx, Ly, 2)):
+            half = (y < Ly // 2) if k == 0 else (y >= Ly // 2)
+            i = np.flatnonzero(half)[np.argmin(amp[half])]
+            assert abs((x[i] + 0.5 - (X + dx) + Lx / 2) % Lx - Lx / 2) <= 1.0
+            assert abs(y[i] - Y) <= 1.0
