@@ -286,6 +286,19 @@ def sdw_kpm_rho_fn(Lx, Ly, n_v, t, tp, J, T, M, probes, weights, K=None):
     return fn
 
 
+def sdw_direct_rho_fn(Lx, Ly, n_v, t, tp, J, T, M, probes, weights, K=None):
+    """Direct probing estimate (series of f' per probe) on the spin-polarised
+    builder's h."""
+    def fn(theta, mu):
+        st = sdw.build_stencil_sdw(Lx, Ly, n_v, t, tp, J, mu, *theta)
+        Hs = builder.sparse_from_stencil(st, Lx, Ly)
+        a, b = chebyshev.rescale(*chebyshev.gershgorin_sparse(Hs))
+        C = chebyshev.kpm_coefficients(M, T, a, b, K)
+        out = kpm_direct.direct_rho(Hs, a, b, probes, weights, C, Lx, Ly)
+        return float(out["omega"]), out["rho"]
+    return fn
+
+
 def sdw_exact_rho_fn(Lx, Ly, n_v, t, tp, J, T):
     """Exact Fermi-function rho of the spin-polarised builder's h."""
     def fn(theta, mu):

@@ -18,9 +18,9 @@ kpm_rmft_iterate) against the oracle's loop (oracle/rmft.py), through the C ABI.
   the density constraint and stay physical;
 * the spin-polarised loop (kpm_rmft_update_sdw, kpm_rmft_iterate_sdw): the
   per-spin map kernel against ``oracle.rmft.update`` on a six-array theta to
-  1e-14, and whole FP64 iterations (linear and Anderson, both searches) on a
-  staggered-moment seed against the oracle loop on the spin-polarised
-  builder, to the same bars as the singlet loop.
+  1e-14, and whole FP64 iterations (linear and Anderson, both searches, both
+  estimators of rho) on a staggered-moment seed against the oracle loop on
+  the spin-polarised builder, to the same bars as the singlet loop.
 """
 import numpy as np
 import pytest
@@ -199,8 +199,9 @@ def _sdw_cfg():
                      "fp64", ckpt_k=16, vortex=False, complex_noise=0.01, seed=4242)
 
 
-@pytest.mark.parametrize("search,anderson", [("illinois", 0), ("bisection", 0), ("illinois", 2)])
-def test_iterate_sdw_parity_fp64(search, anderson):
+@pytest.mark.parametrize("search,anderson,estimator", [("illinois", 0, "adjoint"), ("bisection", 0, "adjoint"),
+                                                       ("illinois", 2, "adjoint"), ("illinois", 0, "direct")])
+def test_iterate_sdw_parity_fp64(search, anderson, estimator):
     from paper_2212_05685_amd import kpm
 
     cfg = _sdw_cfg()
@@ -209,13 +210,15 @@ def test_iterate_sdw_parity_fp64(search, anderson):
     n_it = 4 if anderson else 3
     th0 = wl.make_theta_sdw(cfg, m_amp=0.01)
     R, w = H.probe_matrix(cfg)
-    fn = ormft.sdw_kpm_rho_fn(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.T, cfg.M, R, w)
+    make = ormft.sdw_kpm_rho_fn if estimator == "adjoint" else ormft.sdw_direct_rho_fn
+    fn = make(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.T, cfg.M, R, w)
     th_ref, mu_ref, hist_ref = ormft.iterate(fn, th0, cfg.mu, p, n_it)
 
     pb = problem(cfg)
     d = [dev(a) for a in th0]
     prm = kpm.rmft_params(p.doping, p.mix, p.tol_n, p.tol_mu, p.mu_step, p.tol_residual, p.max_evals,
                           search={"bisection": kpm.KPM_RMFT_BISECTION, "illinois": kpm.KPM_RMFT_ILLINOIS}[search],
+                          estimator={"adjoint": kpm.KPM_RMFT_ADJOINT, "direct": kpm.KPM_RMFT_DIRECT}[estimator],
                           anderson=anderson)
     mu, hist, st = pb.rmft_iterate_sdw(*d, cfg.mu, prm, n_it)
     assert st == 0 and len(hist) == len(hist_ref) == n_it
