@@ -504,6 +504,32 @@ def supercell_form(k_count: int = 8):
     return res
 
 
+def cpu_dense_ed():
+    """The oracle's dense exact diagonalisation (O1: eigh of the 2N x 2N BdG
+    matrix, then the Fermi sums for Omega and rho) on the 32x32 vortex lattice
+    (D = 2048), timed on the host with threaded LAPACK.  Reported beside the
+    KPM baseline; the build of h is not timed."""
+    import os
+    from threadpoolctl import threadpool_info
+
+    from oracle import builder, dense
+    import workloads as wl
+
+    cfg = wl.C2("fp64")
+    n, chi, dlt = wl.make_theta(cfg)
+    st = builder.build_stencil(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, n, chi, dlt)
+    H = builder.dense_from_stencil(st, cfg.Lx, cfg.Ly)
+    t0 = time.perf_counter()
+    dense.exact(H, cfg.T)
+    dt = time.perf_counter() - t0
+    threads = max((p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"),
+                  default=1)
+    log(f"cpu dense ED (D = {2 * cfg.N}): {dt:.2f} s on {threads} threads")
+    return {"seconds": dt, "D": 2 * cfg.N, "cores": threads, "host_cpus": os.cpu_count(),
+            "kind": "oracle (dense ED, O1)",
+            "sample": "32x32 torus, 2 vortices: eigh of the 2048 x 2048 BdG matrix + Fermi sums for Omega and rho"}
+
+
 def cpu_baseline(cfg, quiet=False):
     """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
     probe of the same workload, single thread."""
@@ -692,6 +718,7 @@ def main():
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg)
+        result["cpu_dense_ed"] = cpu_dense_ed()
     print(json.dumps(result), flush=True)
 
 
