@@ -593,8 +593,8 @@ def main():
         traffic_summary(args.traffic_summary, args.copy_calibration or (1 << 30))
         return
     if args.gpus != 1:
-        print("bench.py measures one MI355X: this build runs on a single GPU only "
-              "(multi-GPU probe sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        print("bench.py measures one MI355X: multi-GPU runs are not supported (the path would shard "
+              "over probes, with one all-reduce of the moments and of rho per step).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
