@@ -482,6 +482,16 @@ int kpm_rmft_iterate_sdw(const kpm_lattice* lat, const kpm_model* model, const k
 int kpm_bloch_H(const kpm_lattice* lat, const double* h, double phi_x, double phi_y, double* Hk,
                 int64_t ld, void* stream);
 
+/* The site weights of eq. Gij at i = j for kpm_supercell_ldos: w_s =
+ * (g^t_{i s})^2 with the per-spin Gutzwiller factor of App. A,
+ *   (g^t_s)^2 = 2 delta (1 - delta)/(1 - delta^2 + 4 m^2)
+ *               * (1 + delta + 2 s m)/(1 + delta - 2 s m),
+ * delta = 1 - n_up - n_dn, m = (n_up - n_dn)/2 (2 delta/(1 + delta) at m = 0;
+ * reading g^t_ij = g^t_i g^t_j at i = j).  n_up, n_dn, w_up, w_dn: device [N]
+ * (a singlet state passes n_up = n_dn = n/2). */
+int kpm_gutzwiller_weights(const kpm_lattice* lat, const double* n_up, const double* n_dn,
+                           double* w_up, double* w_dn, void* stream);
+
 /* Workspace bytes of kpm_supercell_ldos with k_batch (1..KPM_SUPERCELL_MAX_BATCH)
  * k points per eigensolver call: k_batch dense matrices of (2N)^2 complex
  * values, their eigenvalues, the site list and per-k solver flags.  0 on

@@ -138,6 +138,21 @@ __global__ __launch_bounds__(kLS * kQL) void k_sc_ldos(int n, long long ld, cons
   }
 }
 
+// w_s = (g^t_{i s})^2, the Gutzwiller factor of eq. Gij at i = j, with the
+// per-spin g^t of App. A: (g^t_s)^2 = 2 delta (1 - delta)/(1 - delta^2 + 4 m^2)
+// * (1 + delta + 2 s m)/(1 + delta - 2 s m), delta = 1 - n_up - n_dn,
+// m = (n_up - n_dn)/2 (2 delta/(1 + delta) at m = 0).
+__global__ __launch_bounds__(kZB) void k_gt_weights(int N, const double* __restrict__ nu,
+                                                    const double* __restrict__ nd,
+                                                    double* __restrict__ wu, double* __restrict__ wd) {
+  const int i = blockIdx.x * kZB + threadIdx.x;
+  if (i >= N) return;
+  const double dl = 1.0 - nu[i] - nd[i], m = 0.5 * (nu[i] - nd[i]);
+  const double base = 2.0 * dl * (1.0 - dl) / (1.0 - dl * dl + 4.0 * m * m);
+  wu[i] = base * (1.0 + dl + 2.0 * m) / (1.0 + dl - 2.0 * m);
+  wd[i] = base * (1.0 + dl - 2.0 * m) / (1.0 + dl + 2.0 * m);
+}
+
 __global__ __launch_bounds__(kZB) void k_fill0(long long len, double* __restrict__ p) {
   for (long long e = (long long)blockIdx.x * kZB + threadIdx.x; e < len; e += (long long)gridDim.x * kZB)
     p[e] = 0.0;
@@ -189,6 +204,16 @@ int kpm_bloch_H(const kpm_lattice* lat, const double* h, double phi_x, double ph
   if (ld < n) return KPM_EINVAL;
   return launch_bloch(lat, h, phi_x, phi_y, reinterpret_cast<double2*>(Hk), ld,
                       static_cast<hipStream_t>(stream));
+}
+
+int kpm_gutzwiller_weights(const kpm_lattice* lat, const double* n_up, const double* n_dn,
+                           double* w_up, double* w_dn, void* stream) {
+  if (!lat || lat->Lx < 1 || lat->Ly < 1 || !n_up || !n_dn || !w_up || !w_dn) return KPM_EINVAL;
+  const long long N = (long long)lat->Lx * lat->Ly;
+  if (N >= (1LL << 31)) return KPM_EINVAL;
+  hipLaunchKernelGGL(k_gt_weights, dim3((unsigned)((N + kZB - 1) / kZB)), dim3(kZB), 0,
+                     static_cast<hipStream_t>(stream), (int)N, n_up, n_dn, w_up, w_dn);
+  return hipGetLastError() == hipSuccess ? KPM_OK : KPM_EDEVICE;
 }
 
 size_t kpm_supercell_workspace_size(const kpm_lattice* lat, int32_t k_batch) {

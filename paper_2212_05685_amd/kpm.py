@@ -38,7 +38,7 @@ EXPORTS = (
     "kpm_batch_destroy", "kpm_set_probe_block", "kpm_profile_begin", "kpm_profile_end",
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
     "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
-    "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_build_H_sdw_vjp", "kpm_bloch_H", "kpm_supercell_workspace_size",
+    "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_build_H_sdw_vjp", "kpm_bloch_H", "kpm_gutzwiller_weights", "kpm_supercell_workspace_size",
     "kpm_supercell_ldos",
 )
 
@@ -130,6 +130,7 @@ def _load():
                                            POINTER(c_int32), P, c_size_t, P]),
         "kpm_build_H_sdw_vjp": (c_int32, [POINTER(Lattice), POINTER(Model)] + [P] * 14),
         "kpm_bloch_H": (c_int32, [POINTER(Lattice), P, c_double, c_double, P, ctypes.c_int64, P]),
+        "kpm_gutzwiller_weights": (c_int32, [POINTER(Lattice), P, P, P, P, P]),
         "kpm_supercell_workspace_size": (c_size_t, [POINTER(Lattice), c_int32]),
         "kpm_supercell_ldos": (c_int32, [POINTER(Lattice), P, c_int32, c_int32, c_int32, c_int32, c_int32,
                                          POINTER(c_int32), c_int32, P, c_int32, c_double, c_double, P, P,
@@ -505,6 +506,14 @@ def kpm_bloch_H(lat, h, phi_x, phi_y, Hk, ld=None, stream=None):
     _check(_lib.kpm_bloch_H(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"), float(phi_x),
                             float(phi_y), _ptr(Hk, torch.complex128, 2 * N * ld, "Hk"), ld,
                             _stream(stream)), "kpm_bloch_H")
+
+
+def kpm_gutzwiller_weights(lat, n_up, n_dn, w_up, w_dn, stream=None):
+    N = lat.Lx * lat.Ly
+    _check(_lib.kpm_gutzwiller_weights(ctypes.byref(lat), _ptr(n_up, torch.float64, N, "n_up"),
+                                       _ptr(n_dn, torch.float64, N, "n_dn"), _ptr(w_up, torch.float64, N, "w_up"),
+                                       _ptr(w_dn, torch.float64, N, "w_dn"), _stream(stream)),
+           "kpm_gutzwiller_weights")
 
 
 def kpm_supercell_workspace_size(lat, k_batch=1) -> int:

@@ -12,7 +12,11 @@ kpm_supercell_ldos) against the oracle (oracle/supercell.py), through the C ABI.
   group) against the oracle;
 * the k grid split over two calls (accumulate) equals one call;
 * 48 x 48 (the paper's smallest cell, 8 x 8 grid) at one k point: eigenvalues
-  and the LDOS along a line cut against the oracle.
+  and the LDOS along a line cut against the oracle;
+* the Gutzwiller weights of eq. Gij (kpm_gutzwiller_weights) against the
+  oracle's App. A factors squared (oracle.sdw.factors, pinned to the printed
+  g^t), spin-polarised and at m = 0 against 2 delta/(1 + delta), and fed to
+  the LDOS against the oracle with the same weights.
 """
 import numpy as np
 import pytest
@@ -116,3 +120,30 @@ def test_supercell_fullsize_one_k():
     q = 1 * 8 + 1
     sites = [24 * 48 + x for x in range(48)]
     _compare(cfg, 8, 8, sites, np.linspace(-1.0, 1.0, 33), ks=[q])
+
+
+def test_gutzwiller_weights_and_weighted_ldos():
+    from oracle import sdw
+    from paper_2212_05685_amd import kpm
+
+    cfg = _cfg(12, 8, seed=21)
+    lat = kpm.lattice(cfg.Lx, cfg.Ly, cfg.n_v)
+    th = wl.make_theta_sdw(cfg, m_amp=0.05)
+    nu, nd = dev(th[0]), dev(th[1])
+    wu, wd = torch.empty_like(nu), torch.empty_like(nd)
+    kpm.kpm_gutzwiller_weights(lat, nu, nd, wu, wd)
+    f = sdw.factors(torch.tensor(th[0]), torch.tensor(th[1]))
+    assert np.max(np.abs(host(wu) - f[2].numpy() ** 2)) < 1e-14
+    assert np.max(np.abs(host(wd) - f[3].numpy() ** 2)) < 1e-14
+    n = np.full(cfg.N, 0.85)
+    kpm.kpm_gutzwiller_weights(lat, dev(n / 2), dev(n / 2), wu, wd)
+    assert np.max(np.abs(host(wu) - 2 * 0.15 / 1.15)) < 1e-15 and np.array_equal(host(wu), host(wd))
+    # the weights through the LDOS
+    kpm.kpm_gutzwiller_weights(lat, nu, nd, wu, wd)
+    st = sdw.build_stencil_sdw(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, *th)
+    om = np.linspace(-2.0, 2.0, 21)
+    sites = [0, 31, 95]
+    ref, _ = supercell.supercell_ldos(st, cfg.Lx, cfg.Ly, 2, 2, sites, om, 0.25, 3e-2,
+                                      f[2].numpy() ** 2, f[3].numpy() ** 2)
+    got, _ = _problem(cfg).supercell_ldos(dev(st), 2, 2, sites, dev(om), 0.25, 3e-2, wu, wd)
+    assert np.max(np.abs(host(got) - ref)) < 1e-10 * np.max(np.abs(ref))
