@@ -153,6 +153,7 @@ def main(argv=None):
                           anderson=args.anderson)
     t0 = time.perf_counter()
     done = 0
+    st = kpm.KPM_OK
     while done < args.iters:
         k = min(args.chunk, args.iters - done)
         mu, h, st = prob.rmft_iterate(n, chi, dlt, mu, prm, k)

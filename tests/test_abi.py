@@ -212,3 +212,24 @@ def test_vortex_seed_shift():
             i = np.flatnonzero(half)[np.argmin(amp[half])]
             assert abs((x[i] + 0.5 - (X + dx) + Lx / 2) % Lx - Lx / 2) <= 1.0
             assert abs(y[i] - Y) <= 1.0
+
+
+def test_core_fit_recovers_synthetic_cores():
+    """rmft_run's host-side analysis: on a synthetic amplitude D0 tanh(r/xi)
+    around two centres (minimum-image distances on the torus), the fit returns
+    the centres, D0 and xi it was built from."""
+    import numpy as np
+    from paper_2212_05685_amd.rmft_run import core_fit, vortex_positions
+
+    Lx, Ly, D0, xi = 48, 96, 0.03, 2.7
+    cs = [(46.6, 28.3), (47.2, 74.4)]
+    x, y = np.arange(Lx * Ly) % Lx, np.arange(Lx * Ly) // Lx
+    amp = np.full(Lx * Ly, D0)
+    for cx, cy in cs:
+        r = np.hypot((x - cx + Lx / 2) % Lx - Lx / 2, (y - cy + Ly / 2) % Ly - Ly / 2)
+        amp = amp * np.tanh(r / xi)
+    pos = vortex_positions(amp, Lx, Ly, 2)
+    fits = sorted(core_fit(amp, Lx, Ly, pos), key=lambda f: f["centre"][1])
+    for f, (cx, cy) in zip(fits, cs):
+        assert abs(f["centre"][0] - cx) < 0.05 and abs(f["centre"][1] - cy) < 0.05
+        assert abs(f["xi"] - xi) < 0.05 and abs(f["D0"] - D0) < 1e-3

@@ -234,3 +234,33 @@ def test_iterate_sdw_parity_fp64(search, anderson, estimator):
         assert np.abs(host(a) - b).max() < 1e-10
     m = (th_ref[0] - th_ref[1]) / 2
     assert np.abs(m).max() > 0.02                 # the staggered moment grew: not the singlet path
+
+
+def test_rmft_driver_save_and_resume(tmp_path):
+    """The chunked driver end to end on a small vortex lattice: a run that
+    writes a restart file, then a resumed run that continues from it (the
+    iteration count and mu carry over)."""
+    import json
+    import subprocess
+    import sys
+
+    state = tmp_path / "s.npz"
+    base = [sys.executable, "-m", "paper_2212_05685_amd.rmft_run", "--lx", "16", "--ly", "16",
+            "--moments", "128", "--chunk", "2"]
+    env = {**__import__("os").environ, "PYTHONPATH": str(__import__("pathlib").Path(__file__).parents[1])}
+    r1 = subprocess.run(base + ["--iters", "3", "--save", str(state)], capture_output=True, text=True,
+                        env=env, timeout=240)
+    assert r1.returncode == 0, r1.stderr[-2000:]
+    s1 = json.loads(r1.stdout.strip().splitlines()[-1])
+    assert s1["iterations"] == 3 and state.exists()
+    r0 = subprocess.run(base + ["--iters", "0", "--resume", str(state)], capture_output=True, text=True,
+                        env=env, timeout=240)
+    assert r0.returncode == 0, r0.stderr[-2000:]
+    s0 = json.loads(r0.stdout.strip().splitlines()[-1])
+    assert s0["iterations"] == 3 and s0["mu"] == s1["mu"]          # the state carries over exactly
+    r2 = subprocess.run(base + ["--iters", "2", "--resume", str(state), "--save", str(state)],
+                        capture_output=True, text=True, env=env, timeout=240)
+    assert r2.returncode == 0, r2.stderr[-2000:]
+    s2 = json.loads(r2.stdout.strip().splitlines()[-1])
+    assert s2["iterations"] == 5 and s2["status"] == 0
+    assert len(s2["cores"]) == 2
