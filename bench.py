@@ -301,6 +301,25 @@ def rmft_form(iters: int, warmup: int):
                      "ms_per_density_matrix_evaluation": dt / evals * 1e3,
                      "residual_first": hist[0]["residual"], "residual_last": hist[-1]["residual"],
                      "mu_last": mu}
+    # the spin-polarised loop (SDW builder, per-spin map, 34 N Anderson vector) on the same lattice,
+    # from a spin-symmetric seed with small spin-dependent noise (the path's cost, not an SDW state)
+    th6 = [torch.from_numpy(x).cuda() for x in wl.make_theta_sdw(cfg, m_amp=0.0, spin_noise=0.005)]
+    try:
+        mu6, _, st = prob.rmft_iterate_sdw(*th6, cfg.mu, params(kpm.KPM_RMFT_ILLINOIS), warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu6, hist6, st6 = prob.rmft_iterate_sdw(*th6, mu6, params(kpm.KPM_RMFT_ILLINOIS), iters)
+        torch.cuda.synchronize()
+        dt6 = time.perf_counter() - t0
+        ev6 = sum(h["evals"] for h in hist6)
+        out["illinois_spin_polarised"] = {
+            "s_per_iteration": dt6 / max(len(hist6), 1), "evaluations_per_iteration": ev6 / max(len(hist6), 1),
+            "ms_per_density_matrix_evaluation": dt6 / max(ev6, 1) * 1e3, "status": st6,
+            "iterations": len(hist6), "residual_last": hist6[-1]["residual"] if hist6 else None}
+        log(f"rmft spin-polarised: {dt6 / max(len(hist6), 1) * 1e3:.1f} ms/iteration, "
+            f"{ev6 / max(len(hist6), 1):.1f} evaluations each")
+    except kpm.KpmError as e:
+        out["illinois_spin_polarised"] = {"error": str(e)}
     R, N = prob.R, cfg.N
     adj_bytes = 6 * 16 * R * N + 36 * 8 * N
     _, _, adj_ms, n_adj = prof
