@@ -155,6 +155,13 @@ def energy_grad(prob, th):
 
 
 def timed(prob, th, steps, warmup, profile):
+    """`warmup` untimed steps, then exactly `steps` steps between two device
+    synchronisations; each step is bracketed by HIP events on the stream the
+    library launches on (torch's current stream).  Returns the median event
+    time per step (s), the per-step times, the wall-clock mean, the last
+    outputs and the sampled kernel durations."""
+    import statistics
+
     import torch
     from paper_2212_05685_amd import kpm
 
@@ -162,19 +169,25 @@ def timed(prob, th, steps, warmup, profile):
         energy_grad(prob, th)
         torch.cuda.synchronize()
         log(f"{'fp32' if prob.precision else 'fp64'} warmup {w + 1}/{warmup} done")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     if profile:
         kpm.kpm_profile_begin(16)
     t0 = time.perf_counter()
     for s in range(steps):
+        ev[s][0].record()
         out, grads = energy_grad(prob, th)
+        ev[s][1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = kpm.kpm_profile_end() if profile else None
     if prob.status() != 0:
         raise RuntimeError(f"device status {prob.status()}")
-    log(f"{'fp32' if prob.precision else 'fp64'} timed {steps} steps: {(t1 - t0) / steps * 1e3:.1f} ms/step")
-    return (t1 - t0) / steps, out, grads, prof
+    per = [a.elapsed_time(b) * 1e-3 for a, b in ev]
+    med = statistics.median(per)
+    log(f"{'fp32' if prob.precision else 'fp64'} timed {steps} steps: median {med * 1e3:.1f} ms/step "
+        f"(events), wall mean {(t1 - t0) / steps * 1e3:.1f} ms")
+    return med, per, (t1 - t0) / steps, out, grads, prof
 
 
 def batched_form(steps: int):
@@ -325,8 +338,13 @@ def rmft_form(iters: int, warmup: int):
     _, _, adj_ms, n_adj = prof
     adj_s = adj_ms / max(n_adj, 1) * 1e-3
     achieved = adj_bytes / adj_s / 1e9
-    cpu = cpu_baseline(cfg, quiet=True)
-    t_eval_cpu = cpu["seconds"] * R
+    pool = OraclePool(host_workers())
+    try:
+        tasks = _oracle_tasks(cfg, pool.workers)
+        wall = pool.wall(tasks)
+    finally:
+        pool.close()
+    t_eval_cpu = wall * R / len(tasks)
     ill = out["illinois"]
     return {
         "workload": "48x96 torus, 2 vortices (plain-vortex seed, chi seeded 0), doping 0.16, M=1024, "
@@ -350,10 +368,10 @@ def rmft_form(iters: int, warmup: int):
         },
         "cpu_baseline": {
             "value": t_eval_cpu * ill["evaluations_per_iteration"], "unit": "s/iteration",
-            "cores": 1, "kind": "oracle",
-            "sample": f"oracle forward + adjoint on 1 of {R} probes at 48x96, M={cfg.M}: "
-                      f"{cpu['seconds']:.2f} s, times {R} probes and the measured "
-                      f"{ill['evaluations_per_iteration']:.1f} evaluations per iteration",
+            "cores": len(tasks), "kind": "oracle",
+            "sample": f"oracle forward + adjoint on {len(tasks)} of {R} probes at 48x96, M={cfg.M}, one "
+                      f"single-threaded process per core: {wall:.2f} s wall, times {R}/{len(tasks)} and the "
+                      f"measured {ill['evaluations_per_iteration']:.1f} evaluations per iteration",
         },
     }
 
@@ -549,43 +567,121 @@ def cpu_dense_ed():
             "sample": "32x32 torus, 2 vortices: eigh of the 2048 x 2048 BdG matrix + Fermi sums for Omega and rho"}
 
 
-def cpu_baseline(cfg, quiet=False):
-    """The oracle (plain FP64 forward + adjoint, all vectors stored) on one
-    probe of the same workload, single thread."""
-    import numpy as np
+def _oracle_probe(task):
+    """Pool worker: the oracle's plain FP64 forward recursion + beta adjoint
+    (O2, every vector stored) on one probe, single-threaded; returns seconds."""
     from threadpoolctl import threadpool_limits
 
-    from oracle import builder, chebyshev, kpm_plain, probes
-
-    n, chi, dlt = __import__("workloads").make_theta(cfg)
+    from oracle import kpm_plain
+    Hs, a, b, r, w, C, Lx, Ly = task
     with threadpool_limits(1):
-        st = builder.build_stencil(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, n, chi, dlt)
-        Hs = builder.sparse_from_stencil(st, cfg.Lx, cfg.Ly)
-        a, b = chebyshev.rescale(*chebyshev.gershgorin_sparse(Hs))
-        C = chebyshev.kpm_coefficients(cfg.M, cfg.T, a, b)
-        p = cfg.probes[0]
-        g = probes.ProbeGroup(probes.COLORED_Z4, p.count, p.seed, p.px, p.py, p.split_nambu, p.first, p.weight)
-        r = probes.probe_vector(g, 0, cfg.Lx, cfg.Ly)[None, :]
-        w = np.array([p.weight])
-        log("cpu baseline: oracle forward + adjoint on 1 probe ...")
         t0 = time.perf_counter()
-        kpm_plain.plain_kpm(Hs, a, b, r, w, C, cfg.Lx, cfg.Ly, want_grad=True)
-        t1 = time.perf_counter()
-    vsteps = 3 * cfg.M - 5
-    log(f"cpu baseline: {t1 - t0:.1f} s")
-    if quiet:
-        return {"seconds": t1 - t0}
-    return {"value": vsteps / (t1 - t0), "unit": "vector-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 of {cfg.R} probes of the 100x100 workload (M={cfg.M}): plain FP64 forward "
-                      f"recursion + beta adjoint with every vector stored (oracle O2), single thread, "
-                      f"{t1 - t0:.1f} s for {vsteps} vector-steps"}
+        kpm_plain.plain_kpm(Hs, a, b, r, w, C, Lx, Ly, want_grad=True)
+        return time.perf_counter() - t0
+
+
+def _oracle_tasks(cfg, nprobe):
+    """The oracle's own inputs (stencil, Gershgorin bounds, coefficients: not
+    timed) and its first `nprobe` probes of the config as pool tasks."""
+    import workloads as wl
+    from oracle import builder, chebyshev, probes
+
+    kinds = {"unit": probes.UNIT, "dense_z4": probes.DENSE_Z4, "colored_z4": probes.COLORED_Z4}
+    n, chi, dlt = wl.make_theta(cfg)
+    st = builder.build_stencil(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, n, chi, dlt)
+    Hs = builder.sparse_from_stencil(st, cfg.Lx, cfg.Ly)
+    a, b = chebyshev.rescale(*chebyshev.gershgorin_sparse(Hs))
+    C = chebyshev.kpm_coefficients(cfg.M, cfg.T, a, b)
+    groups = [probes.ProbeGroup(kinds[p.kind], p.count, p.seed, p.px, p.py, p.split_nambu, p.first, p.weight)
+              for p in cfg.probes]
+    R, w = probes.probe_set(groups, cfg.Lx, cfg.Ly)
+    return [(Hs, a, b, R[q:q + 1], w[q:q + 1], C, cfg.Lx, cfg.Ly) for q in range(min(nprobe, R.shape[0]))]
+
+
+def host_workers():
+    """Worker processes for the oracle baselines: the CPUs this process may run
+    on, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+class OraclePool:
+    """Single-threaded oracle processes, one per worker core (spawned, so that
+    no GPU context is inherited)."""
+
+    def __init__(self, workers):
+        from multiprocessing import get_context
+        self.workers = workers
+        self.pool = get_context("spawn").Pool(workers)
+        self.pool.map(_noop, range(workers))            # start-up outside the timed samples
+
+    def wall(self, tasks, timeout=900):
+        """Wall-clock seconds to run `tasks` (one probe each) on the pool."""
+        t0 = time.perf_counter()
+        self.pool.map_async(_oracle_probe, tasks, chunksize=1).get(timeout)
+        return time.perf_counter() - t0
+
+    def close(self):
+        self.pool.terminate()
+
+
+def _noop(x):
+    """Worker start-up: the oracle's imports happen here, outside the samples."""
+    import threadpoolctl  # noqa: F401
+    from oracle import kpm_plain  # noqa: F401
+    return x
+
+
+def cpu_baseline(pool):
+    """The oracle (O2: plain FP64 forward + beta adjoint, every vector stored)
+    on all worker cores, parallel over probes (one single-threaded process per
+    core, one probe per process), for the five workloads.  Each workload runs a
+    bounded sample of one probe per core; its energy + gradient time is the
+    sample's wall time scaled by the workload's probe work (probes x sites, M
+    fixed), i.e. the model is perfect probe parallelism at `cores` processes.
+    The headline entry is the 100 x 100 workload."""
+    import workloads as wl
+
+    P = pool.workers
+    out = {}
+    for name, cfgs in (("C1_8x8", [wl.C1()]), ("C2_32x32", [wl.C2("fp64")]), ("C3_64x64", [wl.C3()]),
+                       ("C4_48_lattices", wl.C4_instances(48)), ("C5_100x100", [wl.C5("fp64")])):
+        if len(cfgs) == 1:
+            tasks = _oracle_tasks(cfgs[0], P)
+            sample_work = len(tasks) * cfgs[0].N
+        else:                              # one probe of each of the first P lattices
+            tasks = [_oracle_tasks(c, 1)[0] for c in cfgs[:P]]
+            sample_work = sum(c.N for c in cfgs[:P])
+        total_work = sum(c.R * c.N for c in cfgs)
+        M = cfgs[0].M
+        wall = pool.wall(tasks)
+        s_eg = wall * total_work / sample_work
+        vsteps = sum(c.R for c in cfgs) * (3 * M - 5)
+        out[name] = {"s_per_energy_grad": s_eg, "vector_steps_per_s": vsteps / s_eg,
+                     "sample_probes": len(tasks), "sample_wall_s": wall, "M": M,
+                     "probes_total": sum(c.R for c in cfgs)}
+        log(f"cpu baseline {name}: {len(tasks)} probes on {P} processes in {wall:.1f} s -> "
+            f"{s_eg:.1f} s per energy + gradient")
+    c5 = out["C5_100x100"]
+    return {"value": c5["vector_steps_per_s"], "unit": "vector-steps/s", "cores": P, "kind": "oracle",
+            "host_cpus": os.cpu_count(),
+            "s_per_energy_grad": c5["s_per_energy_grad"],
+            "sample": f"oracle O2 (plain FP64 forward recursion + beta adjoint, every vector stored) on "
+                      f"{c5['sample_probes']} of the 256 probes of the 100x100 workload (M=4096), one "
+                      f"single-threaded process per core on {P} cores, {c5['sample_wall_s']:.1f} s wall; "
+                      f"energy + gradient time = wall x 256 / {c5['sample_probes']} (perfect probe "
+                      f"parallelism at {P} processes)",
+            "per_config": out}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--no-batched-form", action="store_true")
@@ -646,7 +742,8 @@ def main():
     prob, th = make_problem(cfg, "fp32")
     R, M, N = prob.R, cfg.M, cfg.N
     log(f"workload 100x100 M={M} R={R}; building and warming up")
-    dt, out32, grads32, prof = timed(prob, th, args.steps, args.warmup, profile=not args.no_kernel_timing)
+    dt, per_step, wall_mean, out32, grads32, prof = timed(prob, th, args.steps, args.warmup,
+                                                          profile=not args.no_kernel_timing)
     vsteps = R * (M - 1) + 2 * R * (M - 2)
     fwd_ms, n_fwd, adj_ms, n_adj = prof if prof else (float("nan"), 0, float("nan"), 0)
     rec = 16                                    # FP32 complex record of one site (2 components)
@@ -666,6 +763,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt * 1e3,
+        "ms_per_step_timing": f"median of {args.steps} per-step HIP event pairs after {args.warmup} warm-up steps",
+        "ms_per_step_wall_mean": wall_mean * 1e3,
+        "ms_per_step_events": [round(x * 1e3, 3) for x in per_step],
         "s_per_energy_grad": dt,
         "higher_is_better": True,
         "scaling": "weak",
@@ -712,7 +812,7 @@ def main():
         del prob
         torch.cuda.empty_cache()
         prob64, th64 = make_problem(wl.C5("fp64"), "fp64")
-        dt64, out64, grads64, _ = timed(prob64, th64, 2, 1, profile=False)
+        dt64, _, _, out64, grads64, _ = timed(prob64, th64, 3, 1, profile=False)
         om32 = float(out32["omega"].item())
         om64 = float(out64["omega"].item())
         r32, r64 = out32["rho"].cpu().numpy(), out64["rho"].cpu().numpy()
@@ -736,7 +836,11 @@ def main():
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(cfg)
+        pool = OraclePool(host_workers())
+        try:
+            result["cpu_baseline"] = cpu_baseline(pool)
+        finally:
+            pool.close()
         result["cpu_dense_ed"] = cpu_dense_ed()
     print(json.dumps(result), flush=True)
 

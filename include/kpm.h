@@ -193,7 +193,7 @@ size_t kpm_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int32_t 
  * alpha_{m-1} (App. B eq. alpha).  Vectors in `precision`, sums in FP64.
  * mu: [R][M] doubles (real parts; the imaginary parts vanish for Hermitian h).
  * ws: workspace of at least kpm_workspace_size(lat, R, M, ckpt_k, precision)
- * bytes, 256-byte aligned.  R * Lx * Ly must be below 2^31 (else KPM_EINVAL;
+ * bytes, 256-byte aligned.  R * Lx * Ly must be below 2^30 (else KPM_EINVAL;
  * the same holds for every instance of a batch plan). */
 int kpm_moments(const kpm_lattice* lat, const double* h, const double* ab,
                 const kpm_probes* probes, int32_t M, int32_t precision, int32_t ckpt_k,
@@ -217,8 +217,11 @@ int kpm_grand_potential(const kpm_lattice* lat, const double* h, const double* a
  * on the stencil.  alpha_m is recomputed backwards by the reversible
  * recursion alpha_m = 2 H~ alpha_{m+1} - alpha_{m+2}, reset at each stored
  * checkpoint pair.  Must follow kpm_grand_potential on the same ws with the
- * same arguments.  omega_bar: device double[1] or NULL (= 1).  rho: [19][N]
- * complex out (STENCIL layout, FP64). */
+ * same arguments (else KPM_EWORKSPACE).  It may be called again after that one
+ * forward call (e.g. a second backward pass): a repeated call first rebuilds
+ * alpha_{M-2}, alpha_{M-1} from the last checkpoint pair (fewer than ckpt_k
+ * forward steps) and returns the same rho.  omega_bar: device double[1] or
+ * NULL (= 1).  rho: [19][N] complex out (STENCIL layout, FP64). */
 int kpm_grand_potential_grad(const kpm_lattice* lat, const double* h, const double* ab,
                              const kpm_probes* probes, int32_t M, const double* C,
                              int32_t precision, int32_t ckpt_k, const double* omega_bar,

@@ -16,7 +16,21 @@ from __future__ import annotations
 
 import torch
 
+from . import kpm
 from .solver import KPMProblem
+
+
+def _adjoint(p: KPMProblem, h, ab, C, gbar):
+    """rho from the library's adjoint; when the shared workspace no longer
+    holds this forward's checkpoints (another forward ran on the same problem
+    in between), the forward recursion is run again first."""
+    try:
+        return p.grand_potential_grad(h, ab, C, omega_bar=gbar)
+    except kpm.KpmError as e:
+        if e.status != kpm.KPM_EWORKSPACE:
+            raise
+    p.grand_potential(h, ab, C)
+    return p.grand_potential_grad(h, ab, C, omega_bar=gbar)
 
 
 class GrandPotential(torch.autograd.Function):
@@ -36,7 +50,7 @@ class GrandPotential(torch.autograd.Function):
         n, chi, delta, h, ab, C = ctx.saved_tensors
         p = ctx.problem
         gbar = grad_out.reshape(1).to(torch.float64).contiguous()
-        rho = p.grand_potential_grad(h, ab, C, omega_bar=gbar)
+        rho = _adjoint(p, h, ab, C, gbar)
         dn, dchi, ddelta = p.build_H_vjp(n, chi, delta, rho)
         return dn, dchi, ddelta, None
 
@@ -58,5 +72,5 @@ class GrandPotentialSDW(torch.autograd.Function):
         *th, h, ab, C = ctx.saved_tensors
         p = ctx.problem
         gbar = grad_out.reshape(1).to(torch.float64).contiguous()
-        rho = p.grand_potential_grad(h, ab, C, omega_bar=gbar)
+        rho = _adjoint(p, h, ab, C, gbar)
         return (*p.build_H_sdw_vjp(th, rho), None)

@@ -79,9 +79,11 @@ long long group_nprobes(const kpm_probe_group& g) {
   return g.count;
 }
 
-// Probe-vector records are addressed with 32-bit indices p * N + site.
+// Probe-vector records are addressed with 32-bit record indices p * N + site,
+// and one Nambu component's element offset (4 values per record) must fit in
+// 32 bits as well.
 bool records_fit(const kpm_lattice* L, int R) {
-  return (long long)R * L->Lx * L->Ly < (1LL << 31);
+  return (long long)R * L->Lx * L->Ly < (1LL << 30);
 }
 
 // Fills the device group table; returns R or < 0.
@@ -181,7 +183,9 @@ Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32) {
   z.ckpt = align_up((size_t)R * z.N * z.rec * (size_t)z.nslots);
   z.mom = align_up(sizeof(double) * (size_t)M * R * z.ntile);
   z.musum = align_up(sizeof(double) * (size_t)M * R);
-  z.gpart = align_up(sizeof(double) * 2 * kNent * (size_t)z.N * R);   // sized for P = 1
+  // one [19][N] FP64 slice per adjoint probe range; a range holds kWaves * P
+  // probes, so P = 1 (the smallest block) needs the most ranges
+  z.gpart = align_up(sizeof(double) * 2 * kNent * (size_t)z.N * (size_t)((R + kWaves - 1) / kWaves));
   z.pcode = align_up((size_t)R * z.N);
   z.pw = align_up(sizeof(double) * (size_t)R);
   z.sink = align_up(4096);
@@ -254,14 +258,38 @@ void set_npb(Ctx& c) {
 }
 
 // Host copies of the tables uploaded for single-lattice calls, kept alive per
-// workspace so that an asynchronous copy never reads freed host memory.
+// workspace so that an asynchronous copy never reads freed host memory.  Each
+// entry records an event after its copies; the store keeps at most
+// kMaxTables workspaces, and an entry is dropped (oldest use first) only
+// after its event has completed.
 struct HostTables {
   std::vector<InstDev> inst;
   std::vector<int2> cmap;
   std::vector<int4> tmap;
+  hipEvent_t done = nullptr;
+  unsigned long long last_use = 0;
 };
 std::map<const void*, HostTables> g_tables;
 std::mutex g_tables_mu;
+unsigned long long g_tables_clock = 0;
+constexpr size_t kMaxTables = 16;
+
+// Drops the least recently used entries beyond kMaxTables (never `keep`).
+int prune_tables(const void* keep) {
+  while (g_tables.size() > kMaxTables) {
+    auto victim = g_tables.end();
+    for (auto it = g_tables.begin(); it != g_tables.end(); ++it)
+      if (it->first != keep && (victim == g_tables.end() || it->second.last_use < victim->second.last_use))
+        victim = it;
+    if (victim == g_tables.end()) break;
+    if (victim->second.done) {
+      KPM_HIP(hipEventSynchronize(victim->second.done));
+      (void)hipEventDestroy(victim->second.done);
+    }
+    g_tables.erase(victim);
+  }
+  return KPM_OK;
+}
 
 int upload_from(const std::vector<InstDev>& inst, const std::vector<int2>& cmap,
                 const std::vector<int4>& tmap, InstDev* d_inst, int2* d_cmap, int4* d_tmap,
@@ -284,12 +312,17 @@ int upload(Ctx& c, hipStream_t s) {
 int upload_single(Ctx& c, const void* ws, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_tables_mu);
   HostTables& t = g_tables[ws];
-  // a copy from pageable memory is staged before hipMemcpyAsync returns, so
-  // the previous upload from this store no longer reads it
+  // the previous upload from this store may still be reading it
+  if (t.done) KPM_HIP(hipEventSynchronize(t.done));
+  else KPM_HIP(hipEventCreateWithFlags(&t.done, hipEventDisableTiming));
   t.inst = c.inst;
   t.cmap = c.cmap;
   t.tmap = c.tmap;
-  return upload_from(t.inst, t.cmap, t.tmap, c.d_inst, c.d_cmap, c.d_tmap, s);
+  t.last_use = ++g_tables_clock;
+  int st = upload_from(t.inst, t.cmap, t.tmap, c.d_inst, c.d_cmap, c.d_tmap, s);
+  if (st != KPM_OK) return st;
+  KPM_HIP(hipEventRecord(t.done, s));
+  return prune_tables(ws);
 }
 
 int run_forward(const Ctx& c, bool ckpt, int nsteps, hipStream_t s) {
@@ -344,8 +377,28 @@ struct FwdSig {
   const double* ab;
   const double* C;
   int M, R, prec, k;
+  bool consumed;   // an adjoint has run: the alpha ping-pong holds alpha_0, alpha_1
 };
 std::map<const void*, FwdSig> g_fwd;
+
+// Puts alpha_{M-2} and alpha_{M-1} back into the ping-pong buffers after an
+// adjoint pass has run them down to alpha_0: copy the last stored checkpoint
+// pair (alpha_j0, alpha_j0+1), j0 = k floor((M-2)/k), and run the forward
+// steps j0+1 .. M-2 again (fewer than k steps; their moment partials are
+// rewritten with the same values and not reduced again).
+int restore_alpha(const Ctx& c, hipStream_t s) {
+  const InstDev& I = c.inst[0];
+  const int M = c.M, k = c.k;
+  const int j0 = ((M - 2) / k) * k;
+  const size_t vec = (size_t)I.R * I.N * (c.fp32 ? 16 : 32);
+  const char* ck = static_cast<const char*>(I.ckpt);
+  const size_t slot = 2 * (size_t)(j0 / k);
+  KPM_HIP(hipMemcpyAsync(I.A[j0 & 1], ck + slot * vec, vec, hipMemcpyDeviceToDevice, s));
+  KPM_HIP(hipMemcpyAsync(I.A[(j0 + 1) & 1], ck + (slot + 1) * vec, vec, hipMemcpyDeviceToDevice, s));
+  for (int m = j0 + 1; m + 1 < M; ++m)
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, M, k, 0, s));
+  return KPM_OK;
+}
 
 int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* ab,
                    const kpm_probes* pr, int M, const double* C, int prec, int k, void* ws,
@@ -445,7 +498,7 @@ int autotune(KpmBatchPlan* pl, hipStream_t s) {
     // forward: warm once, then time
     for (int rep = 0; rep < 2; ++rep) {
       KPM_HIP(hipEventRecord(e0, s));
-      st = run_forward(c, false, steps, s);
+      st = run_forward(c, true, steps, s);
       if (st != KPM_OK) return st;
       KPM_HIP(hipEventRecord(e1, s));
     }
@@ -457,7 +510,9 @@ int autotune(KpmBatchPlan* pl, hipStream_t s) {
       Pf = P;
     }
     if (c.M >= 3) {
-      // adjoint steps on whatever the buffers hold (timing only; m = M-3 >= 0)
+      // adjoint steps at m = M-3 (timing only) on initialised data: alpha from the
+      // forward steps just timed (with checkpoint stores, so an anchored step at
+      // small M reads written slots), gamma and the partial sums from k_adj_init
       KPM_HIP(hipEventRecord(e0, s));
       KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_tmap, c.ntl(), c.nra(), 0, c.M, c.k, 0, s));
       for (int q = 0; q < steps; ++q)
@@ -606,7 +661,7 @@ int kpm_grand_potential(const kpm_lattice* lat, const double* h, const double* a
   if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
   KPM_HIP(launch_omega(c.d_inst, 1, M, s));
   std::lock_guard<std::mutex> lk(g_mu);
-  g_fwd[ws] = FwdSig{h, ab, C, M, c.Rmax, precision, ckpt_k};
+  g_fwd[ws] = FwdSig{h, ab, C, M, c.Rmax, precision, ckpt_k, false};
   return KPM_OK;
 }
 
@@ -618,6 +673,7 @@ int kpm_grand_potential_grad(const kpm_lattice* lat, const double* h, const doub
   Ctx c;
   int st = prepare_single(c, lat, h, ab, probes, M, C, precision, ckpt_k, ws, ws_bytes);
   if (st != KPM_OK) return st;
+  bool consumed;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_fwd.find(ws);
@@ -626,12 +682,20 @@ int kpm_grand_potential_grad(const kpm_lattice* lat, const double* h, const doub
     if (f.h != h || f.ab != ab || f.C != C || f.M != M || f.R != c.Rmax || f.prec != precision ||
         f.k != ckpt_k)
       return KPM_EWORKSPACE;
+    consumed = f.consumed;
   }
   c.inst[0].rho = reinterpret_cast<double2*>(rho);
   c.inst[0].omega_bar = omega_bar;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
-  return run_adjoint(c, s);
+  // a second adjoint after one forward (e.g. two backward passes): the first
+  // one left alpha_0, alpha_1 in the ping-pong buffers
+  if (consumed && (st = restore_alpha(c, s)) != KPM_OK) return st;
+  if ((st = run_adjoint(c, s)) != KPM_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_fwd.find(ws);
+  if (it != g_fwd.end()) it->second.consumed = true;
+  return KPM_OK;
 }
 
 int kpm_density_matrix(const kpm_lattice* lat, const double* h, const double* ab,

@@ -262,6 +262,50 @@ def test_grad_requires_forward():
     assert e.value.status == kpm.KPM_EWORKSPACE
 
 
+@pytest.mark.parametrize("prec,M,k", [("fp64", 40, 8), ("fp64", 2, 2), ("fp64", 3, 2),
+                                      ("fp64", 65, 64), ("fp32", 257, 64), ("fp32", 47, 4)])
+def test_grad_twice_after_one_forward(prec, M, k):
+    """A second adjoint after one forward call (a second backward pass) must
+    give the same rho: the first adjoint ran the alpha ping-pong down to
+    alpha_0, alpha_1, and the repeated call rebuilds alpha_{M-2}, alpha_{M-1}
+    from the last checkpoint pair.  Both equal the oracle's rho."""
+    cfg = _cfg(M=M, ckpt_k=k)
+    p, h, ab, C = _run_forward(cfg, prec=prec)
+    om = host(p.grand_potential(h, ab, C))[0]
+    r1 = host(p.grand_potential_grad(h, ab, C)).copy()
+    r2 = host(p.grand_potential_grad(h, ab, C)).copy()
+    r3 = host(p.grand_potential_grad(h, ab, C))
+    assert p.status() == 0
+    assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
+    st, a, b, Cref = H.oracle_inputs(cfg, M=M)
+    ref = H.plain(cfg, st, a, b, Cref)
+    tol = TOL if prec == "fp64" else 1e-5
+    assert abs(om - ref["omega"]) < tol * abs(ref["omega"])
+    assert H.rel_err(r2, ref["rho"]) < tol
+
+
+def test_autograd_backward_twice():
+    """torch.autograd.grad twice on one graph (retain_graph) and a backward
+    after a second forward on the same problem give the first gradients."""
+    from paper_2212_05685_amd.autograd import GrandPotential
+    cfg = _cfg(8, 8, 2, M=70, ckpt_k=8, probes=(wl.ProbeSpec("colored_z4", 1, 3, 4, 4, 1, 0, 1.0),))
+    p = problem(cfg)
+    th = [x.requires_grad_(True) for x in theta_dev(cfg)]
+    om = GrandPotential.apply(*th, p)
+    g1 = [host(g).copy() for g in torch.autograd.grad(om, th, retain_graph=True)]
+    g2 = [host(g).copy() for g in torch.autograd.grad(om, th, retain_graph=True)]
+    # another forward on the same problem (its workspace now holds other checkpoints)
+    th_b = [x.detach().clone().requires_grad_(True) for x in th]
+    with torch.no_grad():
+        th_b[0] += 1e-3
+    om_b = GrandPotential.apply(*th_b, p)
+    g3 = [host(g).copy() for g in torch.autograd.grad(om, th, retain_graph=True)]
+    gb = [host(g) for g in torch.autograd.grad(om_b, th_b)]
+    for a_, b_, c_ in zip(g1, g2, g3):
+        assert np.array_equal(a_, b_) and np.array_equal(a_, c_)
+    assert max(H.rel_err(x, y) for x, y in zip(gb, g1)) > 1e-8   # a different point
+
+
 @pytest.mark.parametrize("k", [8, 2])
 def test_batch_matches_single(k):
     """Batch plan (plain and graph-replayed) against single lattices, at

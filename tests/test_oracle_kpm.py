@@ -7,6 +7,9 @@ derivations, published test vectors and brute force.
 * coefficients: the undamped series reproduces f(a x + b) pointwise, the odd
   part of f is e/2 so c_1 = a/4 and c_odd>1 = 0 at b = 0, and doubling the
   quadrature changes nothing;
+* Gershgorin bounds: the discs of hand-built matrices worked out by hand
+  (including a tight case whose rescaled spectrum is exactly -+0.995), and
+  the stencil-built sparse form equals the dense rows and encloses eigh;
 * moments: mu_0 = sum_l w_l |r_l|^2; exact-trace moments equal
   sum_n cos(m arccos x_n) from eigh; odd moments vanish for particle-hole
   symmetric h (b = 0);
@@ -55,6 +58,52 @@ def test_coefficients_reproduce_f_and_odd_part():
     assert np.max(np.abs(C[3::2])) < 1e-13
     Cj = chebyshev.kpm_coefficients(M, T, a, b)
     assert abs(Cj[1] - np.cos(np.pi / (M + 1)) * a / 2) < 1e-14
+
+
+def test_gershgorin_hand_built_discs():
+    """Gershgorin discs of a hand-built 3 x 3 Hermitian matrix, worked out by
+    hand: row 0 has centre 1 and radius |0.3i| + |0.2| = 0.5, row 1 centre -2
+    and radius 0.3 + |0.1 + 0.1i| = 0.3 + 0.1 sqrt 2, row 2 centre 0.5 and
+    radius 0.2 + 0.1 sqrt 2.  So Emin = -2.3 - 0.1 sqrt 2 (row 1) and
+    Emax = 1.5 (row 0).  A radius that counted |h_II|, a sign slip on the
+    centre or a column sum of the modulus-free entries each moves a bound."""
+    s2 = np.sqrt(2.0)
+    H = np.array([[1.0, 0.3j, 0.2],
+                  [-0.3j, -2.0, 0.1 + 0.1j],
+                  [0.2, 0.1 - 0.1j, 0.5]])
+    Emin, Emax = chebyshev.gershgorin(H)
+    assert abs(Emin - (-2.3 - 0.1 * s2)) < 1e-15
+    assert abs(Emax - 1.5) < 1e-15
+    import scipy.sparse as sp
+    assert chebyshev.gershgorin_sparse(sp.csr_matrix(H)) == (Emin, Emax)
+    # a diagonal matrix: the discs are points, the bounds the extreme entries
+    assert chebyshev.gershgorin(np.diag([0.25, -3.0, 7.5])) == (-3.0, 7.5)
+    # [[0, 1], [1, 0]] has eigenvalues -1, 1 and the discs are [-1, 1]: tight,
+    # and the rescale maps them to -+0.995 (pad 0.01)
+    P = np.array([[0.0, 1.0], [1.0, 0.0]])
+    a, b = chebyshev.rescale(*chebyshev.gershgorin(P))
+    assert abs(a - 2.0 / 1.99) < 1e-15 and b == 0.0
+    assert np.allclose(np.linalg.eigvalsh((P - b * np.eye(2)) / a), [-0.995, 0.995], atol=1e-15)
+    # a shifted spectrum: diag(3, 5) with coupling 1 -> discs [2, 4] and [4, 6]
+    S = np.array([[3.0, 1.0], [1.0, 5.0]])
+    assert chebyshev.gershgorin(S) == (2.0, 6.0)
+    a, b = chebyshev.rescale(2.0, 6.0)
+    assert abs(a - 4.0 / 1.99) < 1e-15 and b == 4.0
+
+
+def test_gershgorin_of_stencil_matches_dense_rows():
+    """The stencil-built sparse h gives the same bounds as its dense form,
+    and those enclose the spectrum."""
+    cfg = wl.C1()
+    n, chi, dlt = wl.make_theta(cfg)
+    st = builder.build_stencil(cfg.Lx, cfg.Ly, cfg.n_v, cfg.t, cfg.tp, cfg.J, cfg.mu, n, chi, dlt)
+    Hd = builder.dense_from_stencil(st, cfg.Lx, cfg.Ly)
+    Hs = builder.sparse_from_stencil(st, cfg.Lx, cfg.Ly)
+    lo, hi = chebyshev.gershgorin(Hd)
+    lo_s, hi_s = chebyshev.gershgorin_sparse(Hs)
+    assert abs(lo - lo_s) < 1e-13 and abs(hi - hi_s) < 1e-13
+    E = np.linalg.eigvalsh(Hd)
+    assert lo <= E[0] and E[-1] <= hi
 
 
 def test_quadrature_doubling_converged():
