@@ -54,7 +54,8 @@ enum {
                           the spectrum is not inside the rescaled interval       */
   KPM_ENOTSUP = -5,    /* option not supported                                  */
   KPM_EWORKSPACE = -6, /* workspace too small or not prepared by the forward call */
-  KPM_ENOCONV = -7     /* chemical-potential search used its evaluation budget    */
+  KPM_ENOCONV = -7,    /* chemical-potential search used its evaluation budget    */
+  KPM_ETOOBIG = -8     /* problem does not fit the static scratch of a no-alloc call */
 };
 
 enum { KPM_FP64 = 0, KPM_FP32 = 1 };   /* recurrence vectors; reductions always FP64 */
@@ -198,6 +199,29 @@ size_t kpm_workspace_size(const kpm_lattice* lat, int32_t R, int32_t M, int32_t 
 int kpm_moments(const kpm_lattice* lat, const double* h, const double* ab,
                 const kpm_probes* probes, int32_t M, int32_t precision, int32_t ckpt_k,
                 double* mu, void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of the library's static device scratch (one per GPU, held until the
+ * process ends) used by kpm_moments_noalloc. */
+#define KPM_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* kpm_moments for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation): the
+ * same moments, with no workspace argument.  Its buffers live in a file-scope
+ * static device array of KPM_NOALLOC_SCRATCH_BYTES per GPU; the call makes no
+ * hipMalloc, hipFree or other allocation.  It needs the forward-only
+ * workspace: 2 vector sets of R * Lx * Ly records (16 B FP32, 32 B FP64), the
+ * FP64 moment partials [M][tiles][R] (tiles = ceil(Lx/8) ceil(Ly/4)),
+ * the rescaled coefficients (288 B FP32 / 576 B FP64 per tile site) and
+ * per-probe tables; a problem beyond the scratch returns KPM_ETOOBIG with
+ * nothing enqueued (e.g. 48 x 48 with 64 probes and M = 1024 fits in FP32).
+ * The scratch is shared by every call on one GPU and keeps the last call's
+ * contents: every part a call reads is written by it first.  Calls that
+ * overlap on one GPU (different streams or threads) race on the scratch and
+ * must be serialised by the caller.  The stream must belong to the current
+ * device.  Arguments, mu layout and device errors as kpm_moments. */
+int kpm_moments_noalloc(const kpm_lattice* lat, const double* h, const double* ab,
+                        const kpm_probes* probes, int32_t M, int32_t precision, double* mu,
+                        void* stream);
 
 /* Grand potential Omega = sum_l w_l sum_m C_m mu_{l,m} (App. B eq. F_KPM with
  * the probe average).  Runs the forward recursion, keeps the checkpoint pairs

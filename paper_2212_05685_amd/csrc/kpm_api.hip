@@ -165,11 +165,13 @@ int g_probe_block = 0;   // 0 = automatic
 // ------------------------------------------------------------ instance layout
 struct Sizes {
   int N, R, M, nchunk, ntile;
-  size_t rec, coef, vec, ckpt, mom, musum, gpart, pcode, pw, sink;
+  size_t rec, coef, vec, gvec, ckpt, mom, musum, gpart, pcode, pw, sink;
   long long nslots;
 };
 
-Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32) {
+// fwd_only: the forward recursion and moments alone (no gamma vectors,
+// checkpoints or adjoint partial sums).
+Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32, bool fwd_only = false) {
   Sizes z{};
   z.N = L->Lx * L->Ly;
   z.R = R;
@@ -189,11 +191,13 @@ Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32) {
   z.pcode = align_up((size_t)R * z.N);
   z.pw = align_up(sizeof(double) * (size_t)R);
   z.sink = align_up(4096);
+  z.gvec = z.vec;
+  if (fwd_only) z.gvec = z.ckpt = z.gpart = 0;
   return z;
 }
 
 size_t inst_bytes(const Sizes& z) {
-  return align_up(sizeof(int)) + z.coef + 4 * z.vec + z.ckpt + z.mom + z.musum + z.gpart +
+  return align_up(sizeof(int)) + z.coef + 2 * z.vec + 2 * z.gvec + z.ckpt + z.mom + z.musum + z.gpart +
          align_up(sizeof(double) * ((z.M + kBlock - 1) / kBlock)) + z.pcode + z.pw + z.sink;
 }
 
@@ -204,8 +208,8 @@ void carve(InstDev& I, const Sizes& z, char* base) {
   I.coef = o;                             o += z.coef;
   I.A[0] = o;                             o += z.vec;
   I.A[1] = o;                             o += z.vec;
-  I.G[0] = o;                             o += z.vec;
-  I.G[1] = o;                             o += z.vec;
+  I.G[0] = o;                             o += z.gvec;
+  I.G[1] = o;                             o += z.gvec;
   I.ckpt = o;                             o += z.ckpt;
   I.mom = reinterpret_cast<double*>(o);   o += z.mom;
   I.musum = reinterpret_cast<double*>(o); o += z.musum;
@@ -402,7 +406,7 @@ int restore_alpha(const Ctx& c, hipStream_t s) {
 
 int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* ab,
                    const kpm_probes* pr, int M, const double* C, int prec, int k, void* ws,
-                   size_t ws_bytes) {
+                   size_t ws_bytes, bool fwd_only = false) {
   if (!valid_lattice(L) || !h || !ab || !ws) return KPM_EINVAL;
   if (M < 2 || k < 2) return KPM_EINVAL;
   if (prec != KPM_FP64 && prec != KPM_FP32) return KPM_EINVAL;
@@ -413,7 +417,7 @@ int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* 
   const int R = build_groups(L, pr, I.g, &ng);
   if (R < 1 || !records_fit(L, R)) return KPM_EINVAL;
   c.fp32 = prec == KPM_FP32;
-  const Sizes z = sizes(L, R, M, k, c.fp32);
+  const Sizes z = sizes(L, R, M, k, c.fp32, fwd_only);
   const WsLayout w = ws_layout(z);
   if (ws_bytes < w.total) return KPM_EWORKSPACE;
   char* base = static_cast<char*>(ws);
@@ -552,6 +556,47 @@ int batch_sequence(KpmBatchPlan* pl, hipStream_t s) {
 
 }  // namespace
 
+// ------------------------------------------------------------ static scratch
+// Workspace of kpm_moments_noalloc: one array per GPU, held for the life of
+// the process.  In host code the name is only a stand-in for the symbol; the
+// device address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) unsigned char scratch[KPM_NOALLOC_SCRATCH_BYTES];
+
+namespace kpm {
+// Writes the instance table and the site-chunk and tile maps of a single
+// lattice (as finish_ctx lays them out) into the scratch; the table travels
+// as a kernel argument, so no host buffer has to outlive the call.
+__global__ void k_fill_tables(InstDev I, InstDev* d_inst, int2* d_cmap, int4* d_tmap, int nchunk,
+                              int ntile, int tiles_x) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) *d_inst = I;
+  if (t < nchunk) d_cmap[t] = make_int2(0, t * kBlock);
+  if (t < ntile) d_tmap[t] = make_int4(0, (t % tiles_x) * 8, (t / tiles_x) * 4, t);
+}
+}  // namespace kpm
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device ordinal -> address of `scratch` there
+
+// Address of the current device's scratch, looked up once per device with
+// that device current.
+int scratch_address(void** out) {
+  int dev = 0;
+  KPM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    KPM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return KPM_EDEVICE;
+    it = g_scratch_ptr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return KPM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int32_t kpm_probe_count(const kpm_lattice* lat, const kpm_probes* probes) {
@@ -639,6 +684,36 @@ int kpm_moments(const kpm_lattice* lat, const double* h, const double* ab, const
   if (st != KPM_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+  if ((st = run_forward(c, false, M, s)) != KPM_OK) return st;
+  if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_fwd.erase(ws);
+  return KPM_OK;
+}
+
+int kpm_moments_noalloc(const kpm_lattice* lat, const double* h, const double* ab,
+                        const kpm_probes* probes, int32_t M, int32_t precision, double* mu,
+                        void* stream) {
+  if (!mu || !valid_lattice(lat) || M < 2) return KPM_EINVAL;
+  if (precision != KPM_FP64 && precision != KPM_FP32) return KPM_EINVAL;
+  const int R = build_groups(lat, probes, nullptr, nullptr);
+  if (R < 1 || !records_fit(lat, R)) return KPM_EINVAL;
+  // forward-only layout (no gamma vectors, checkpoints or adjoint sums)
+  const WsLayout w = ws_layout(sizes(lat, R, M, M, precision == KPM_FP32, true));
+  if (w.total > (size_t)KPM_NOALLOC_SCRATCH_BYTES) return KPM_ETOOBIG;
+  void* ws = nullptr;
+  int st = scratch_address(&ws);
+  if (st != KPM_OK) return st;
+  Ctx c;
+  st = prepare_single(c, lat, h, ab, probes, M, nullptr, precision, std::max<int32_t>(M, 2), ws,
+                      KPM_NOALLOC_SCRATCH_BYTES, true);
+  if (st != KPM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int tiles_x = (lat->Lx + kTX - 1) / kTX;
+  const int nt = std::max(c.nch(), c.ntl());
+  hipLaunchKernelGGL(k_fill_tables, dim3((nt + 255) / 256), dim3(256), 0, s, c.inst[0], c.d_inst,
+                     c.d_cmap, c.d_tmap, c.nch(), c.ntl(), tiles_x);
+  KPM_HIP(hipGetLastError());
   if ((st = run_forward(c, false, M, s)) != KPM_OK) return st;
   if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -983,6 +1058,7 @@ const char* kpm_strerror(int status) {
     case KPM_ENOTSUP: return "not supported";
     case KPM_EWORKSPACE: return "workspace too small or not prepared by the forward call";
     case KPM_ENOCONV: return "chemical-potential search used its evaluation budget";
+    case KPM_ETOOBIG: return "problem larger than the library's static scratch (KPM_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }

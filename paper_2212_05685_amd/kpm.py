@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libkpm.so")
 
 KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_EBOUNDS, KPM_ENOTSUP, KPM_EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
 KPM_ENOCONV = -7
+KPM_ETOOBIG = -8
+KPM_NOALLOC_SCRATCH_BYTES = 64 << 20
 KPM_RMFT_STATS_LEN = 520
 KPM_RMFT_BISECTION, KPM_RMFT_ILLINOIS = 0, 1
 KPM_RMFT_ADJOINT, KPM_RMFT_DIRECT = 0, 1
@@ -39,7 +41,7 @@ EXPORTS = (
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
     "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
     "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_build_H_sdw_vjp", "kpm_bloch_H", "kpm_gutzwiller_weights", "kpm_supercell_workspace_size",
-    "kpm_supercell_ldos",
+    "kpm_supercell_ldos", "kpm_moments_noalloc",
 )
 
 
@@ -94,6 +96,8 @@ def _load():
         "kpm_workspace_size": (c_size_t, [POINTER(Lattice), c_int32, c_int32, c_int32, c_int32]),
         "kpm_moments": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, c_int32, c_int32,
                                   P, P, c_size_t, P]),
+        "kpm_moments_noalloc": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, c_int32, P,
+                                          P]),
         "kpm_grand_potential": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P, c_int32,
                                           c_int32, P, P, P, c_size_t, P]),
         "kpm_grand_potential_grad": (c_int32, [POINTER(Lattice), P, P, POINTER(Probes), c_int32, P,
@@ -280,6 +284,15 @@ def kpm_moments(lat, h, ab, probes, M, precision, ckpt_k, mu, ws, stream=None):
                             precision, ckpt_k, _ptr(mu, torch.float64, R * M, "mu"),
                             _ptr(ws, torch.uint8, None, "ws"), ws.numel(), _stream(stream)),
            "kpm_moments")
+
+
+def kpm_moments_noalloc(lat, h, ab, probes, M, precision, mu, stream=None):
+    N = lat.Lx * lat.Ly
+    R = kpm_probe_count(lat, probes)
+    _check(_lib.kpm_moments_noalloc(ctypes.byref(lat), _ptr(h, torch.complex128, NENT * N, "h"),
+                                    _ptr(ab, torch.float64, 2, "ab"), ctypes.byref(_probes(probes)), M,
+                                    precision, _ptr(mu, torch.float64, R * M, "mu"), _stream(stream)),
+           "kpm_moments_noalloc")
 
 
 def kpm_grand_potential(lat, h, ab, probes, M, C, precision, ckpt_k, omega, mu, ws, stream=None):
