@@ -89,7 +89,7 @@ def traffic_summary(base: str, copy_bytes: int) -> None:
     f_fetch, f_write = copy_bytes / (kib_f * 1024.0), copy_bytes / (kib_w * 1024.0)
     out = {}
     # the plain step launches (not the checkpoint-storing forward nor the last adjoint step)
-    for short, tags in (("k_adj", (">::adj<false>(",)), ("k_fwd", (">::fwd<false>(",))):
+    for short, tags in (("k_adj", (">::adj<false>(",)), ("k_fwd", (">::fwdp<false, false>(",))):
         fr = [v for k, vs in fetch.items() if any(t in k for t in tags) for v in vs]
         wr = [v for k, vs in write.items() if any(t in k for t in tags) for v in vs]
         if not fr or not wr:
@@ -172,7 +172,7 @@ def timed(prob, th, steps, warmup, profile):
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     if profile:
-        kpm.kpm_profile_begin(16)
+        kpm.kpm_profile_begin(128)
     t0 = time.perf_counter()
     for s in range(steps):
         ev[s][0].record()

@@ -551,12 +551,15 @@ int kpm_supercell_ldos(const kpm_lattice* lat, const double* h, int32_t Mx, int3
                        double* evals, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- measurement ----------------------------------------------------------
- * Between kpm_profile_begin and kpm_profile_end, one in `sample_every`
- * forward-step and adjoint-step kernel launches of this library (not inside a
- * graph capture) carries start/stop events recorded by its own dispatch on its
- * own stream.  kpm_profile_end synchronises those events and returns the
- * summed durations (milliseconds, host memory) and counts of the sampled
- * launches of both kinds. */
+ * Between kpm_profile_begin and kpm_profile_end, runs of min(16, sample_every)
+ * consecutive forward-step (or adjoint-step) kernel launches of this library,
+ * one run starting every `sample_every` launches of that kind, are timed by
+ * start/stop events recorded by the first and last dispatch of the run on its
+ * own stream (not inside a graph capture; a run interrupted by any other
+ * launch of the library is dropped).  kpm_profile_end synchronises those
+ * events and returns, for both kinds, the summed run durations (milliseconds,
+ * host memory) and the number of launches they cover, so that the ratio is the
+ * average launch duration, inter-kernel gaps included. */
 int kpm_profile_begin(int32_t sample_every);
 int kpm_profile_end(double* fwd_ms, int32_t* n_fwd, double* adj_ms, int32_t* n_adj);
 

@@ -28,7 +28,7 @@ hipError_t launch_bounds(int, int, const double*, double*, hipStream_t);
 hipError_t launch_rescale(const InstDev*, const int4*, int, bool, hipStream_t);
 hipError_t launch_coeffs(int, int, double, const double*, double*, hipStream_t);
 hipError_t launch_cheb(bool, int, int, const InstDev*, const int4*, int, int, int, int, int, int,
-                       hipStream_t);
+                       int, hipStream_t);
 hipError_t launch_mom_reduce(const InstDev*, int, int, int, double*, hipStream_t);
 hipError_t launch_omega(const InstDev*, int, int, hipStream_t);
 hipError_t launch_rho(const InstDev*, const int2*, int, hipStream_t);
@@ -239,6 +239,8 @@ struct Ctx {
   int nra() const { return (Rmax + kWaves * Pa - 1) / (kWaves * Pa); }
   int nch() const { return (int)cmap.size(); }
   int ntl() const { return (int)tmap.size(); }
+  // tiles per lattice row for a single lattice (blocks compute their tile), 0 for a batch
+  int tpx() const { return inst.size() == 1 ? (inst[0].Lx + kTX - 1) / kTX : 0; }
 };
 
 void finish_ctx(Ctx& c) {
@@ -334,10 +336,10 @@ int run_forward(const Ctx& c, bool ckpt, int nsteps, hipStream_t s) {
   hipLaunchKernelGGL(k_set_status, dim3((ninst + 63) / 64), dim3(64), 0, s, c.d_inst, ninst, 0);
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), 0, c.M, c.k,
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, c.M, c.k,
                       ckpt ? 1 : 0, s));
   for (int m = 0; m + 1 < nsteps; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, c.M, c.k,
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, c.M, c.k,
                         ckpt ? 1 : 0, s));
   return KPM_OK;
 }
@@ -351,10 +353,10 @@ int run_moments(const Ctx& c, double* mu_user, hipStream_t s) {
 
 int run_adjoint(const Ctx& c, hipStream_t s) {
   const int M = c.M;
-  KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_tmap, c.ntl(), c.nra(), 0, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, M, c.k, 0, s));
   for (int m = M - 3; m >= 0; --m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.nra(), m, M, c.k, 0, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.nra(), 0, M, c.k, 1, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), m, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, M, c.k, 1, s));
   KPM_HIP(launch_rho(c.d_inst, c.d_cmap, c.nch(), s));
   return KPM_OK;
 }
@@ -400,7 +402,7 @@ int restore_alpha(const Ctx& c, hipStream_t s) {
   KPM_HIP(hipMemcpyAsync(I.A[j0 & 1], ck + slot * vec, vec, hipMemcpyDeviceToDevice, s));
   KPM_HIP(hipMemcpyAsync(I.A[(j0 + 1) & 1], ck + (slot + 1) * vec, vec, hipMemcpyDeviceToDevice, s));
   for (int m = j0 + 1; m + 1 < M; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, M, k, 0, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, k, 0, s));
   return KPM_OK;
 }
 
@@ -518,9 +520,9 @@ int autotune(KpmBatchPlan* pl, hipStream_t s) {
       // forward steps just timed (with checkpoint stores, so an anchored step at
       // small M reads written slots), gamma and the partial sums from k_adj_init
       KPM_HIP(hipEventRecord(e0, s));
-      KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_tmap, c.ntl(), c.nra(), 0, c.M, c.k, 0, s));
+      KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, c.M, c.k, 0, s));
       for (int q = 0; q < steps; ++q)
-        KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.nra(), c.M - 3, c.M,
+        KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), c.M - 3, c.M,
                             c.M + 1, 0, s));
       KPM_HIP(hipEventRecord(e1, s));
       KPM_HIP(hipEventSynchronize(e1));
@@ -811,10 +813,10 @@ int kpm_density_matrix_direct(const kpm_lattice* lat, const double* h, const dou
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
   KPM_HIP(launch_direct_coef(c.d_inst, 1, M, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), 0, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, s));
   // step m writes alpha_{m+1}; even steps also add D_m alpha_m + D_{m+1} alpha_{m+1} to y
   for (int m = 0; m + 1 < M; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, (m & 1) ? 1 : 5, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, M,
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, (m & 1) ? 1 : 5, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M,
                         c.k, m == 0 ? 1 : 0, s));
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_omega(c.d_inst, 1, M, s));
@@ -840,10 +842,10 @@ int kpm_moments_doubling(const kpm_lattice* lat, const double* h, const double* 
   hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, c.d_inst, 1, 0);
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), 0, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, s));
   // alpha_1 .. alpha_{M/2}: every moment slot below M is then written
   for (int m = 0; m < M / 2; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, 4, c.d_inst, c.d_tmap, c.ntl(), c.nrf(), m, M, c.k, 0, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, 4, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, c.k, 0, s));
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_mom_double(c.d_inst, 1, c.inst[0].R * M, M, mu, s));
   if (omega) KPM_HIP(launch_omega(c.d_inst, 1, M, s));

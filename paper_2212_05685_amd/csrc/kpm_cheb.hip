@@ -4,26 +4,28 @@
 // gamma_m = w C_{m+1} r + 2 H~ gamma_{m+1} - gamma_{m+2} and accumulates
 // dOmega/dH~ on the stencil (App. B, eqs. alpha, dFdH, dalphadH, beta).
 //
-// Work decomposition (gfx950, wave64):
-//  * A wave owns one 8 x 4 tile of sites and TWO lanes per site, one per Nambu
-//    row, so each lane keeps only its row's 18 coefficients of H~ (36 VGPRs in
-//    FP32) for the whole launch.  Lane l: site s = l >> 1 of the tile
-//    (tx = s & 7, ty = s >> 3), row a = l & 1.
+// Work decomposition (gfx950, wave64), sites tiled 8 x 4:
+//  * Adjoint (both precisions) and FP64 forward: a wave owns one tile with TWO
+//    lanes per site, one per Nambu row, so each lane keeps only its row's 18
+//    coefficients of H~ (36 VGPRs in FP32) for the whole launch.  Lane l: site
+//    s = l >> 1 of the tile (tx = s & 7, ty = s >> 3), row a = l & 1.
+//  * FP32 forward (fwdp_body): two probes per wave step, one lane per (probe
+//    slot, site) applying both Nambu rows, register coefficients of the
+//    model's sparse rows, the tile's coefficient table staged once per block.
 //  * The tile's input vector plus a one-site halo (10 x 6 = 60 records) is
-//    staged through the wave's own LDS buffer, double-buffered: while probe p is
-//    computed from LDS, the global loads of probe p+1's halo tile (one 16 B /
-//    32 B record per lane) are in flight.
+//    staged through the wave's own LDS buffer, double-buffered: while one probe
+//    (pair) is computed from LDS, the global loads of the next are in flight.
 //  * The 4 waves of a block share the tile and take different probe subgroups
 //    (PW probes each), so the adjoint's dOmega/dH~ contributions of 4 PW probes
 //    are summed in LDS and written once per (site, probe range) per step.
-//  * Blocks are dispatched round-robin over the 8 XCDs.  When the number of
-//    probe ranges divides 8, XCD x takes one probe range on one contiguous
-//    strip of tiles (block_work), so the halo rows it shares stay in its L2
-//    and each tile's coefficients and partial sums are touched by as many
-//    XCDs as there are ranges.
+//  * Blocks are dispatched round-robin over the 8 XCDs and scheduled so that
+//    each XCD sweeps a spatially coherent part of the lattice (block_work):
+//    the adjoint keeps one probe range per XCD on contiguous strips of tiles,
+//    the forward sweeps one strip per XCD, range after range.
 #include <hip/hip_ext.h>
 
 #include <mutex>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -251,16 +253,36 @@ __device__ __forceinline__ double probe_weight(const InstDev& I, int p) {
   return ((const __attribute__((address_space(4))) double*)(I.pw))[p];
 }
 
-// Block -> (tile, probe range).  When the number of probe ranges divides 8,
-// XCD x = blockIdx % 8 (blocks go to the 8 XCDs round-robin) takes range
-// x % nranges on the (x / nranges)-th contiguous strip of `chunk` tiles: each
-// XCD sweeps a spatially coherent part of the lattice with one probe range,
-// so the halo rows it shares stay in its L2, and a tile's coefficients and
-// partial sums are touched by nranges XCDs only.  Otherwise tile-major.
-struct Sched { int nranges, chunk, ntiles; };
+// Block -> (tile, probe range).  Blocks go to the 8 XCDs round-robin (XCD
+// x = blockIdx % 8), and two schedules keep each XCD on a spatially coherent
+// part of the lattice, so the halo rows neighbouring tiles share stay in its
+// L2:
+//  * RANGES (nranges divides 8): XCD x takes range x % nranges on the
+//    (x / nranges)-th of 8 / nranges contiguous strips of `chunk` tiles; a
+//    tile's coefficients and partial sums are touched by nranges XCDs.
+//  * STRIPS: XCD x takes the x-th of 8 contiguous strips of `chunk` tiles and
+//    sweeps it once per probe range, range after range; every tile's
+//    coefficients are read by one XCD only, at the price of halo rows read
+//    twice at the 8 strip boundaries.
+//  Otherwise tile-major (range fastest).
+enum : int { kSchedTileMajor = 0, kSchedRanges = 1, kSchedStrips = 2 };
+// tiles_x > 0: a single lattice, whose tile t sits at ((t % tiles_x) 8, (t / tiles_x) 4),
+// so a block finds its tile without reading the tile table
+struct Sched { int nranges, chunk, ntiles, mode, tiles_x; };
+
+__device__ __forceinline__ int4 tile_of(const Sched& sc, const int4* __restrict__ tmap, int tile) {
+  if (sc.tiles_x > 0) return make_int4(0, (tile % sc.tiles_x) * TX, (tile / sc.tiles_x) * TY, tile);
+  return tmap[tile];
+}
 __device__ __forceinline__ bool block_work(const Sched& sc, int& tile, int& range) {
   const int b = blockIdx.x;
-  if (sc.chunk > 0) {
+  if (sc.mode == kSchedStrips) {
+    const int x = b & 7, i = b >> 3;
+    range = i / sc.chunk;
+    tile = x * sc.chunk + (i - range * sc.chunk);
+    return tile < sc.ntiles;
+  }
+  if (sc.mode == kSchedRanges) {
     const int x = b & 7;
     range = x % sc.nranges;
     tile = (x / sc.nranges) * sc.chunk + (b >> 3);
@@ -283,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDev* __restrict__ ins
                                                  int k_ckpt, int store_ckpt) {
   int tile, range;
   if (!block_work(sc, tile, range)) return;               // block-uniform
-  const int4 tm = tmap[tile];
+  const int4 tm = tile_of(sc, tmap, tile);
   const InstDev& I = insts[tm.x];
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
@@ -441,7 +463,7 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   __shared__ Stage<V> S;
   int tile, range;
   if (!block_work(sc, tile, range)) return;               // block-uniform
-  const int4 tm = tmap[tile];
+  const int4 tm = tile_of(sc, tmap, tile);
   const InstDev& I = insts[tm.x];
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
@@ -569,6 +591,305 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
   }
 }
 
+// ------------------------------------------------------------- forward step, FP32 pairs
+// The FP32 forward step with two probes per wave step: lane l takes probe
+// slot q = l >> 5 of the step and tile site s = l & 31, and applies both Nambu
+// rows of its site.  Per (site, probe) this halves the LDS reads (the 9 staged
+// records serve both rows) and the global loads and stores (one 16 B record
+// instead of two 8 B components), against one row per lane.
+//
+// Rows: in the model's h the on-site block is diagonal and real (pairing only
+// on nearest-neighbour bonds, App. A), and the next-nearest-neighbour blocks
+// are Nambu-diagonal.  Those 50 coefficients of the two rows stay in
+// registers; the 20 others (the on-site (i0,i1) pair and the anomalous next-
+// nearest-neighbour entries) are staged in LDS and used only by waves whose
+// tile has one of them nonzero (a ballot at launch), so any stencil is exact.
+// The factor 2 of the recursion is folded into the register coefficients and
+// alpha_{m-1} seeds the accumulator: alpha_{m+1} = (2 H~) alpha_m - alpha_{m-1}
+// (FIRST, m = 0: alpha_1 = (1/2)(2 H~) alpha_0).
+//
+// The probe loop is fully unrolled (PW/2 steps), so the ring of loads in
+// flight (FPP steps ahead: both halo records, the own alpha_{m-1} record and
+// the code byte) lives in fixed registers and every memory wait count is
+// static; every load and store is issued on every path (clamped probe index,
+// sink for lanes outside the lattice or past the wave's last probe).
+constexpr int PREC = 72;     // staged record slots per probe (60 used; the pitch keeps the
+                             // two slots' reads of one tile row in disjoint LDS banks)
+constexpr int FPP = 1;       // probe pairs in flight
+
+struct PairLane {
+  int s, q;
+  bool valid;
+  unsigned site, halo;
+  int hoff[9];
+};
+
+// Lane l: tile row g = l >> 4, probe slot q = bit 3, column c = l & 7, so a
+// group of 16 lanes reads one tile row of both slots: 8 consecutive staged
+// records per slot, in disjoint banks (an LDS b128 read is served 16 lanes at
+// a time; two tile rows 10 records apart would share banks).
+__device__ __forceinline__ PairLane pair_geometry(const InstDev& I, int X0, int Y0, int lane) {
+  PairLane L;
+  L.q = (lane >> 3) & 1;
+  L.s = ((lane >> 4) << 3) | (lane & 7);
+  const int tx = L.s & (TX - 1), ty = L.s / TX;
+  const int x = X0 + tx, y = Y0 + ty;
+  L.valid = x < I.Lx && y < I.Ly;
+  const int xc = x < I.Lx ? x : I.Lx - 1, yc = y < I.Ly ? y : I.Ly - 1;
+  L.site = (unsigned)(yc * I.Lx + xc);
+  const int h = lane < HREC ? lane : 0;
+  int hx = X0 + (h % HX) - 1, hy = Y0 + (h / HX) - 1;
+  hx = ((hx % I.Lx) + I.Lx) % I.Lx;
+  hy = ((hy % I.Ly) + I.Ly) % I.Ly;
+  L.halo = (unsigned)(hy * I.Lx + hx);
+  const int c = (ty + 1) * HX + (tx + 1);
+  L.hoff[0] = c;
+  L.hoff[1] = c + 1;
+  L.hoff[2] = c + HX;
+  L.hoff[3] = c + HX + 1;
+  L.hoff[4] = c - HX + 1;
+  L.hoff[5] = c - 1;
+  L.hoff[6] = c - HX;
+  L.hoff[7] = c - HX - 1;
+  L.hoff[8] = c + HX - 1;
+  return L;
+}
+
+// Register coefficients of both rows of a site, scaled by 2 (records k:
+// 0 site, 1 +x, 2 +y, 3 +x+y, 4 +x-y, 5 -x, 6 -y, 7 -x-y, 8 -x+y).
+struct PairCoef {
+  float d0, d1;             // 2 H~_{(i0),(i0)}, 2 H~_{(i1),(i1)} (real)
+  Cx<float> nn[4][2][2];    // records 1, 2, 5, 6: [row][component]
+  Cx<float> dg[4][2];       // records 3, 4, 7, 8: (row 0, comp 0), (row 1, comp 1)
+};
+__device__ __forceinline__ constexpr int nn_rec(int j) { return j < 2 ? 1 + j : 3 + j; }   // 1 2 5 6
+__device__ __forceinline__ constexpr int dg_rec(int j) { return j < 2 ? 3 + j : 5 + j; }   // 3 4 7 8
+
+// LDS of a forward block: the tile's lane-ordered coefficient table (read
+// once per block, shared by its 4 waves) and each wave's double-buffered
+// staging of the two probes' halo records.
+struct PairStage {
+  F4 coef[9][64];                   // [record][lane 2 s + row] (row, comp 0 | comp 1), unscaled
+  F4 r[WAVES][2][2][PREC];          // [wave][buffer][slot][record]
+};
+
+__device__ __forceinline__ Cx<float> c2x(float re, float im, float f) { return Cx<float>{re * f, im * f}; }
+
+// acc += c * (real r)
+__device__ __forceinline__ void rfma(Cx<float>& acc, float c, float vx, float vy) {
+  acc.x = fmaf(c, vx, acc.x);
+  acc.y = fmaf(c, vy, acc.y);
+}
+
+// The coefficients outside the register set (FULL: the stencil has anomalous
+// on-site or next-nearest-neighbour entries), read from the staged table:
+// on-site (i0, i1) and (i1, i0), and per next-nearest record (row 0, comp 1)
+// and (row 1, comp 0).  Scaled by 2 here.
+template <bool FULL>
+__device__ __forceinline__ void pair_rows(Cx<float>& o0, Cx<float>& o1, const PairCoef& K,
+                                          const F4* lds, const PairLane& L, const F4 (*T)[64]) {
+  const F4 v0 = lds[L.hoff[0]];
+  rfma(o0, K.d0, v0.x, v0.y);
+  rfma(o1, K.d1, v0.z, v0.w);
+  if constexpr (FULL) {
+    const F4 t0 = T[0][2 * L.s], t1 = T[0][2 * L.s + 1];
+    cfma(o0, c2x(t0.z, t0.w, 2.f), Cx<float>{v0.z, v0.w});
+    cfma(o1, c2x(t1.x, t1.y, 2.f), Cx<float>{v0.x, v0.y});
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const F4 v = lds[L.hoff[nn_rec(j)]];
+    const Cx<float> a{v.x, v.y}, b{v.z, v.w};
+    cfma(o0, K.nn[j][0][0], a);
+    cfma(o0, K.nn[j][0][1], b);
+    cfma(o1, K.nn[j][1][0], a);
+    cfma(o1, K.nn[j][1][1], b);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const F4 v = lds[L.hoff[dg_rec(j)]];
+    const Cx<float> a{v.x, v.y}, b{v.z, v.w};
+    cfma(o0, K.dg[j][0], a);
+    cfma(o1, K.dg[j][1], b);
+    if constexpr (FULL) {
+      const F4 t0 = T[dg_rec(j)][2 * L.s], t1 = T[dg_rec(j)][2 * L.s + 1];
+      cfma(o0, c2x(t0.z, t0.w, 2.f), b);
+      cfma(o1, c2x(t1.x, t1.y, 2.f), a);
+    }
+  }
+}
+
+// Re(conj(r_a) o_a) summed over the two Nambu components of a lane, from
+// the probe's code byte (nibble a: 8 | k for the entry i^k, 0 for zero); FP64.
+__device__ __forceinline__ double code_dot(unsigned cb, float x0, float y0, float x1, float y1) {
+  const unsigned n0 = cb & 15u, n1 = (cb >> 4) & 15u;
+  float v0 = (n0 & 1u) ? y0 : x0;
+  v0 = (n0 & 2u) ? -v0 : v0;
+  float v1 = (n1 & 1u) ? y1 : x1;
+  v1 = (n1 & 2u) ? -v1 : v1;
+  const double t0 = (n0 & 8u) ? (double)v0 : 0.0;
+  const double t1 = (n1 & 8u) ? (double)v1 : 0.0;
+  return t0 + t1;
+}
+
+// Sum of v over the lanes of each probe slot (slot q: lanes with bit 3 = q)
+// flagged nz, in a fixed order: a slot with at most two such lanes reads them
+// directly (coloured and unit probes), else a butterfly over the slot's 32
+// lanes (lane distances 1, 2, 4, 16, 32).  s0, s1: the two slots' sums.
+__device__ __forceinline__ void slot_moments(double v, bool nz, double& s0, double& s1) {
+  const unsigned long long mask = __ballot(nz);
+  const unsigned long long m0 = mask & 0x00FF00FF00FF00FFull, m1 = mask & 0xFF00FF00FF00FF00ull;
+  double b0 = 0.0, b1 = 0.0;
+  if (__popcll(m0) > 2 || __popcll(m1) > 2) {
+    double t = nz ? v : 0.0;
+    t += __shfl_xor(t, 1, 64);
+    t += __shfl_xor(t, 2, 64);
+    t += __shfl_xor(t, 4, 64);
+    t += __shfl_xor(t, 16, 64);
+    t += __shfl_xor(t, 32, 64);
+    b0 = read_lane(t, 0);
+    b1 = read_lane(t, 8);
+  }
+  auto direct = [&](unsigned long long m, double b) {
+    if (__popcll(m) > 2) return b;
+    double r = 0.0;
+    if (m) {
+      r = read_lane(v, __ffsll((long long)m) - 1);
+      m &= m - 1ull;
+      if (m) r += read_lane(v, __ffsll((long long)m) - 1);
+    }
+    return r;
+  };
+  s0 = direct(m0, b0);
+  s1 = direct(m1, b1);
+}
+
+template <int PW, bool CK, bool FIRST>
+__device__ __forceinline__ void fwdp_body(const InstDev* __restrict__ insts,
+                                          const int4* __restrict__ tmap, Sched sc, int m,
+                                          int k_ckpt) {
+  static_assert(PW % 2 == 0, "two probes per wave step");
+  constexpr int NP = PW / 2;
+  __shared__ PairStage S;
+  int tile, range;
+  if (!block_work(sc, tile, range)) return;               // block-uniform
+  const int4 tm = tile_of(sc, tmap, tile);
+  const InstDev& I = insts[tm.x];
+  if (range * WAVES * PW >= I.R) return;                 // block-uniform
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int pbase = (range * WAVES + wave) * PW;
+  const bool has = pbase < I.R;                          // wave-uniform
+  const int N = I.N;
+  const PairLane L = pair_geometry(I, tm.y, tm.z, lane);
+  const void* cur = I.A[m & 1];
+  void* nxt = I.A[(m + 1) & 1];
+  const int pend = has ? min(pbase + PW, I.R) : I.R;
+  // ring of loads in flight; the first pair's loads are issued before the
+  // block stages its coefficient table, so the two latencies overlap
+  F4 h0[FPP], h1[FPP], pv[FPP];
+  unsigned cd[FPP];
+  auto issue_halo = [&](int j, int u) {
+    const int p0 = min(pbase + 2 * j, pend - 1), p1 = min(pbase + 2 * j + 1, pend - 1);
+    h0[u] = ldg_rec<float>(cur, (unsigned)(p0 * N) + L.halo);
+    h1[u] = ldg_rec<float>(cur, (unsigned)(p1 * N) + L.halo);
+  };
+  auto issue_prev = [&](int j, int u) {
+    const int p = min(pbase + 2 * j + L.q, pend - 1);
+    if constexpr (!FIRST) pv[u] = ldg_rec<float>(nxt, (unsigned)(p * N) + L.site);
+  };
+  auto issue_code = [&](int j, int u) {
+    const int p = min(pbase + 2 * j + L.q, pend - 1);
+    cd[u] = ldg_code(I, (unsigned)(p * N) + L.site);
+  };
+  if (has) {
+#pragma unroll
+    for (int j = 0; j < FPP && j < NP; ++j) {
+      issue_halo(j, j);
+      issue_prev(j, j);
+      issue_code(j, j);
+    }
+  }
+  // the tile's coefficient table, staged once for the block's waves
+  {
+    GPtr<F4> src = (GPtr<F4>)(I.coef) + (size_t)tm.w * 9 * 64;
+    for (int e = threadIdx.x; e < 9 * 64; e += kBlock) S.coef[e >> 6][e & 63] = src[e];
+  }
+  __syncthreads();
+  if (!has) return;                                      // wave-uniform; no barrier below
+  PairCoef K;
+  bool extra_nz;
+  {
+    const F4 s0 = S.coef[0][2 * L.s], s1 = S.coef[0][2 * L.s + 1];
+    K.d0 = 2.f * s0.x;
+    K.d1 = 2.f * s1.z;
+    bool nz = s0.z != 0.f || s0.w != 0.f || s1.x != 0.f || s1.y != 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const F4 r0 = S.coef[nn_rec(j)][2 * L.s], r1 = S.coef[nn_rec(j)][2 * L.s + 1];
+      K.nn[j][0][0] = c2x(r0.x, r0.y, 2.f);
+      K.nn[j][0][1] = c2x(r0.z, r0.w, 2.f);
+      K.nn[j][1][0] = c2x(r1.x, r1.y, 2.f);
+      K.nn[j][1][1] = c2x(r1.z, r1.w, 2.f);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const F4 r0 = S.coef[dg_rec(j)][2 * L.s], r1 = S.coef[dg_rec(j)][2 * L.s + 1];
+      K.dg[j][0] = c2x(r0.x, r0.y, 2.f);
+      K.dg[j][1] = c2x(r1.z, r1.w, 2.f);
+      nz = nz || r0.z != 0.f || r0.w != 0.f || r1.x != 0.f || r1.y != 0.f;
+    }
+    extra_nz = __any(nz);
+  }
+  const int mo = m + 1;
+  void* ckbuf = CK ? (void*)((char*)I.ckpt + ckpt_slot(mo, k_ckpt) * (long long)I.R * N * sizeof(F4))
+                   : nullptr;
+  GPtrW<double> mom = (GPtrW<double>)(I.mom) + ((long long)mo * I.nchunk + tm.w) * I.R;
+  const char* sink = (const char*)I.sink + (unsigned)lane * 16u;
+  double momv = 0.0;
+  auto step = [&](auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int u = j % FPP;
+      F4* buf = S.r[wave][j & 1][0];
+      if (lane < HREC) {
+        buf[lane] = h0[u];
+        buf[PREC + lane] = h1[u];
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (j + FPP < NP) issue_halo(j + FPP, u);
+      const int p = pbase + 2 * j + L.q;
+      const bool live = L.valid && p < pend;
+      Cx<float> o0{0.f, 0.f}, o1{0.f, 0.f};
+      if constexpr (!FIRST) {
+        o0 = Cx<float>{-pv[u].x, -pv[u].y};
+        o1 = Cx<float>{-pv[u].z, -pv[u].w};
+      }
+      if (j + FPP < NP) issue_prev(j + FPP, u);
+      pair_rows<FULL>(o0, o1, K, buf + L.q * PREC, L, S.coef);
+      if constexpr (FIRST) {
+        o0.x *= 0.5f; o0.y *= 0.5f; o1.x *= 0.5f; o1.y *= 0.5f;
+      }
+      const unsigned cb = live ? cd[u] : 0u;
+      if (j + FPP < NP) issue_code(j + FPP, u);
+      const size_t own = (size_t)((unsigned)(p < pend ? p : pend - 1) * (unsigned)N + L.site) * 16u;
+      F4 ov;
+      ov.x = o0.x; ov.y = o0.y; ov.z = o1.x; ov.w = o1.y;
+      *(GPtrW<F4>)store_addr(live, (const char*)nxt + own, sink) = ov;
+      if (CK) *(GPtrW<F4>)store_addr(live, (const char*)ckbuf + own, sink) = ov;
+      const double t = code_dot(cb, o0.x, o0.y, o1.x, o1.y);
+      double s0, s1;
+      slot_moments(t, (cb & 0x88u) != 0u, s0, s1);
+      if (lane == 2 * j) momv = s0;
+      if (lane == 2 * j + 1) momv = s1;
+      __builtin_amdgcn_wave_barrier();
+    }
+  };
+  if (extra_nz) step(std::true_type{});
+  else step(std::false_type{});
+  if (lane < pend - pbase) mom[pbase + lane] = momv;
+}
+
 // ------------------------------------------------------------- adjoint
 // gamma_{M-1} = 0, gamma_{M-2} = w C_{M-1} r; clears the dOmega/dH~ partials.
 template <typename V, int PW>
@@ -577,7 +898,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(const InstDev* __restrict__
                                                      int M) {
   int tile, range;
   if (!block_work(sc, tile, range)) return;               // block-uniform
-  const int4 tm = tmap[tile];
+  const int4 tm = tile_of(sc, tmap, tile);
   const InstDev& I = insts[tm.x];
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int pbase = (range * WAVES + wave) * PW;
@@ -714,7 +1035,7 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   } S;
   int tile, range;
   if (!block_work(sc, tile, range)) return;               // block-uniform
-  const int4 tm = tmap[tile];
+  const int4 tm = tile_of(sc, tmap, tile);
   const InstDev& I = insts[tm.x];
   if (range * WAVES * PW >= I.R) return;                 // block-uniform
   const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -799,6 +1120,12 @@ template <int PW> struct StepKernels<float, PW> {
            int k_ckpt) {
     fwd_body<float, PW, CK>(insts, tmap, sc, m, k_ckpt);
   }
+  template <bool CK, bool FIRST>
+  static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+  void fwdp(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
+            int k_ckpt) {
+    if constexpr (PW % 2 == 0) fwdp_body<PW, CK, FIRST>(insts, tmap, sc, m, k_ckpt);
+  }
   static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
   void fwd2(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
             int M) {
@@ -816,6 +1143,7 @@ template <int PW> struct StepKernels<float, PW> {
            int k_ckpt) {
     adj_body<float, PW, TAIL>(insts, tmap, sc, m, k_ckpt);
   }
+
 };
 template <int PW> struct StepKernels<double, PW> {
   template <bool CK>
@@ -1049,35 +1377,87 @@ __global__ __launch_bounds__(kBlock) void k_rho_direct(const InstDev* __restrict
 }
 
 // ------------------------------------------------------------- profiling
-// When enabled, one in `every` forward-step and adjoint-step launches carries
-// a pair of HIP events recorded by the dispatch itself (hipExtLaunchKernelGGL),
-// so kernel durations are sampled on the kernel's own stream without marker
-// packets between kernels.
+// When enabled, runs of kWindow consecutive launches of the plain forward step
+// (kind 1) or adjoint step (kind 3), one run starting every `every` launches of
+// that kind, are timed by a pair of HIP events recorded by the dispatches
+// themselves (hipExtLaunchKernelGGL): the start event by the run's first
+// launch, the stop event by its last.  No marker packet sits between kernels,
+// and the cost of the event signals is spread over the run.  A run is
+// abandoned (its slot is not counted) when any other launch of this library
+// comes before its last launch: another kernel, a step that is not the next
+// one, another stream.  Kernels launched outside these launchers (moment
+// reduction, copies) only follow a complete loop, whose runs have closed.
 namespace prof {
+constexpr int kWindow = 16;
 std::mutex mu;
 bool on = false;
-int every = 1;
-long long seen = 0;
+int every = kWindow;
+int window = kWindow;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
-std::vector<int> kind;      // 1 = forward step, 3 = adjoint step
+std::vector<int> kind;      // 1 = forward step, 3 = adjoint step, 0 = abandoned
 size_t used = 0;
+// the open run: its slot, kind, stream, next expected step and launches left
+struct Open {
+  bool on = false;
+  int kind = 0, next_m = 0, left = 0;
+  hipStream_t s = nullptr;
+  size_t slot = 0;
+} open;
 
-bool next(int k, hipEvent_t& a, hipEvent_t& b) {
+void abandon() {
+  if (open.on) kind[open.slot] = 0;
+  open.on = false;
+}
+
+// Events to attach to this launch (either may be null).  `k` is the launch's
+// kind (1, 3, or 0 for any other launch), m its step, M the moment count.
+void next(int k, int m, int M, hipStream_t s, hipEvent_t& a, hipEvent_t& b) {
+  a = b = nullptr;
   std::lock_guard<std::mutex> lk(mu);
-  if (!on) return false;
-  if ((seen++ % every) != 0) return false;
+  if (!on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    abandon();      // launches recorded into a graph are not timed
+    return;
+  }
+  if (open.on) {
+    if (k != open.kind || m != open.next_m || s != open.s) {
+      abandon();
+    } else {
+      if (--open.left == 0) {
+        b = pool[open.slot].second;
+        open.on = false;
+      } else {
+        open.next_m += k == 1 ? 1 : -1;
+      }
+      return;
+    }
+  }
+  // the forward loop runs m = 0 .. M-2 upwards, the adjoint m = M-3 .. 0 downwards
+  const int pos = k == 1 ? m : M - 3 - m;
+  const int last = k == 1 ? M - 2 : 0;
+  if (k == 0 || pos % every != 0) return;
+  if (k == 1 ? m + window - 1 > last : m - (window - 1) < last) return;
   if (used == pool.size()) {
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return false;
-    if (hipEventCreate(&e1) != hipSuccess) return false;
+    if (hipEventCreate(&e0) != hipSuccess) return;
+    if (hipEventCreate(&e1) != hipSuccess) return;
     pool.emplace_back(e0, e1);
     kind.push_back(0);
   }
   a = pool[used].first;
-  b = pool[used].second;
   kind[used] = k;
+  if (window == 1) {
+    b = pool[used].second;
+  } else {
+    open.on = true;
+    open.kind = k;
+    open.s = s;
+    open.slot = used;
+    open.left = window - 1;
+    open.next_m = k == 1 ? m + 1 : m - 1;
+  }
   ++used;
-  return true;
 }
 }  // namespace prof
 
@@ -1085,17 +1465,20 @@ hipError_t profile_begin(int every) {
   std::lock_guard<std::mutex> lk(prof::mu);
   prof::on = true;
   prof::every = every < 1 ? 1 : every;
-  prof::seen = 0;
+  prof::window = std::min(prof::kWindow, prof::every);
   prof::used = 0;
+  prof::open.on = false;
   return hipSuccess;
 }
 
 hipError_t profile_end(double* fwd_ms, int* nfwd, double* adj_ms, int* nadj) {
   std::lock_guard<std::mutex> lk(prof::mu);
   prof::on = false;
+  prof::abandon();
   double f = 0.0, a = 0.0;
   int nf = 0, na = 0;
   for (size_t q = 0; q < prof::used; ++q) {
+    if (prof::kind[q] == 0) continue;
     hipError_t e = hipEventSynchronize(prof::pool[q].second);
     if (e != hipSuccess) return e;
     float ms = 0.f;
@@ -1103,10 +1486,10 @@ hipError_t profile_end(double* fwd_ms, int* nfwd, double* adj_ms, int* nadj) {
     if (e != hipSuccess) return e;
     if (prof::kind[q] == 1) {
       f += ms;
-      ++nf;
-    } else if (prof::kind[q] == 3) {
+      nf += prof::window;
+    } else {
       a += ms;
-      ++na;
+      na += prof::window;
     }
   }
   prof::used = 0;
@@ -1118,18 +1501,38 @@ hipError_t profile_end(double* fwd_ms, int* nfwd, double* adj_ms, int* nadj) {
 }
 
 // ------------------------------------------------------------- launchers
+// Schedule of a launch: the forward step (which 0, 1, 4, 5) sweeps strips
+// (its coefficient table would otherwise be read by every XCD that holds a
+// probe range), the adjoint (2, 3) keeps probe ranges per XCD.
+static int g_sched_fwd = kSchedStrips, g_sched_adj = kSchedRanges;
+static int sched_mode(int which, int nranges, int ntiles) {
+  (void)ntiles;
+  const int m = (which == 2 || which == 3) ? g_sched_adj : g_sched_fwd;
+  if (m == kSchedRanges && 8 % nranges != 0) return kSchedTileMajor;
+  return m;
+}
+
 template <typename V, int PW>
 static hipError_t launch_all(int which, const InstDev* insts, const int4* tmap, int ntiles,
-                             int nranges, int m, int M, int k_ckpt, int flag, hipStream_t s) {
-  Sched sc{nranges, 0, ntiles};
+                             int tiles_x, int nranges, int m, int M, int k_ckpt, int flag,
+                             hipStream_t s) {
+  Sched sc{nranges, 0, ntiles, kSchedTileMajor, tiles_x};
   int nblocks = ntiles * nranges;
-  if (8 % nranges == 0) {
+  const int mode = sched_mode(which, nranges, ntiles);
+  if (mode == kSchedStrips) {
+    sc.mode = kSchedStrips;
+    sc.chunk = (ntiles + 7) / 8;
+    nblocks = 8 * sc.chunk * nranges;
+  } else if (mode == kSchedRanges && 8 % nranges == 0) {
+    sc.mode = kSchedRanges;
     sc.chunk = (ntiles + 8 / nranges - 1) / (8 / nranges);
     nblocks = 8 * sc.chunk;
   }
   dim3 grid(nblocks), block(kBlock);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  const bool timed = (which == 1 || (which == 3 && flag == 0)) && prof::next(which, e0, e1);
+  const int pk = which == 1 ? 1 : (which == 3 && flag == 0) ? 3 : 0;
+  prof::next(pk, m, M, s, e0, e1);
+  const bool timed = e0 != nullptr || e1 != nullptr;
   switch (which) {
     case 0:
       hipLaunchKernelGGL((k_init<V, PW>), grid, block, 0, s, insts, tmap, sc, k_ckpt, flag);
@@ -1138,6 +1541,13 @@ static hipError_t launch_all(int which, const InstDev* insts, const int4* tmap, 
       // this step stores alpha_{m+1} as a checkpoint
       const bool ck = flag && ((m + 1) % k_ckpt) <= 1;
       auto kern = ck ? StepKernels<V, PW>::template fwd<true> : StepKernels<V, PW>::template fwd<false>;
+      if constexpr (sizeof(V) == 4 && PW % 2 == 0) {
+        // FP32: two probes per wave step
+        if (m == 0)
+          kern = ck ? StepKernels<V, PW>::template fwdp<true, true> : StepKernels<V, PW>::template fwdp<false, true>;
+        else
+          kern = ck ? StepKernels<V, PW>::template fwdp<true, false> : StepKernels<V, PW>::template fwdp<false, false>;
+      }
       if (timed)
         hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, insts, tmap, sc, m, k_ckpt);
       else
@@ -1172,22 +1582,24 @@ static hipError_t launch_all(int which, const InstDev* insts, const int4* tmap, 
 
 template <typename V>
 static hipError_t launch_p(int PW, int which, const InstDev* insts, const int4* tmap, int ntiles,
-                           int nranges, int m, int M, int k_ckpt, int flag, hipStream_t s) {
+                           int tiles_x, int nranges, int m, int M, int k_ckpt, int flag, hipStream_t s) {
   switch (PW) {
-    case 1: return launch_all<V, 1>(which, insts, tmap, ntiles, nranges, m, M, k_ckpt, flag, s);
-    case 2: return launch_all<V, 2>(which, insts, tmap, ntiles, nranges, m, M, k_ckpt, flag, s);
-    case 4: return launch_all<V, 4>(which, insts, tmap, ntiles, nranges, m, M, k_ckpt, flag, s);
-    case 8: return launch_all<V, 8>(which, insts, tmap, ntiles, nranges, m, M, k_ckpt, flag, s);
-    case 16: return launch_all<V, 16>(which, insts, tmap, ntiles, nranges, m, M, k_ckpt, flag, s);
-    case 32: return launch_all<V, 32>(which, insts, tmap, ntiles, nranges, m, M, k_ckpt, flag, s);
+    case 1: return launch_all<V, 1>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 2: return launch_all<V, 2>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 4: return launch_all<V, 4>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 8: return launch_all<V, 8>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 16: return launch_all<V, 16>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 32: return launch_all<V, 32>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
     default: return hipErrorInvalidValue;
   }
 }
 
+// tiles_x > 0 for a single lattice (tiles_x tiles per row), 0 for a batch (tile table)
 hipError_t launch_cheb(bool fp32, int PW, int which, const InstDev* insts, const int4* tmap,
-                       int ntiles, int nranges, int m, int M, int k_ckpt, int flag, hipStream_t s) {
-  return fp32 ? launch_p<float>(PW, which, insts, tmap, ntiles, nranges, m, M, k_ckpt, flag, s)
-              : launch_p<double>(PW, which, insts, tmap, ntiles, nranges, m, M, k_ckpt, flag, s);
+                       int ntiles, int tiles_x, int nranges, int m, int M, int k_ckpt, int flag,
+                       hipStream_t s) {
+  return fp32 ? launch_p<float>(PW, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s)
+              : launch_p<double>(PW, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
 }
 
 hipError_t launch_mom_reduce(const InstDev* insts, int ninst, int maxRM, int M, double* mu_user,
