@@ -592,9 +592,9 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
 }
 
 // ------------------------------------------------------------- forward step, FP32 pairs
-// The FP32 forward step with two probes per wave step: lane l takes probe
-// slot q = l >> 5 of the step and tile site s = l & 31, and applies both Nambu
-// rows of its site.  Per (site, probe) this halves the LDS reads (the 9 staged
+// The FP32 forward step with two probes per wave step: each lane takes one
+// probe slot q of the step and one tile site s (pair_geometry), and applies
+// both Nambu rows of its site.  Per (site, probe) this halves the LDS reads (the 9 staged
 // records serve both rows) and the global loads and stores (one 16 B record
 // instead of two 8 B components), against one row per lane.
 //
