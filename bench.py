@@ -217,6 +217,7 @@ def batched_form(steps: int):
         rhos = [torch.zeros_like(h) for h in hs]
         kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=True)   # tune + capture
         torch.cuda.synchronize()
+        tune = kpm.kpm_batch_tuning(plan)
         t0 = time.perf_counter()
         for _ in range(steps):
             kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=True)
@@ -224,8 +225,23 @@ def batched_form(steps: int):
         dt32 = (time.perf_counter() - t0) / steps
         om32 = omega.cpu().numpy()
         r32 = [r.cpu().numpy() for r in rhos]
+        # kernel durations: the same sequence launched directly (a graph replay
+        # cannot carry the library's timing events), same kernels and configuration
+        kpm.kpm_profile_begin(32)
+        t0 = time.perf_counter()
+        for _ in range(2):
+            kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=False)
+        torch.cuda.synchronize()
+        dt_direct = (time.perf_counter() - t0) / 2
+        fwd_ms, n_fwd, adj_ms, n_adj = kpm.kpm_profile_end()
     finally:
         kpm.kpm_batch_destroy(plan)
+    RN = sum(q.R * c.N for q, c in zip(probs, cfgs))
+    NS = sum(c.N for c in cfgs)
+    fwd_bytes = 3 * 16 * RN + 288 * NS
+    adj_bytes = 6 * 16 * RN + 288 * NS
+    fwd_s = fwd_ms / max(n_fwd, 1) * 1e-3
+    adj_s = adj_ms / max(n_adj, 1) * 1e-3
     log(f"batched FP32: {dt32 * 1e3:.1f} ms per energy + gradient of 48 lattices")
     p64 = []
     for cfg in cfgs:
@@ -261,6 +277,23 @@ def batched_form(steps: int):
         "vector_steps_per_s_fp32_batched": vsteps / dt32,
         "fp32_vs_fp64_max_rel_err_omega": e_om,
         "fp32_vs_fp64_max_rel_err_rho": e_rho,
+        "ms_per_step_fp32_batched_direct_launches": dt_direct * 1e3,
+        "tuning": tune,
+        "roofline": {
+            "kernel": "k_adj (fused adjoint step, all 48 lattices per launch)",
+            "bound": "hbm",
+            "achieved": adj_bytes / adj_s / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": adj_bytes / adj_s / 1e9 / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": adj_bytes,
+            "avg_launch_us": adj_s * 1e6,
+            "launches_timed": n_adj,
+        },
+        "forward_kernel": {"algorithmic_bytes_per_launch": fwd_bytes, "avg_launch_us": fwd_s * 1e6,
+                           "achieved_GBs": fwd_bytes / fwd_s / 1e9, "launches_timed": n_fwd},
+        "hbm_GBs_algorithmic_whole_step": ((M - 1) * fwd_bytes + (M - 2) * adj_bytes) / dt32 / 1e9,
     }
 
 
@@ -690,6 +723,8 @@ def main():
     ap.add_argument("--no-supercell-form", action="store_true")
     ap.add_argument("--only-supercell-form", action="store_true",
                     help="run only the magnetic super-cell ED form and print its JSON")
+    ap.add_argument("--only-batched-form", action="store_true",
+                    help="run only the 48-lattice batched form and print its record")
     ap.add_argument("--only-rmft-form", action="store_true",
                     help="run only the self-consistent iteration timing and print its JSON (profiling)")
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -730,6 +765,9 @@ def main():
     if args.probe_block:
         from paper_2212_05685_amd import kpm
         kpm.kpm_set_probe_block(args.probe_block)
+    if args.only_batched_form:
+        print(json.dumps({"batched_form": batched_form(args.steps)}), flush=True)
+        return
     if args.only_rmft_form:
         print(json.dumps({"rmft_form": rmft_form(args.steps, args.warmup)}), flush=True)
         return

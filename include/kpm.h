@@ -328,9 +328,17 @@ int kpm_status_read(const void* ws, int32_t* status, void* stream);
 
 /* Create a plan for n_inst lattices of possibly different size, vortex count
  * and probes, all with the same M, precision and checkpoint interval.  The
- * plan owns its device memory and chooses the probes-per-thread blocking of
- * the recursion kernels by timing candidates on first use (autotune),
- * remembered per shape in the process.  lats/probes: host arrays [n_inst]. */
+ * plan owns its device memory.  On first use it chooses the probes-per-thread
+ * blocking and the block schedule of the forward and of the adjoint kernel by
+ * timing every pair (autotune), unless kpm_set_probe_block fixed the block.
+ * Picks are remembered per shape (device, M, precision, checkpoint interval,
+ * every instance's N and R) in the process and in a text file: the path in
+ * the environment variable KPM_TUNE_CACHE, else $XDG_CACHE_HOME/kpm_tune.txt,
+ * else $HOME/.cache/kpm_tune.txt.  Each line of that file is
+ * "<key> <Pf> <Sf> <Pa> <Sa>", with <key> =
+ * "<arch>:<compute units>:M<M>:<f|d>:k<ckpt_k>:<N_0>x<R_0>,<N_1>x<R_1>,...";
+ * the last valid line of a key is used, and a file that cannot be read or
+ * written only disables the disk cache.  lats/probes: host arrays [n_inst]. */
 int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* probes,
                      int32_t M, int32_t precision, int32_t ckpt_k, void** plan);
 
@@ -346,9 +354,42 @@ int kpm_batch_energy_grad(void* plan, const double* const* h, const double* cons
 
 int kpm_batch_destroy(void* plan);
 
+/* The plan's kernel configuration (host int32_t out[5]): forward probe block,
+ * forward schedule, adjoint probe block, adjoint schedule, and where they
+ * came from: 0 timed by this plan, 1 this process's cache, 2 the disk cache,
+ * -1 not tuned (fixed by kpm_set_probe_block / kpm_set_schedule, or the plan
+ * has not run yet).  Schedules are KPM_SCHED_* values. */
+int kpm_batch_tuning(const void* plan, int32_t* out);
+
 /* Probes-per-thread blocking used by the single-lattice calls (0 = automatic,
- * else one of 1, 2, 4, 8, 16, 32).  Process-wide; returns the previous value. */
+ * else one of 1, 2, 4, 8, 16, 32).  Process-wide; returns the previous value.
+ * Batch plans created while it is nonzero use it too, and are not tuned.
+ * Automatic: the configuration remembered for the call's shape (see
+ * kpm_batch_create for the process and file caches); a shape not seen yet is
+ * tuned by its first kpm_grand_potential (or kpm_density_matrix) call, on
+ * that call's workspace, unless the stream is being captured; until then a
+ * size heuristic picks the blocks. */
 int32_t kpm_set_probe_block(int32_t probes_per_thread);
+
+/* Block schedules of the recursion kernels (how (tile, probe range) work
+ * items map to blocks, and so to the 8 XCDs that blocks are dealt to in
+ * turn): KPM_SCHED_TILE_MAJOR, tiles in order with the probe range fastest;
+ * KPM_SCHED_RANGES, each XCD one probe range on its share of contiguous tiles
+ * (when the range count divides 8, else tile-major); KPM_SCHED_STRIPS, each
+ * XCD one eighth of the tiles, range after range.  KPM_SCHED_DEFAULT is
+ * strips for the forward steps and ranges for the adjoint. */
+#define KPM_SCHED_DEFAULT (-1)
+#define KPM_SCHED_TILE_MAJOR 0
+#define KPM_SCHED_RANGES 1
+#define KPM_SCHED_STRIPS 2
+
+/* Schedules used, while the probe block is fixed (kpm_set_probe_block
+ * nonzero), by the single-lattice calls and the batch plans created then;
+ * with the automatic block the tuned schedules apply.  Process-wide.
+ * Returns KPM_EINVAL (nothing changed) for a value outside -1..2.  The
+ * results do not depend on the schedule, up to the order of FP64 sums of the
+ * adjoint partial sums. */
+int kpm_set_schedule(int32_t fwd, int32_t adj);
 
 /* ---- self-consistent iteration (RMFT outer loop) ---------------------------
  * Model and methods: the local order parameters that define h (eqs. delta,

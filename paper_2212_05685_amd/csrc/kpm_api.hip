@@ -3,13 +3,18 @@
 // probes-per-thread autotuner.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <tuple>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "../../include/kpm.h"
 #include "kpm_internal.h"
@@ -27,7 +32,7 @@ hipError_t launch_build_sdw_vjp(const ModelDev&, const double*, const double*, c
 hipError_t launch_bounds(int, int, const double*, double*, hipStream_t);
 hipError_t launch_rescale(const InstDev*, const int4*, int, bool, hipStream_t);
 hipError_t launch_coeffs(int, int, double, const double*, double*, hipStream_t);
-hipError_t launch_cheb(bool, int, int, const InstDev*, const int4*, int, int, int, int, int, int,
+hipError_t launch_cheb(bool, int, int, int, const InstDev*, const int4*, int, int, int, int, int, int,
                        int, hipStream_t);
 hipError_t launch_mom_reduce(const InstDev*, int, int, int, double*, hipStream_t);
 hipError_t launch_omega(const InstDev*, int, int, hipStream_t);
@@ -161,6 +166,7 @@ int auto_probe_adj(long long tiles_total, int Rmax) {
 
 std::mutex g_mu;
 int g_probe_block = 0;   // 0 = automatic
+int g_sched_f = KPM_SCHED_DEFAULT, g_sched_a = KPM_SCHED_DEFAULT;   // single-lattice schedules
 
 // ------------------------------------------------------------ instance layout
 struct Sizes {
@@ -233,6 +239,8 @@ struct Ctx {
   int M = 0, k = 0;
   bool fp32 = false;
   int Pf = 1, Pa = 1;         // probes per wave, forward and adjoint kernels
+  int Sf = -1, Sa = -1;       // block schedules (KPM_SCHED_*), -1 = the kernel's default
+  bool want_tune = false;     // single lattice, automatic block, shape not tuned yet
   int Rmax = 0;
   long long sites = 0;
   int nrf() const { return (Rmax + kWaves * Pf - 1) / (kWaves * Pf); }
@@ -336,10 +344,10 @@ int run_forward(const Ctx& c, bool ckpt, int nsteps, hipStream_t s) {
   hipLaunchKernelGGL(k_set_status, dim3((ninst + 63) / 64), dim3(64), 0, s, c.d_inst, ninst, 0);
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, c.M, c.k,
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, c.M, c.k,
                       ckpt ? 1 : 0, s));
   for (int m = 0; m + 1 < nsteps; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, c.M, c.k,
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, c.M, c.k,
                         ckpt ? 1 : 0, s));
   return KPM_OK;
 }
@@ -353,10 +361,10 @@ int run_moments(const Ctx& c, double* mu_user, hipStream_t s) {
 
 int run_adjoint(const Ctx& c, hipStream_t s) {
   const int M = c.M;
-  KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 2, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, M, c.k, 0, s));
   for (int m = M - 3; m >= 0; --m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), m, M, c.k, 0, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, M, c.k, 1, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), m, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, M, c.k, 1, s));
   KPM_HIP(launch_rho(c.d_inst, c.d_cmap, c.nch(), s));
   return KPM_OK;
 }
@@ -402,9 +410,206 @@ int restore_alpha(const Ctx& c, hipStream_t s) {
   KPM_HIP(hipMemcpyAsync(I.A[j0 & 1], ck + slot * vec, vec, hipMemcpyDeviceToDevice, s));
   KPM_HIP(hipMemcpyAsync(I.A[(j0 + 1) & 1], ck + (slot + 1) * vec, vec, hipMemcpyDeviceToDevice, s));
   for (int m = j0 + 1; m + 1 < M; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, k, 0, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, k, 0, s));
   return KPM_OK;
 }
+
+// ---- autotuner: probe block and block schedule of each recursion kernel
+struct Tune {
+  int Pf, Sf, Pa, Sa;
+};
+std::map<std::string, Tune> g_tune_cache;   // this process's picks, by shape key
+
+// Shape key: device (architecture, compute units), M, precision, checkpoint
+// interval and every instance's N and R, in plan order.
+std::string device_tag() {
+  static std::mutex mu;
+  static std::map<int, std::string> tags;   // device ordinal -> "<arch>:<compute units>"
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "dev:0";
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = tags.find(dev);
+  if (it != tags.end()) return it->second;
+  hipDeviceProp_t prop{};
+  std::string arch = "dev";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  return tags[dev] = arch + ":" + std::to_string(cus);
+}
+
+std::string shape_key(const Ctx& c) {
+  std::string key = device_tag() + ":M" + std::to_string(c.M) + (c.fp32 ? ":f" : ":d") + ":k" +
+                    std::to_string(c.k);
+  for (size_t q = 0; q < c.inst.size(); ++q)
+    key += (q ? "," : ":") + std::to_string(c.inst[q].N) + "x" + std::to_string(c.inst[q].R);
+  return key;
+}
+
+// On-disk cache: the file named by KPM_TUNE_CACHE, else
+// $XDG_CACHE_HOME/kpm_tune.txt, else $HOME/.cache/kpm_tune.txt.  One line per
+// shape: "<key> <Pf> <Sf> <Pa> <Sa>"; the last line of a key wins; lines that
+// do not parse, or hold values the launchers do not take, are ignored.
+std::string tune_path() {
+  if (const char* e = std::getenv("KPM_TUNE_CACHE")) return e;
+  if (const char* x = std::getenv("XDG_CACHE_HOME")) return std::string(x) + "/kpm_tune.txt";
+  if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/kpm_tune.txt";
+  return "";
+}
+
+bool valid_tune(const Tune& t) {
+  auto okP = [](int P) { return P == 1 || P == 2 || P == 4 || P == 8 || P == 16 || P == 32; };
+  auto okS = [](int S) { return S >= 0 && S <= 2; };
+  return okP(t.Pf) && okP(t.Pa) && okS(t.Sf) && okS(t.Sa);
+}
+
+bool disk_lookup(const std::string& key, Tune& out) {
+  const std::string path = tune_path();
+  if (path.empty()) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  bool found = false;
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream ls(line);
+    std::string k;
+    Tune t{};
+    if (!(ls >> k >> t.Pf >> t.Sf >> t.Pa >> t.Sa)) continue;
+    if (k == key && valid_tune(t)) {
+      out = t;
+      found = true;
+    }
+  }
+  return found;
+}
+
+void disk_store(const std::string& key, const Tune& t) {
+  const std::string path = tune_path();
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << ' ' << t.Pf << ' ' << t.Sf << ' ' << t.Pa << ' ' << t.Sa << '\n';
+}
+
+// Picks for this shape from the process cache, else from the file (then
+// remembered in the process); *source = 1 or 2.
+bool tune_lookup(const std::string& key, Tune& t, int* source) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      t = it->second;
+      *source = 1;
+      return true;
+    }
+  }
+  if (!disk_lookup(key, t)) return false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tune_cache[key] = t;
+  *source = 2;
+  return true;
+}
+
+void apply_tune(Ctx& c, const Tune& t) {
+  c.Pf = t.Pf;
+  c.Sf = t.Sf;
+  c.Pa = t.Pa;
+  c.Sa = t.Sa;
+  set_npb(c);
+}
+
+// Times a few forward steps and a few adjoint steps for each candidate
+// (probe block, schedule) and keeps the fastest of each kernel.  The forward
+// runs on the probes (the adjoint after it, on the alpha just computed, with
+// gamma and the partial sums from k_adj_init), so no step reads uninitialised
+// data.  KPM_TUNE_VERBOSE=1 prints every timing on stderr.
+// single_ws: the workspace of a single-lattice call (its tables are uploaded
+// through the per-workspace host store), or null for a plan.
+int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
+  const std::string key = shape_key(c);
+  Tune t{};
+  auto put = [&](Ctx& cc) { return single_ws ? upload_single(cc, single_ws, s) : upload(cc, s); };
+  if (tune_lookup(key, t, source)) {
+    apply_tune(c, t);
+    return put(c);
+  }
+  const bool verbose = std::getenv("KPM_TUNE_VERBOSE") != nullptr;
+  hipEvent_t e0, e1;
+  KPM_HIP(hipEventCreate(&e0));
+  KPM_HIP(hipEventCreate(&e1));
+  const int steps = std::min(c.M, 8);
+  float best_f = 1e30f, best_a = 1e30f;
+  Tune best{1, -1, 1, -1};
+  int st = KPM_OK;
+  for (int P : {1, 2, 4, 8, 16, 32}) {
+    for (int S : {KPM_SCHED_TILE_MAJOR, KPM_SCHED_RANGES, KPM_SCHED_STRIPS}) {
+      c.Pf = c.Pa = P;
+      c.Sf = c.Sa = S;
+      set_npb(c);
+      if ((st = put(c)) != KPM_OK) break;
+      // forward: warm once, then time
+      for (int rep = 0; rep < 2; ++rep) {
+        KPM_HIP(hipEventRecord(e0, s));
+        if ((st = run_forward(c, true, steps, s)) != KPM_OK) break;
+        KPM_HIP(hipEventRecord(e1, s));
+      }
+      if (st != KPM_OK) break;
+      KPM_HIP(hipEventSynchronize(e1));
+      float tf = 0.f;
+      KPM_HIP(hipEventElapsedTime(&tf, e0, e1));
+      if (tf < best_f) {
+        best_f = tf;
+        best.Pf = P;
+        best.Sf = S;
+      }
+      float ta = 0.f;
+      if (c.M >= 3) {
+        // adjoint steps at m = M-3 (timing only) on initialised data: alpha from the
+        // forward steps just timed (with checkpoint stores, so an anchored step at
+        // small M reads written slots), gamma and the partial sums from k_adj_init
+        KPM_HIP(hipEventRecord(e0, s));
+        KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 2, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, c.M,
+                            c.k, 0, s));
+        for (int q = 0; q < steps; ++q)
+          KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(),
+                              c.M - 3, c.M, c.M + 1, 0, s));
+        KPM_HIP(hipEventRecord(e1, s));
+        KPM_HIP(hipEventSynchronize(e1));
+        KPM_HIP(hipEventElapsedTime(&ta, e0, e1));
+        if (ta < best_a) {
+          best_a = ta;
+          best.Pa = P;
+          best.Sa = S;
+        }
+      }
+      if (verbose)
+        std::fprintf(stderr, "[kpm tune] %s P=%d sched=%d forward %.1f us/step adjoint %.1f us/step\n",
+                     key.c_str(), P, S, 1e3f * tf / steps, 1e3f * ta / steps);
+    }
+    if (st != KPM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != KPM_OK) return st;
+  if (c.M < 3) {
+    best.Pa = best.Pf;
+    best.Sa = best.Sf;
+  }
+  apply_tune(c, best);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune_cache[key] = best;
+  }
+  disk_store(key, best);
+  *source = 0;
+  return put(c);
+}
+
 
 int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* ab,
                    const kpm_probes* pr, int M, const double* C, int prec, int k, void* ws,
@@ -444,11 +649,38 @@ int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* 
   {
     std::lock_guard<std::mutex> lk(g_mu);
     P = g_probe_block;
+    c.Sf = g_sched_f;
+    c.Sa = g_sched_a;
   }
   c.Pf = P ? P : auto_probe_fwd(c.ntl(), c.Rmax);
   c.Pa = P ? P : auto_probe_adj(c.ntl(), c.Rmax);
   set_npb(c);
+  if (P == 0) {
+    Tune t{};
+    int src = 0;
+    if (tune_lookup(shape_key(c), t, &src)) apply_tune(c, t);
+    else c.want_tune = !fwd_only;
+  }
   return KPM_OK;
+}
+
+// First forward of a shape with the automatic probe block: time the
+// candidates on this call's workspace (whose state the forward then rebuilds;
+// a forward kept for a later gradient is forgotten first).  Not while the
+// stream is being captured: the timing synchronises.
+int tune_single(Ctx& c, const void* ws, hipStream_t s) {
+  if (!c.want_tune) return KPM_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  KPM_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return KPM_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_fwd.erase(ws);
+  }
+  int src = 0;
+  int st = tune_ctx(c, ws, s, &src);
+  c.want_tune = false;
+  return st;
 }
 
 }  // namespace
@@ -459,93 +691,13 @@ struct KpmBatchPlan {
   void* mem = nullptr;
   hipStream_t capture_stream = nullptr;   // graphs are captured here, launched on the caller's
   bool tuned = false;
+  int tune_source = -1;                 // 0 timed, 1 process cache, 2 disk cache, -1 fixed
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   std::vector<const void*> graph_ptrs;   // pointers the captured graph was built with
 };
 
 namespace {
-
-std::map<std::string, std::pair<int, int>> g_tune_cache;
-
-std::string shape_key(const Ctx& c) {
-  std::string key = std::to_string(c.M) + (c.fp32 ? "f" : "d");
-  for (auto& I : c.inst) key += ":" + std::to_string(I.N) + "x" + std::to_string(I.R);
-  return key;
-}
-
-// Times a few forward steps and a few adjoint steps for each candidate block.
-int autotune(KpmBatchPlan* pl, hipStream_t s) {
-  Ctx& c = pl->c;
-  const std::string key = shape_key(c);
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      c.Pf = it->second.first;
-      c.Pa = it->second.second;
-      set_npb(c);
-      pl->tuned = true;
-      return upload(c, s);
-    }
-  }
-  hipEvent_t e0, e1;
-  KPM_HIP(hipEventCreate(&e0));
-  KPM_HIP(hipEventCreate(&e1));
-  const int steps = std::min(c.M, 8);
-  float best_f = 1e30f, best_a = 1e30f;
-  int Pf = 1, Pa = 1;
-  for (int P : {1, 2, 4, 8, 16, 32}) {
-    c.Pf = P;
-    c.Pa = P;
-    set_npb(c);
-    int st = upload(c, s);
-    if (st != KPM_OK) return st;
-    // forward: warm once, then time
-    for (int rep = 0; rep < 2; ++rep) {
-      KPM_HIP(hipEventRecord(e0, s));
-      st = run_forward(c, true, steps, s);
-      if (st != KPM_OK) return st;
-      KPM_HIP(hipEventRecord(e1, s));
-    }
-    KPM_HIP(hipEventSynchronize(e1));
-    float tf = 0.f;
-    KPM_HIP(hipEventElapsedTime(&tf, e0, e1));
-    if (tf < best_f) {
-      best_f = tf;
-      Pf = P;
-    }
-    if (c.M >= 3) {
-      // adjoint steps at m = M-3 (timing only) on initialised data: alpha from the
-      // forward steps just timed (with checkpoint stores, so an anchored step at
-      // small M reads written slots), gamma and the partial sums from k_adj_init
-      KPM_HIP(hipEventRecord(e0, s));
-      KPM_HIP(launch_cheb(c.fp32, c.Pa, 2, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, c.M, c.k, 0, s));
-      for (int q = 0; q < steps; ++q)
-        KPM_HIP(launch_cheb(c.fp32, c.Pa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), c.M - 3, c.M,
-                            c.M + 1, 0, s));
-      KPM_HIP(hipEventRecord(e1, s));
-      KPM_HIP(hipEventSynchronize(e1));
-      float ta = 0.f;
-      KPM_HIP(hipEventElapsedTime(&ta, e0, e1));
-      if (ta < best_a) {
-        best_a = ta;
-        Pa = P;
-      }
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  c.Pf = Pf;
-  c.Pa = Pa;
-  set_npb(c);
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_tune_cache[key] = {Pf, Pa};
-  }
-  pl->tuned = true;
-  return upload(c, s);
-}
 
 int batch_sequence(KpmBatchPlan* pl, hipStream_t s) {
   Ctx& c = pl->c;
@@ -734,6 +886,7 @@ int kpm_grand_potential(const kpm_lattice* lat, const double* h, const double* a
   c.inst[0].omega = omega;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+  if ((st = tune_single(c, ws, s)) != KPM_OK) return st;
   if ((st = run_forward(c, true, M, s)) != KPM_OK) return st;
   if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
   KPM_HIP(launch_omega(c.d_inst, 1, M, s));
@@ -813,10 +966,10 @@ int kpm_density_matrix_direct(const kpm_lattice* lat, const double* h, const dou
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
   KPM_HIP(launch_direct_coef(c.d_inst, 1, M, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, s));
   // step m writes alpha_{m+1}; even steps also add D_m alpha_m + D_{m+1} alpha_{m+1} to y
   for (int m = 0; m + 1 < M; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, (m & 1) ? 1 : 5, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M,
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, (m & 1) ? 1 : 5, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M,
                         c.k, m == 0 ? 1 : 0, s));
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_omega(c.d_inst, 1, M, s));
@@ -842,10 +995,10 @@ int kpm_moments_doubling(const kpm_lattice* lat, const double* h, const double* 
   hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, c.d_inst, 1, 0);
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, s));
   // alpha_1 .. alpha_{M/2}: every moment slot below M is then written
   for (int m = 0; m < M / 2; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, 4, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, c.k, 0, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 4, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, c.k, 0, s));
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_mom_double(c.d_inst, 1, c.inst[0].R * M, M, mu, s));
   if (omega) KPM_HIP(launch_omega(c.d_inst, 1, M, s));
@@ -903,6 +1056,26 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread) {
   return old;
 }
 
+int kpm_set_schedule(int32_t fwd, int32_t adj) {
+  auto ok = [](int32_t v) { return v >= KPM_SCHED_DEFAULT && v <= KPM_SCHED_STRIPS; };
+  if (!ok(fwd) || !ok(adj)) return KPM_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_sched_f = fwd;
+  g_sched_a = adj;
+  return KPM_OK;
+}
+
+int kpm_batch_tuning(const void* plan, int32_t* out) {
+  if (!plan || !out) return KPM_EINVAL;
+  const KpmBatchPlan* pl = static_cast<const KpmBatchPlan*>(plan);
+  out[0] = pl->c.Pf;
+  out[1] = pl->c.Sf;
+  out[2] = pl->c.Pa;
+  out[3] = pl->c.Sa;
+  out[4] = pl->tune_source;
+  return KPM_OK;
+}
+
 int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* probes, int32_t M,
                      int32_t precision, int32_t ckpt_k, void** plan) {
   if (n_inst < 1 || !lats || !probes || !plan || M < 2 || ckpt_k < 2) return KPM_EINVAL;
@@ -956,6 +1129,8 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
   {
     std::lock_guard<std::mutex> lk(g_mu);
     P = g_probe_block;
+    pl->c.Sf = g_sched_f;
+    pl->c.Sa = g_sched_a;
   }
   pl->c.Pf = P ? P : auto_probe_fwd(pl->c.ntl(), pl->c.Rmax);
   pl->c.Pa = P ? P : auto_probe_adj(pl->c.ntl(), pl->c.Rmax);
@@ -987,7 +1162,8 @@ int kpm_batch_energy_grad(void* plan, const double* const* h, const double* cons
   int st;
   if (!pl->tuned) {
     if ((st = upload(c, s)) != KPM_OK) return st;
-    if ((st = autotune(pl, s)) != KPM_OK) return st;
+    if ((st = tune_ctx(pl->c, nullptr, s, &pl->tune_source)) != KPM_OK) return st;
+    pl->tuned = true;
   }
   if ((st = upload(c, s)) != KPM_OK) return st;
   if (!use_graph) return batch_sequence(pl, s);

@@ -1504,21 +1504,22 @@ hipError_t profile_end(double* fwd_ms, int* nfwd, double* adj_ms, int* nadj) {
 // Schedule of a launch: the forward step (which 0, 1, 4, 5) sweeps strips
 // (its coefficient table would otherwise be read by every XCD that holds a
 // probe range), the adjoint (2, 3) keeps probe ranges per XCD.
-static int g_sched_fwd = kSchedStrips, g_sched_adj = kSchedRanges;
-static int sched_mode(int which, int nranges, int ntiles) {
-  (void)ntiles;
-  const int m = (which == 2 || which == 3) ? g_sched_adj : g_sched_fwd;
+// A requested schedule (0 tile-major, 1 ranges, 2 strips) overrides the
+// default; ranges needs a range count that divides 8, else tile-major runs.
+static int sched_mode(int which, int nranges, int req) {
+  int m = (which == 2 || which == 3) ? kSchedRanges : kSchedStrips;
+  if (req >= kSchedTileMajor && req <= kSchedStrips) m = req;
   if (m == kSchedRanges && 8 % nranges != 0) return kSchedTileMajor;
   return m;
 }
 
 template <typename V, int PW>
-static hipError_t launch_all(int which, const InstDev* insts, const int4* tmap, int ntiles,
-                             int tiles_x, int nranges, int m, int M, int k_ckpt, int flag,
-                             hipStream_t s) {
+static hipError_t launch_all(int sched, int which, const InstDev* insts, const int4* tmap,
+                             int ntiles, int tiles_x, int nranges, int m, int M, int k_ckpt,
+                             int flag, hipStream_t s) {
   Sched sc{nranges, 0, ntiles, kSchedTileMajor, tiles_x};
   int nblocks = ntiles * nranges;
-  const int mode = sched_mode(which, nranges, ntiles);
+  const int mode = sched_mode(which, nranges, sched);
   if (mode == kSchedStrips) {
     sc.mode = kSchedStrips;
     sc.chunk = (ntiles + 7) / 8;
@@ -1581,25 +1582,28 @@ static hipError_t launch_all(int which, const InstDev* insts, const int4* tmap, 
 }
 
 template <typename V>
-static hipError_t launch_p(int PW, int which, const InstDev* insts, const int4* tmap, int ntiles,
-                           int tiles_x, int nranges, int m, int M, int k_ckpt, int flag, hipStream_t s) {
+static hipError_t launch_p(int PW, int sched, int which, const InstDev* insts, const int4* tmap,
+                           int ntiles, int tiles_x, int nranges, int m, int M, int k_ckpt, int flag,
+                           hipStream_t s) {
   switch (PW) {
-    case 1: return launch_all<V, 1>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 2: return launch_all<V, 2>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 4: return launch_all<V, 4>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 8: return launch_all<V, 8>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 16: return launch_all<V, 16>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 32: return launch_all<V, 32>(which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 1: return launch_all<V, 1>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 2: return launch_all<V, 2>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 4: return launch_all<V, 4>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 8: return launch_all<V, 8>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 16: return launch_all<V, 16>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 32: return launch_all<V, 32>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 // tiles_x > 0 for a single lattice (tiles_x tiles per row), 0 for a batch (tile table)
-hipError_t launch_cheb(bool fp32, int PW, int which, const InstDev* insts, const int4* tmap,
-                       int ntiles, int tiles_x, int nranges, int m, int M, int k_ckpt, int flag,
-                       hipStream_t s) {
-  return fp32 ? launch_p<float>(PW, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s)
-              : launch_p<double>(PW, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+hipError_t launch_cheb(bool fp32, int PW, int sched, int which, const InstDev* insts,
+                       const int4* tmap, int ntiles, int tiles_x, int nranges, int m, int M,
+                       int k_ckpt, int flag, hipStream_t s) {
+  return fp32 ? launch_p<float>(PW, sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt,
+                                flag, s)
+              : launch_p<double>(PW, sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt,
+                                 flag, s);
 }
 
 hipError_t launch_mom_reduce(const InstDev* insts, int ninst, int maxRM, int M, double* mu_user,

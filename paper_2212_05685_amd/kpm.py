@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libkpm.so")
 KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_EBOUNDS, KPM_ENOTSUP, KPM_EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
 KPM_ENOCONV = -7
 KPM_ETOOBIG = -8
+KPM_SCHED_DEFAULT, KPM_SCHED_TILE_MAJOR, KPM_SCHED_RANGES, KPM_SCHED_STRIPS = -1, 0, 1, 2
 KPM_NOALLOC_SCRATCH_BYTES = 64 << 20
 KPM_RMFT_STATS_LEN = 520
 KPM_RMFT_BISECTION, KPM_RMFT_ILLINOIS = 0, 1
@@ -41,7 +42,7 @@ EXPORTS = (
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
     "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
     "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_build_H_sdw_vjp", "kpm_bloch_H", "kpm_gutzwiller_weights", "kpm_supercell_workspace_size",
-    "kpm_supercell_ldos", "kpm_moments_noalloc",
+    "kpm_supercell_ldos", "kpm_moments_noalloc", "kpm_set_schedule", "kpm_batch_tuning",
 )
 
 
@@ -117,6 +118,8 @@ def _load():
                                             P, POINTER(c_void_p), c_int32, P]),
         "kpm_batch_destroy": (c_int32, [P]),
         "kpm_set_probe_block": (c_int32, [c_int32]),
+        "kpm_set_schedule": (c_int32, [c_int32, c_int32]),
+        "kpm_batch_tuning": (c_int32, [P, P]),
         "kpm_profile_begin": (c_int32, [c_int32]),
         "kpm_profile_end": (c_int32, [POINTER(c_double), POINTER(c_int32), POINTER(c_double),
                                       POINTER(c_int32)]),
@@ -374,6 +377,10 @@ def kpm_set_probe_block(probes_per_thread: int) -> int:
     return int(_lib.kpm_set_probe_block(probes_per_thread))
 
 
+def kpm_set_schedule(fwd: int, adj: int) -> None:
+    _check(_lib.kpm_set_schedule(fwd, adj), "kpm_set_schedule")
+
+
 def kpm_profile_begin(sample_every: int = 1) -> None:
     _check(_lib.kpm_profile_begin(sample_every), "kpm_profile_begin")
 
@@ -476,6 +483,15 @@ def kpm_batch_energy_grad(plan, h, ab, C, omega, rho, use_graph=True, stream=Non
 
 def kpm_batch_destroy(plan) -> None:
     _check(_lib.kpm_batch_destroy(plan), "kpm_batch_destroy")
+
+
+def kpm_batch_tuning(plan) -> dict:
+    """The plan's probe blocks and schedules, and where they came from."""
+    out = (c_int32 * 5)()
+    _check(_lib.kpm_batch_tuning(plan, out), "kpm_batch_tuning")
+    src = {0: "timed", 1: "process cache", 2: "disk cache", -1: "fixed"}[out[4]]
+    return {"fwd_probe_block": out[0], "fwd_schedule": out[1], "adj_probe_block": out[2],
+            "adj_schedule": out[3], "source": src}
 
 
 # ---------------------------------------------------------------- helpers
