@@ -73,6 +73,13 @@ def test_host_validation():
     old = kpm.kpm_set_probe_block(4)
     assert kpm.kpm_set_probe_block(3) == 4       # invalid value leaves the setting
     assert kpm.kpm_set_probe_block(old) == 4
+    # block schedules: -1 (default) .. 2 (strips); anything else is rejected
+    for bad in ((3, 0), (0, 3), (-2, 0), (0, -2)):
+        assert kpm._lib.kpm_set_schedule(*bad) == kpm.KPM_EINVAL
+    assert kpm._lib.kpm_set_schedule(kpm.KPM_SCHED_STRIPS, kpm.KPM_SCHED_TILE_MAJOR) == kpm.KPM_OK
+    assert kpm._lib.kpm_set_schedule(kpm.KPM_SCHED_DEFAULT, kpm.KPM_SCHED_DEFAULT) == kpm.KPM_OK
+    out = (ctypes.c_int32 * 5)()
+    assert kpm._lib.kpm_batch_tuning(None, out) == kpm.KPM_EINVAL
 
 
 def test_rmft_host_validation():
