@@ -31,7 +31,7 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
-PMC_ARGS = "--moments 256 --steps 1 --warmup 0 --no-cpu-baseline --no-fp64-form --no-kernel-timing"
+PMC_ARGS = "--moments 256 --steps 1 --warmup 1 --no-cpu-baseline --no-fp64-form --no-kernel-timing"
 METRIC = "Chebyshev vector-steps/s + HBM GB/s; s per KPM energy+gradient at 100x100"
 
 
@@ -64,18 +64,26 @@ def traffic_record(kernel: str):
 
 
 def _pmc_rows(d, counter):
-    """Per-dispatch values of one counter from a rocprofv3 --pmc CSV directory,
-    keyed by kernel name."""
+    """Per-dispatch (grid size, value) of one counter from a rocprofv3 --pmc CSV
+    directory, keyed by kernel name."""
     import csv
     import glob
     vals = {}
     for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(f)):
             if r["Counter_Name"] == counter:
-                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+                vals.setdefault(r["Kernel_Name"], []).append((int(r["Grid_Size"]), float(r["Counter_Value"])))
     if not vals:
         raise SystemExit(f"no {counter} rows under {d}")
     return vals
+
+
+def _modal_grid(rows):
+    """Values of the dispatches with the most common grid size: the kernel in
+    the configuration the run used, without the tuner's trial launches."""
+    import collections
+    grid = collections.Counter(g for g, _ in rows).most_common(1)[0][0]
+    return grid, [v for g, v in rows if g == grid]
 
 
 def traffic_summary(base: str, copy_bytes: int) -> None:
@@ -84,22 +92,25 @@ def traffic_summary(base: str, copy_bytes: int) -> None:
     traffic record of the recursion kernels (written under profiles/)."""
     fetch, write = _pmc_rows(os.path.join(base, "fetch"), "FETCH_SIZE"), _pmc_rows(os.path.join(base, "write"), "WRITE_SIZE")
     cf, cw = _pmc_rows(os.path.join(base, "copyf"), "FETCH_SIZE"), _pmc_rows(os.path.join(base, "copyw"), "WRITE_SIZE")
-    kib_f = max(max(v) for v in cf.values())      # the copy is the largest dispatch of its run
-    kib_w = max(max(v) for v in cw.values())
+    kib_f = max(v for rows in cf.values() for _, v in rows)   # the copy is the largest dispatch of its run
+    kib_w = max(v for rows in cw.values() for _, v in rows)
     f_fetch, f_write = copy_bytes / (kib_f * 1024.0), copy_bytes / (kib_w * 1024.0)
     out = {}
     # the plain step launches (not the checkpoint-storing forward nor the last adjoint step)
     for short, tags in (("k_adj", (">::adj<false>(",)), ("k_fwd", (">::fwdp<false, false>(",))):
-        fr = [v for k, vs in fetch.items() if any(t in k for t in tags) for v in vs]
-        wr = [v for k, vs in write.items() if any(t in k for t in tags) for v in vs]
+        fr = [x for k, vs in fetch.items() if any(t in k for t in tags) for x in vs]
+        wr = [x for k, vs in write.items() if any(t in k for t in tags) for x in vs]
         if not fr or not wr:
             raise SystemExit(f"no dispatches of {short} in the counter runs")
+        grid, fr = _modal_grid(fr)
+        wr = [v for g, v in wr if g == grid]
         fk, wk = sum(fr) / len(fr), sum(wr) / len(wr)
         out[short] = {
             "kernel_source_sha256_16": kernel_source_hash(),
             "kernel_source_hash_rule": "sha256 of kpm_cheb.hip with comments and whitespace removed "
                                        "(bench.kernel_source_hash)",
             "dispatches": len(fr),
+            "grid_size": grid,
             "FETCH_SIZE_KiB_per_dispatch": fk,
             "WRITE_SIZE_KiB_per_dispatch": wk,
             "copy_calibration": {"bytes": copy_bytes, "FETCH_SIZE_KiB": kib_f, "WRITE_SIZE_KiB": kib_w,
@@ -109,6 +120,10 @@ def traffic_summary(base: str, copy_bytes: int) -> None:
                     "scaled by what the same counters read for a plain copy of known size",
             "commands": [
                 "cd /tmp && export TMPDIR=/tmp",
+                "export KPM_TUNE_CACHE=<file>   # the kernel configuration tuned at the benchmark's M, "
+                "reused by the counter runs (the shape key does not include M)",
+                "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp64-form --no-batched-form "
+                "--no-rmft-form --no-direct-form --no-supercell-form",
                 f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {base}/fetch -o fetch -- python3 bench.py {PMC_ARGS}",
                 f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {base}/write -o write -- python3 bench.py {PMC_ARGS}",
                 f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {base}/copyf -o copyf -- python3 bench.py "

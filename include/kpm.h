@@ -331,12 +331,14 @@ int kpm_status_read(const void* ws, int32_t* status, void* stream);
  * plan owns its device memory.  On first use it chooses the probes-per-thread
  * blocking and the block schedule of the forward and of the adjoint kernel by
  * timing every pair (autotune), unless kpm_set_probe_block fixed the block.
- * Picks are remembered per shape (device, M, precision, checkpoint interval,
- * every instance's N and R) in the process and in a text file: the path in
- * the environment variable KPM_TUNE_CACHE, else $XDG_CACHE_HOME/kpm_tune.txt,
- * else $HOME/.cache/kpm_tune.txt.  Each line of that file is
+ * Picks are remembered per shape (device, precision, every instance's N and
+ * R; not M or the checkpoint interval, which do not change a step's cost) in
+ * the process and in a text file: the path in the environment variable
+ * KPM_TUNE_CACHE, else $XDG_CACHE_HOME/kpm_tune.txt, else
+ * $HOME/.cache/kpm_tune.txt.  Each line of that file is
  * "<key> <Pf> <Sf> <Pa> <Sa>", with <key> =
- * "<arch>:<compute units>:M<M>:<f|d>:k<ckpt_k>:<N_0>x<R_0>,<N_1>x<R_1>,...";
+ * "<arch>:<compute units>:<f|d>:<N_0>x<R_0>,<N_1>x<R_1>,...";
+ * a shape tuned with M < 3 (no adjoint step to time) is not remembered;
  * the last valid line of a key is used, and a file that cannot be read or
  * written only disables the disk cache.  lats/probes: host arrays [n_inst]. */
 int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* probes,

@@ -420,8 +420,9 @@ struct Tune {
 };
 std::map<std::string, Tune> g_tune_cache;   // this process's picks, by shape key
 
-// Shape key: device (architecture, compute units), M, precision, checkpoint
-// interval and every instance's N and R, in plan order.
+// Shape key: device (architecture, compute units), precision and every
+// instance's N and R, in plan order.  A step's cost does not depend on M or
+// on the checkpoint interval, so those are not part of it.
 std::string device_tag() {
   static std::mutex mu;
   static std::map<int, std::string> tags;   // device ordinal -> "<arch>:<compute units>"
@@ -443,8 +444,7 @@ std::string device_tag() {
 }
 
 std::string shape_key(const Ctx& c) {
-  std::string key = device_tag() + ":M" + std::to_string(c.M) + (c.fp32 ? ":f" : ":d") + ":k" +
-                    std::to_string(c.k);
+  std::string key = device_tag() + (c.fp32 ? ":f" : ":d");
   for (size_t q = 0; q < c.inst.size(); ++q)
     key += (q ? "," : ":") + std::to_string(c.inst[q].N) + "x" + std::to_string(c.inst[q].R);
   return key;
@@ -596,9 +596,13 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != KPM_OK) return st;
+  *source = 0;
   if (c.M < 3) {
+    // no adjoint step to time: use the forward's pick, and remember nothing
     best.Pa = best.Pf;
     best.Sa = best.Sf;
+    apply_tune(c, best);
+    return put(c);
   }
   apply_tune(c, best);
   {
@@ -606,7 +610,6 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
     g_tune_cache[key] = best;
   }
   disk_store(key, best);
-  *source = 0;
   return put(c);
 }
 

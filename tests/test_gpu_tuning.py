@@ -100,7 +100,7 @@ def _key(cfgs, M, k, fp32):
     props = torch.cuda.get_device_properties(0)
     arch = props.gcnArchName.split(":")[0]
     inst = ",".join(f"{c.Lx * c.Ly}x{problem(c).R}" for c in cfgs)
-    return f"{arch}:{props.multi_processor_count}:M{M}:{'f' if fp32 else 'd'}:k{k}:{inst}"
+    return f"{arch}:{props.multi_processor_count}:{'f' if fp32 else 'd'}:{inst}"
 
 
 def _batch(cfgs, M, k, prec):
