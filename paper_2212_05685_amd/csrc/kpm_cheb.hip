@@ -613,21 +613,28 @@ __device__ __forceinline__ void fwd_body(const InstDev* __restrict__ insts,
 // the code byte) lives in fixed registers and every memory wait count is
 // static; every load and store is issued on every path (clamped probe index,
 // sink for lanes outside the lattice or past the wave's last probe).
-constexpr int PREC = 72;     // staged record slots per probe (60 used; the pitch keeps the
-                             // two slots' reads of one tile row in disjoint LDS banks)
+
+// Staged halo of one probe: 6 rows of 10 records, rows PROW records apart,
+// the two probe slots PREC records apart.  With these pitches the 128-bit
+// reads of a wave (16-lane groups holding one tile row of both slots) hit
+// distinct LDS banks; pitches of 10 / 72 cost about 4 conflict cycles per
+// read (measured with SQ_LDS_BANK_CONFLICT on gfx950).
+constexpr int PROW = 16;
+constexpr int PREC = 104;    // >= 6 * PROW, and PREC = 8 (mod 16)
 constexpr int FPP = 1;       // probe pairs in flight
 
 struct PairLane {
   int s, q;
   bool valid;
   unsigned site, halo;
+  int hw;                 // LDS record index this lane stages (halo lanes)
   int hoff[9];
 };
 
 // Lane l: tile row g = l >> 4, probe slot q = bit 3, column c = l & 7, so a
 // group of 16 lanes reads one tile row of both slots: 8 consecutive staged
-// records per slot, in disjoint banks (an LDS b128 read is served 16 lanes at
-// a time; two tile rows 10 records apart would share banks).
+// records per slot.  Halo lane h (< 60) stages record (h % 10, h / 10) at
+// row pitch PROW.
 __device__ __forceinline__ PairLane pair_geometry(const InstDev& I, int X0, int Y0, int lane) {
   PairLane L;
   L.q = (lane >> 3) & 1;
@@ -642,16 +649,17 @@ __device__ __forceinline__ PairLane pair_geometry(const InstDev& I, int X0, int 
   hx = ((hx % I.Lx) + I.Lx) % I.Lx;
   hy = ((hy % I.Ly) + I.Ly) % I.Ly;
   L.halo = (unsigned)(hy * I.Lx + hx);
-  const int c = (ty + 1) * HX + (tx + 1);
+  L.hw = (h / HX) * PROW + (h % HX);
+  const int c = (ty + 1) * PROW + (tx + 1);
   L.hoff[0] = c;
   L.hoff[1] = c + 1;
-  L.hoff[2] = c + HX;
-  L.hoff[3] = c + HX + 1;
-  L.hoff[4] = c - HX + 1;
+  L.hoff[2] = c + PROW;
+  L.hoff[3] = c + PROW + 1;
+  L.hoff[4] = c - PROW + 1;
   L.hoff[5] = c - 1;
-  L.hoff[6] = c - HX;
-  L.hoff[7] = c - HX - 1;
-  L.hoff[8] = c + HX - 1;
+  L.hoff[6] = c - PROW;
+  L.hoff[7] = c - PROW - 1;
+  L.hoff[8] = c + PROW - 1;
   return L;
 }
 
@@ -853,8 +861,8 @@ __device__ __forceinline__ void fwdp_body(const InstDev* __restrict__ insts,
       const int u = j % FPP;
       F4* buf = S.r[wave][j & 1][0];
       if (lane < HREC) {
-        buf[lane] = h0[u];
-        buf[PREC + lane] = h1[u];
+        buf[L.hw] = h0[u];
+        buf[PREC + L.hw] = h1[u];
       }
       __builtin_amdgcn_wave_barrier();
       if (j + FPP < NP) issue_halo(j + FPP, u);
