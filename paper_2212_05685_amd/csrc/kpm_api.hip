@@ -467,8 +467,11 @@ bool valid_tune(const Tune& t) {
   return okP(t.Pf) && okP(t.Pa) && okS(t.Sf) && okS(t.Sa);
 }
 
+std::mutex g_tune_file_mu;   // one reader or writer of the cache file at a time in this process
+
 bool disk_lookup(const std::string& key, Tune& out) {
   const std::string path = tune_path();
+  std::lock_guard<std::mutex> lk(g_tune_file_mu);
   if (path.empty()) return false;
   std::ifstream f(path);
   if (!f) return false;
@@ -490,6 +493,7 @@ bool disk_lookup(const std::string& key, Tune& out) {
 void disk_store(const std::string& key, const Tune& t) {
   const std::string path = tune_path();
   if (path.empty()) return;
+  std::lock_guard<std::mutex> lk(g_tune_file_mu);
   const size_t slash = path.rfind('/');
   if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
   std::ofstream f(path, std::ios::app);
@@ -539,9 +543,17 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
     return put(c);
   }
   const bool verbose = std::getenv("KPM_TUNE_VERBOSE") != nullptr;
-  hipEvent_t e0, e1;
-  KPM_HIP(hipEventCreate(&e0));
-  KPM_HIP(hipEventCreate(&e1));
+  // timing events, destroyed on every return path
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  KPM_HIP(hipEventCreate(&ev.a));
+  KPM_HIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   const int steps = std::min(c.M, 8);
   float best_f = 1e30f, best_a = 1e30f;
   Tune best{1, -1, 1, -1};
@@ -593,8 +605,6 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
     }
     if (st != KPM_OK) break;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (st != KPM_OK) return st;
   *source = 0;
   if (c.M < 3) {
