@@ -463,7 +463,7 @@ std::string tune_path() {
 
 bool valid_tune(const Tune& t) {
   auto okP = [](int P) { return P == 1 || P == 2 || P == 4 || P == 8 || P == 16 || P == 32; };
-  auto okS = [](int S) { return S >= 0 && S <= 2; };
+  auto okS = [](int S) { return S >= KPM_SCHED_TILE_MAJOR && S <= KPM_SCHED_STRIP_TILES; };
   return okP(t.Pf) && okP(t.Pa) && okS(t.Sf) && okS(t.Sa);
 }
 
@@ -559,7 +559,7 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
   Tune best{1, -1, 1, -1};
   int st = KPM_OK;
   for (int P : {1, 2, 4, 8, 16, 32}) {
-    for (int S : {KPM_SCHED_TILE_MAJOR, KPM_SCHED_RANGES, KPM_SCHED_STRIPS}) {
+    for (int S : {KPM_SCHED_TILE_MAJOR, KPM_SCHED_RANGES, KPM_SCHED_STRIPS, KPM_SCHED_STRIP_TILES}) {
       c.Pf = c.Pa = P;
       c.Sf = c.Sa = S;
       set_npb(c);
@@ -1070,7 +1070,7 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread) {
 }
 
 int kpm_set_schedule(int32_t fwd, int32_t adj) {
-  auto ok = [](int32_t v) { return v >= KPM_SCHED_DEFAULT && v <= KPM_SCHED_STRIPS; };
+  auto ok = [](int32_t v) { return v >= KPM_SCHED_DEFAULT && v <= KPM_SCHED_STRIP_TILES; };
   if (!ok(fwd) || !ok(adj)) return KPM_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   g_sched_f = fwd;

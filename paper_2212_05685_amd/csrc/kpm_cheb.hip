@@ -264,8 +264,11 @@ __device__ __forceinline__ double probe_weight(const InstDev& I, int p) {
 //    sweeps it once per probe range, range after range; every tile's
 //    coefficients are read by one XCD only, at the price of halo rows read
 //    twice at the 8 strip boundaries.
+//  * STRIP_TILES: XCD x takes the x-th of 8 contiguous strips and sweeps it
+//    once, tile after tile, with all probe ranges of a tile in a row, so a
+//    tile's coefficients are read from memory once and then from the XCD's L2.
 //  Otherwise tile-major (range fastest).
-enum : int { kSchedTileMajor = 0, kSchedRanges = 1, kSchedStrips = 2 };
+enum : int { kSchedTileMajor = 0, kSchedRanges = 1, kSchedStrips = 2, kSchedStripTiles = 3 };
 // tiles_x > 0: a single lattice, whose tile t sits at ((t % tiles_x) 8, (t / tiles_x) 4),
 // so a block finds its tile without reading the tile table
 struct Sched { int nranges, chunk, ntiles, mode, tiles_x; };
@@ -280,6 +283,13 @@ __device__ __forceinline__ bool block_work(const Sched& sc, int& tile, int& rang
     const int x = b & 7, i = b >> 3;
     range = i / sc.chunk;
     tile = x * sc.chunk + (i - range * sc.chunk);
+    return tile < sc.ntiles;
+  }
+  if (sc.mode == kSchedStripTiles) {
+    const int x = b & 7, i = b >> 3;
+    const int t = i / sc.nranges;
+    range = i - t * sc.nranges;
+    tile = x * sc.chunk + t;
     return tile < sc.ntiles;
   }
   if (sc.mode == kSchedRanges) {
@@ -1512,11 +1522,12 @@ hipError_t profile_end(double* fwd_ms, int* nfwd, double* adj_ms, int* nadj) {
 // Schedule of a launch: the forward step (which 0, 1, 4, 5) sweeps strips
 // (its coefficient table would otherwise be read by every XCD that holds a
 // probe range), the adjoint (2, 3) keeps probe ranges per XCD.
-// A requested schedule (0 tile-major, 1 ranges, 2 strips) overrides the
+// A requested schedule (0 tile-major, 1 ranges, 2 strips, 3 strips tile by
+// tile) overrides the
 // default; ranges needs a range count that divides 8, else tile-major runs.
 static int sched_mode(int which, int nranges, int req) {
   int m = (which == 2 || which == 3) ? kSchedRanges : kSchedStrips;
-  if (req >= kSchedTileMajor && req <= kSchedStrips) m = req;
+  if (req >= kSchedTileMajor && req <= kSchedStripTiles) m = req;
   if (m == kSchedRanges && 8 % nranges != 0) return kSchedTileMajor;
   return m;
 }
@@ -1528,8 +1539,8 @@ static hipError_t launch_all(int sched, int which, const InstDev* insts, const i
   Sched sc{nranges, 0, ntiles, kSchedTileMajor, tiles_x};
   int nblocks = ntiles * nranges;
   const int mode = sched_mode(which, nranges, sched);
-  if (mode == kSchedStrips) {
-    sc.mode = kSchedStrips;
+  if (mode == kSchedStrips || mode == kSchedStripTiles) {
+    sc.mode = mode;
     sc.chunk = (ntiles + 7) / 8;
     nblocks = 8 * sc.chunk * nranges;
   } else if (mode == kSchedRanges && 8 % nranges == 0) {

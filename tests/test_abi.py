@@ -74,7 +74,7 @@ def test_host_validation():
     assert kpm.kpm_set_probe_block(3) == 4       # invalid value leaves the setting
     assert kpm.kpm_set_probe_block(old) == 4
     # block schedules: -1 (default) .. 2 (strips); anything else is rejected
-    for bad in ((3, 0), (0, 3), (-2, 0), (0, -2)):
+    for bad in ((4, 0), (0, 4), (-2, 0), (0, -2)):
         assert kpm._lib.kpm_set_schedule(*bad) == kpm.KPM_EINVAL
     assert kpm._lib.kpm_set_schedule(kpm.KPM_SCHED_STRIPS, kpm.KPM_SCHED_TILE_MAJOR) == kpm.KPM_OK
     assert kpm._lib.kpm_set_schedule(kpm.KPM_SCHED_DEFAULT, kpm.KPM_SCHED_DEFAULT) == kpm.KPM_OK

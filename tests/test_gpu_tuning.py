@@ -60,7 +60,7 @@ def _single(cfg, prec, P, sf, sa):
     return host(omega)[0], host(mu), rho
 
 
-SCHEDS = [(sf, sa) for sf in (0, 1, 2) for sa in (0, 1, 2)]
+SCHEDS = [(sf, sa) for sf in (0, 1, 2, 3) for sa in (0, 1, 2, 3)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -91,7 +91,7 @@ def test_range_schedule_falls_back_when_ranges_do_not_divide_8(prec):
 
 def test_set_schedule_rejects_bad_values():
     from paper_2212_05685_amd import kpm
-    for bad in ((3, 0), (0, -2), (7, 7)):
+    for bad in ((4, 0), (0, -2), (7, 7)):
         with pytest.raises(RuntimeError):
             kpm.kpm_set_schedule(*bad)
 
