@@ -340,7 +340,8 @@ int kpm_status_read(const void* ws, int32_t* status, void* stream);
  * "<arch>:<compute units>:<f|d>:<N_0>x<R_0>,<N_1>x<R_1>,...";
  * a shape tuned with M < 3 (no adjoint step to time) is not remembered;
  * the last valid line of a key is used, and a file that cannot be read or
- * written only disables the disk cache.  lats/probes: host arrays [n_inst]. */
+ * written only disables the disk cache (so does KPM_TUNE_CACHE set to the
+ * empty string).  lats/probes: host arrays [n_inst]. */
 int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* probes,
                      int32_t M, int32_t precision, int32_t ckpt_k, void** plan);
 
