@@ -371,7 +371,8 @@ int kpm_batch_tuning(const void* plan, int32_t* out);
  * kpm_batch_create for the process and file caches); a shape not seen yet is
  * tuned by its first kpm_grand_potential (or kpm_density_matrix) call, on
  * that call's workspace, unless the stream is being captured; until then a
- * size heuristic picks the blocks. */
+ * size heuristic picks the blocks.  A shape's entry in the file is read at
+ * most once per process.  kpm_moments_noalloc always uses the heuristic. */
 int32_t kpm_set_probe_block(int32_t probes_per_thread);
 
 /* Block schedules of the recursion kernels (how (tile, probe range) work

@@ -9,6 +9,7 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <set>
 #include <sstream>
 #include <string>
 #include <tuple>
@@ -419,6 +420,7 @@ struct Tune {
   int Pf, Sf, Pa, Sa;
 };
 std::map<std::string, Tune> g_tune_cache;   // this process's picks, by shape key
+std::set<std::string> g_tune_miss;          // keys the file did not hold when last read
 
 // Shape key: device (architecture, compute units), precision and every
 // instance's N and R, in plan order.  A step's cost does not depend on M or
@@ -501,7 +503,8 @@ void disk_store(const std::string& key, const Tune& t) {
 }
 
 // Picks for this shape from the process cache, else from the file (then
-// remembered in the process); *source = 1 or 2.
+// remembered in the process); *source = 1 or 2.  A key the file did not hold
+// is not looked up in the file again by this process.
 bool tune_lookup(const std::string& key, Tune& t, int* source) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -511,9 +514,14 @@ bool tune_lookup(const std::string& key, Tune& t, int* source) {
       *source = 1;
       return true;
     }
+    if (g_tune_miss.count(key)) return false;
   }
-  if (!disk_lookup(key, t)) return false;
+  const bool hit = disk_lookup(key, t);
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!hit) {
+    g_tune_miss.insert(key);
+    return false;
+  }
   g_tune_cache[key] = t;
   *source = 2;
   return true;
@@ -676,11 +684,13 @@ int prepare_single(Ctx& c, const kpm_lattice* L, const double* h, const double* 
   c.Pf = P ? P : auto_probe_fwd(c.ntl(), c.Rmax);
   c.Pa = P ? P : auto_probe_adj(c.ntl(), c.Rmax);
   set_npb(c);
-  if (P == 0) {
+  // the forward-only layout (the entry point without allocation) keeps the
+  // size heuristic: no cache lookup, no file access
+  if (P == 0 && !fwd_only) {
     Tune t{};
     int src = 0;
     if (tune_lookup(shape_key(c), t, &src)) apply_tune(c, t);
-    else c.want_tune = !fwd_only;
+    else c.want_tune = true;
   }
   return KPM_OK;
 }
