@@ -372,7 +372,12 @@ int kpm_batch_tuning(const void* plan, int32_t* out);
  * tuned by its first kpm_grand_potential (or kpm_density_matrix) call, on
  * that call's workspace, unless the stream is being captured; until then a
  * size heuristic picks the blocks.  A shape's entry in the file is read at
- * most once per process.  kpm_moments_noalloc always uses the heuristic. */
+ * most once per process.  kpm_moments_noalloc always uses the heuristic.
+ * The picks change results only through the order of floating-point sums
+ * (the FP32 per-wave sums and the FP64 partial sums of the adjoint): within
+ * 1e-7 relative in FP32, 1e-14 in FP64.  Fixing the block (and the schedules
+ * with kpm_set_schedule), or a prepared cache file, makes runs repeatable
+ * across processes. */
 int32_t kpm_set_probe_block(int32_t probes_per_thread);
 
 /* Block schedules of the recursion kernels (how (tile, probe range) work
