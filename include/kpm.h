@@ -387,18 +387,25 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread);
  * (when the range count divides 8, else tile-major); KPM_SCHED_STRIPS, each
  * XCD one eighth of the tiles, range after range; KPM_SCHED_STRIP_TILES, each
  * XCD one eighth of the tiles, tile after tile with all probe ranges of a
- * tile in a row.  KPM_SCHED_DEFAULT is strips for the forward steps and
- * ranges for the adjoint. */
+ * tile in a row; KPM_SCHED_BALANCED (adjoint steps of a single lattice; the
+ * forward steps run their default), the (tile, probe) work cut into one equal
+ * share per block that the chip holds at once, so every compute unit gets the
+ * same work in a single round (each XCD one eighth of the work, the probes in
+ * two halves when R is even; the partial sums use up to ceil(R/4) FP64 slices,
+ * and the schedule falls back to ranges when that is not enough or the
+ * lattice is too small to fill the grid).  KPM_SCHED_DEFAULT is strips for
+ * the forward steps and ranges for the adjoint. */
 #define KPM_SCHED_DEFAULT (-1)
 #define KPM_SCHED_TILE_MAJOR 0
 #define KPM_SCHED_RANGES 1
 #define KPM_SCHED_STRIPS 2
 #define KPM_SCHED_STRIP_TILES 3
+#define KPM_SCHED_BALANCED 4
 
 /* Schedules used, while the probe block is fixed (kpm_set_probe_block
  * nonzero), by the single-lattice calls and the batch plans created then;
  * with the automatic block the tuned schedules apply.  Process-wide.
- * Returns KPM_EINVAL (nothing changed) for a value outside -1..3.  The
+ * Returns KPM_EINVAL (nothing changed) for a value outside -1..4.  The
  * results do not depend on the schedule, up to the order of FP64 sums of the
  * adjoint partial sums. */
 int kpm_set_schedule(int32_t fwd, int32_t adj);

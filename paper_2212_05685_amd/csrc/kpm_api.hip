@@ -34,7 +34,9 @@ hipError_t launch_bounds(int, int, const double*, double*, hipStream_t);
 hipError_t launch_rescale(const InstDev*, const int4*, int, bool, hipStream_t);
 hipError_t launch_coeffs(int, int, double, const double*, double*, hipStream_t);
 hipError_t launch_cheb(bool, int, int, int, const InstDev*, const int4*, int, int, int, int, int, int,
-                       int, hipStream_t);
+                       int, int4, hipStream_t);
+hipError_t adj_bal_blocks_per_cu(bool, int*);
+hipError_t launch_zero2(double2*, long long, hipStream_t);
 hipError_t launch_mom_reduce(const InstDev*, int, int, int, double*, hipStream_t);
 hipError_t launch_omega(const InstDev*, int, int, hipStream_t);
 hipError_t launch_rho(const InstDev*, const int2*, int, hipStream_t);
@@ -242,6 +244,8 @@ struct Ctx {
   int Pf = 1, Pa = 1;         // probes per wave, forward and adjoint kernels
   int Sf = -1, Sa = -1;       // block schedules (KPM_SCHED_*), -1 = the kernel's default
   bool want_tune = false;     // single lattice, automatic block, shape not tuned yet
+  int4 bal = make_int4(0, 0, 0, 0);   // balanced adjoint split (blocks, probes per group,
+                                      // slices per group, groups); blocks = 0: not used
   int Rmax = 0;
   long long sites = 0;
   int nrf() const { return (Rmax + kWaves * Pf - 1) / (kWaves * Pf); }
@@ -267,9 +271,58 @@ void finish_ctx(Ctx& c) {
   }
 }
 
-// number of probe ranges of each instance in the adjoint (partial dOmega/dH~ buffers)
+// compute units of the current device (0 if unknown)
+int device_cus() {
+  static std::mutex mu;
+  static std::map<int, int> cus;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cus.find(dev);
+  if (it != cus.end()) return it->second;
+  hipDeviceProp_t prop{};
+  const int n = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 0;
+  return cus[dev] = n;
+}
+
+// Work split of the balanced adjoint schedule (single lattice, see
+// adj_bal_body): the grid is the number of blocks the chip holds at once
+// (a multiple of 8, capped so that every share has at least 8 units); the
+// probes form 2 groups when R is even (the XCDs then split the probes in
+// halves, as in the ranges schedule), else 1; the slices per group are the
+// most blocks that touch one (group, tile) segment.  Not used (bal.x = 0)
+// when those slices would not fit the partial-sum buffer (ceil(R / 4)
+// slices) or the lattice is too small to fill the grid.
+void set_bal(Ctx& c) {
+  c.bal = make_int4(0, 0, 0, 0);
+  if (c.Sa != KPM_SCHED_BALANCED || c.inst.size() != 1) return;
+  InstDev& I = c.inst[0];
+  int nb = 0;
+  if (adj_bal_blocks_per_cu(c.fp32, &nb) != hipSuccess || nb < 1) return;
+  const long long cus = device_cus();
+  const long long ntiles = c.ntl(), W = ntiles * I.R;
+  if (W >= (1LL << 31)) return;                 // the kernel's unit indices are 32-bit
+  long long G = std::min((long long)nb * cus, W / 8);
+  G -= G % 8;
+  if (G < 8) return;
+  const int ng = I.R % 2 == 0 ? 2 : 1;
+  const long long Lg = I.R / ng;
+  long long S = 0;
+  for (long long seg = 0; seg < ng * ntiles; ++seg) {
+    // blocks holding the segment's first and last units: block_of(v) = ((v + 1) G - 1) / W
+    const long long b0 = ((seg * Lg + 1) * G - 1) / W, b1 = ((seg + 1) * Lg * G - 1) / W;
+    S = std::max(S, b1 - b0 + 1);
+  }
+  if (ng * S > (I.R + kWaves - 1) / kWaves) return;
+  c.bal = make_int4((int)G, (int)Lg, (int)S, ng);
+  I.npb = (int)(ng * S);
+}
+
+// number of probe ranges of each instance in the adjoint (partial dOmega/dH~
+// buffers); the balanced schedule's slices instead when it applies
 void set_npb(Ctx& c) {
   for (auto& I : c.inst) I.npb = (I.R + kWaves * c.Pa - 1) / (kWaves * c.Pa);
+  set_bal(c);
 }
 
 // Host copies of the tables uploaded for single-lattice calls, kept alive per
@@ -346,10 +399,10 @@ int run_forward(const Ctx& c, bool ckpt, int nsteps, hipStream_t s) {
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
   KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, c.M, c.k,
-                      ckpt ? 1 : 0, s));
+                      ckpt ? 1 : 0, c.bal, s));
   for (int m = 0; m + 1 < nsteps; ++m)
     KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, c.M, c.k,
-                        ckpt ? 1 : 0, s));
+                        ckpt ? 1 : 0, c.bal, s));
   return KPM_OK;
 }
 
@@ -360,12 +413,25 @@ int run_moments(const Ctx& c, double* mu_user, hipStream_t s) {
   return KPM_OK;
 }
 
+// gamma_{M-1}, gamma_{M-2} and cleared partial sums (every slice the
+// balanced schedule uses; the other schedules' init clears its own ranges)
+int adj_init(const Ctx& c, hipStream_t s) {
+  if (c.bal.x > 0) {
+    const InstDev& I = c.inst[0];
+    KPM_HIP(launch_zero2(I.gpart, (long long)I.npb * kNent * I.N, s));
+  }
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 2, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, c.M, c.k, 0,
+                      c.bal, s));
+  return KPM_OK;
+}
+
 int run_adjoint(const Ctx& c, hipStream_t s) {
   const int M = c.M;
-  KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 2, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, M, c.k, 0, s));
+  int st = adj_init(c, s);
+  if (st != KPM_OK) return st;
   for (int m = M - 3; m >= 0; --m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), m, M, c.k, 0, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, M, c.k, 1, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), m, M, c.k, 0, c.bal, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, M, c.k, 1, c.bal, s));
   KPM_HIP(launch_rho(c.d_inst, c.d_cmap, c.nch(), s));
   return KPM_OK;
 }
@@ -411,7 +477,7 @@ int restore_alpha(const Ctx& c, hipStream_t s) {
   KPM_HIP(hipMemcpyAsync(I.A[j0 & 1], ck + slot * vec, vec, hipMemcpyDeviceToDevice, s));
   KPM_HIP(hipMemcpyAsync(I.A[(j0 + 1) & 1], ck + (slot + 1) * vec, vec, hipMemcpyDeviceToDevice, s));
   for (int m = j0 + 1; m + 1 < M; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, k, 0, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, k, 0, c.bal, s));
   return KPM_OK;
 }
 
@@ -465,7 +531,7 @@ std::string tune_path() {
 
 bool valid_tune(const Tune& t) {
   auto okP = [](int P) { return P == 1 || P == 2 || P == 4 || P == 8 || P == 16 || P == 32; };
-  auto okS = [](int S) { return S >= KPM_SCHED_TILE_MAJOR && S <= KPM_SCHED_STRIP_TILES; };
+  auto okS = [](int S) { return S >= KPM_SCHED_TILE_MAJOR && S <= KPM_SCHED_BALANCED; };
   return okP(t.Pf) && okP(t.Pa) && okS(t.Sf) && okS(t.Sa);
 }
 
@@ -568,7 +634,11 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
   Tune best{1, -1, 1, -1};
   int st = KPM_OK;
   for (int P : {1, 2, 4, 8, 16, 32}) {
-    for (int S : {KPM_SCHED_TILE_MAJOR, KPM_SCHED_RANGES, KPM_SCHED_STRIPS, KPM_SCHED_STRIP_TILES}) {
+    for (int S : {KPM_SCHED_TILE_MAJOR, KPM_SCHED_RANGES, KPM_SCHED_STRIPS, KPM_SCHED_STRIP_TILES,
+                  KPM_SCHED_BALANCED}) {
+      // the balanced adjoint does not depend on the probe block (the forward
+      // then runs its default schedule): one candidate is enough
+      if (S == KPM_SCHED_BALANCED && P != 32) continue;
       c.Pf = c.Pa = P;
       c.Sf = c.Sa = S;
       set_npb(c);
@@ -585,7 +655,7 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
         if (rep > 0) tf = std::min(tf, t);
       }
       if (st != KPM_OK) break;
-      if (tf < best_f) {
+      if (tf < best_f && S != KPM_SCHED_BALANCED) {
         best_f = tf;
         best.Pf = P;
         best.Sf = S;
@@ -596,13 +666,12 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
         // forward steps just timed (with checkpoint stores, so an anchored step at
         // small M reads written slots), gamma and the partial sums from k_adj_init;
         // warm once, then the faster of two timed runs
-        KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 2, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(), 0, c.M,
-                            c.k, 0, s));
+        if ((st = adj_init(c, s)) != KPM_OK) break;
         for (int rep = 0; rep < 3; ++rep) {
           KPM_HIP(hipEventRecord(e0, s));
           for (int q = 0; q < steps; ++q)
             KPM_HIP(launch_cheb(c.fp32, c.Pa, c.Sa, 3, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nra(),
-                                c.M - 3, c.M, c.M + 1, 0, s));
+                                c.M - 3, c.M, c.M + 1, 0, c.bal, s));
           KPM_HIP(hipEventRecord(e1, s));
           KPM_HIP(hipEventSynchronize(e1));
           float t = 0.f;
@@ -997,11 +1066,11 @@ int kpm_density_matrix_direct(const kpm_lattice* lat, const double* h, const dou
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
   KPM_HIP(launch_direct_coef(c.d_inst, 1, M, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, c.bal, s));
   // step m writes alpha_{m+1}; even steps also add D_m alpha_m + D_{m+1} alpha_{m+1} to y
   for (int m = 0; m + 1 < M; ++m)
     KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, (m & 1) ? 1 : 5, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M,
-                        c.k, m == 0 ? 1 : 0, s));
+                        c.k, m == 0 ? 1 : 0, c.bal, s));
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_omega(c.d_inst, 1, M, s));
   KPM_HIP(launch_rho_direct(c.d_inst, c.d_cmap, c.nch(), s));
@@ -1026,10 +1095,10 @@ int kpm_moments_doubling(const kpm_lattice* lat, const double* h, const double* 
   hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, c.d_inst, 1, 0);
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
-  KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, s));
+  KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 0, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), 0, M, c.k, 0, c.bal, s));
   // alpha_1 .. alpha_{M/2}: every moment slot below M is then written
   for (int m = 0; m < M / 2; ++m)
-    KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 4, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, c.k, 0, s));
+    KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 4, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, M, c.k, 0, c.bal, s));
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_mom_double(c.d_inst, 1, c.inst[0].R * M, M, mu, s));
   if (omega) KPM_HIP(launch_omega(c.d_inst, 1, M, s));
@@ -1088,7 +1157,7 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread) {
 }
 
 int kpm_set_schedule(int32_t fwd, int32_t adj) {
-  auto ok = [](int32_t v) { return v >= KPM_SCHED_DEFAULT && v <= KPM_SCHED_STRIP_TILES; };
+  auto ok = [](int32_t v) { return v >= KPM_SCHED_DEFAULT && v <= KPM_SCHED_BALANCED; };
   if (!ok(fwd) || !ok(adj)) return KPM_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   g_sched_f = fwd;

@@ -268,10 +268,16 @@ __device__ __forceinline__ double probe_weight(const InstDev& I, int p) {
 //    once, tile after tile, with all probe ranges of a tile in a row, so a
 //    tile's coefficients are read from memory once and then from the XCD's L2.
 //  Otherwise tile-major (range fastest).
-enum : int { kSchedTileMajor = 0, kSchedRanges = 1, kSchedStrips = 2, kSchedStripTiles = 3 };
+//  * BALANCED (adjoint step of a single lattice): the (tile, probe) work is
+//    cut into exactly as many equal contiguous shares as blocks fit on the
+//    chip at once (adj_bal_body), so every CU gets the same work in one round.
+enum : int { kSchedTileMajor = 0, kSchedRanges = 1, kSchedStrips = 2, kSchedStripTiles = 3,
+             kSchedBalanced = 4 };
 // tiles_x > 0: a single lattice, whose tile t sits at ((t % tiles_x) 8, (t / tiles_x) 4),
-// so a block finds its tile without reading the tile table
-struct Sched { int nranges, chunk, ntiles, mode, tiles_x; };
+// so a block finds its tile without reading the tile table.
+// BALANCED: nranges = probe groups, chunk = blocks in the grid, lg = probes per
+// group, sl = partial-sum slices per group.
+struct Sched { int nranges, chunk, ntiles, mode, tiles_x, lg, sl; };
 
 __device__ __forceinline__ int4 tile_of(const Sched& sc, const int4* __restrict__ tmap, int tile) {
   if (sc.tiles_x > 0) return make_int4(0, (tile % sc.tiles_x) * TX, (tile / sc.tiles_x) * TY, tile);
@@ -1037,28 +1043,27 @@ __device__ __forceinline__ void adj_loop(const InstDev& I, const Lane& L, const 
   }
 }
 
+// LDS of an adjoint block: the waves' staged halos during the probe loop,
+// then the per-wave partial sums (precision of V) for the block reduction.
+template <typename V> union AdjShared {
+  Stage<V> st;
+  Cx<V> red[WAVES][kNent][TX * TY];
+};
+
 // Step m (0 <= m <= M-3): alpha_m, gamma_m from the m+1, m+2 vectors (the m+2
 // buffers are overwritten), plus 2 conj(gamma_{m+1}) x alpha_{m+1} into the
 // partial dOmega/dH~.  TAIL: only conj(gamma_0) x alpha_0 (weight 1).
 // Lane (site, row a) accumulates the entries of row a: 4d + 2a + b (d < 4,
 // b < 2) and the onsite ones (a = 0: 16, 18; a = 1: 17).
-template <typename V, int PW, bool TAIL>
-__device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
-                                         const int4* __restrict__ tmap, Sched sc, int m,
-                                         int k_ckpt) {
+// One segment of a block's work: tile tm, this wave's probes [pbase, pend)
+// (possibly none); the block's sums go to partial-sum slice `slice`.  Every
+// wave of the block calls it (it synchronises the block).
+template <typename V, bool TAIL>
+__device__ __forceinline__ void adj_segment(const InstDev& I, const int4 tm, int pbase, int pend,
+                                            int slice, int m, int k_ckpt, AdjShared<V>& S,
+                                            int lane) {
   using R4 = typename RecT<V>::T;
-  __shared__ union {
-    Stage<V> st;
-    Cx<V> red[WAVES][kNent][TX * TY];     // per-wave partial sums, precision of V
-  } S;
-  int tile, range;
-  if (!block_work(sc, tile, range)) return;               // block-uniform
-  const int4 tm = tile_of(sc, tmap, tile);
-  const InstDev& I = insts[tm.x];
-  if (range * WAVES * PW >= I.R) return;                 // block-uniform
-  const int wave = wave_id(), lane = threadIdx.x & 63;
-  const int pbase = (range * WAVES + wave) * PW;
-  const int pend = min(pbase + PW, I.R);
+  const int wave = wave_id();
   const int N = I.N;
   const Lane L = lane_geometry(I, tm.y, tm.z, lane);
   RowCoef<V> K;
@@ -1108,7 +1113,7 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
   }
   __syncthreads();
   const double wgt = TAIL ? 1.0 : 2.0;
-  double2* gp = I.gpart + (long long)range * kNent * N;
+  double2* gp = I.gpart + (long long)slice * kNent * N;
   for (int q = threadIdx.x; q < kNent * TX * TY; q += kBlock) {
     const int e = q / (TX * TY), ss = q % (TX * TY);
     const int x = tm.y + (ss & (TX - 1)), y = tm.z + ss / TX;
@@ -1124,6 +1129,72 @@ __device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
     o.x += wgt * sx;
     o.y += wgt * sy;
     gp[gi] = o;
+  }
+}
+
+// Block b = (tile, probe range) of the schedule; wave w runs the range's
+// w-th PW probes; slice = range.
+template <typename V, int PW, bool TAIL>
+__device__ __forceinline__ void adj_body(const InstDev* __restrict__ insts,
+                                         const int4* __restrict__ tmap, Sched sc, int m,
+                                         int k_ckpt) {
+  __shared__ AdjShared<V> S;
+  int tile, range;
+  if (!block_work(sc, tile, range)) return;               // block-uniform
+  const int4 tm = tile_of(sc, tmap, tile);
+  const InstDev& I = insts[tm.x];
+  if (range * WAVES * PW >= I.R) return;                 // block-uniform
+  const int pbase = (range * WAVES + wave_id()) * PW;
+  adj_segment<V, TAIL>(I, tm, pbase, min(pbase + PW, I.R), range, m, k_ckpt, S, threadIdx.x & 63);
+}
+
+// Balanced schedule (single lattice).  The work units (probe group g, tile t,
+// probe q of the group), ordered g, t, q, W = ntiles R of them, are cut into
+// G = gridDim.x equal contiguous shares, G being the number of blocks that fit
+// on the chip at once: every CU gets the same work in a single round.  Shares
+// are dealt so that XCD x (blocks b = x mod 8) takes the x-th eighth of the
+// order, a spatially coherent part of the lattice.  A share runs as segments
+// (one per (g, t) it touches, at most a few), each split evenly over the
+// block's waves.  The blocks touching one segment are consecutive in the
+// order; the i-th of them adds into slice g sl + i, so no two blocks ever
+// update the same partial sums in one launch (sl bounds that count; the host
+// checks it and clears every slice before the first step).
+template <typename V, bool TAIL>
+__device__ __forceinline__ void adj_bal_body(const InstDev* __restrict__ insts,
+                                             const int4* __restrict__ tmap, Sched sc, int m,
+                                             int k_ckpt) {
+  __shared__ AdjShared<V> S;
+  const InstDev& I = insts[0];
+  const int b = blockIdx.x;
+  const long long G = sc.chunk, W = (long long)sc.ntiles * I.R;   // W < 2^31 (host check)
+  const long long bl = (long long)(b & 7) * (G >> 3) + (b >> 3);
+  // the share [u, u1) of the order, and its first segment's slice index: the
+  // block's place among the blocks touching that segment (later segments
+  // start inside the share, so the block is the first to touch them)
+  int u = __builtin_amdgcn_readfirstlane((int)(bl * W / G));
+  const int u1 = __builtin_amdgcn_readfirstlane((int)((bl + 1) * W / G));
+  const int Lg = sc.lg;
+  int sidx = __builtin_amdgcn_readfirstlane(
+      (int)(bl - (((long long)(u / Lg) * Lg + 1) * G - 1) / W));
+  const int wave = wave_id();
+  while (u < u1) {                                       // block-uniform
+    const int seg = u / Lg;
+    const int q0 = u - seg * Lg;
+    const int q1 = min(Lg, q0 + (u1 - u));
+    const int g = seg / sc.ntiles, t = seg - g * sc.ntiles;
+    const int lo = g * Lg + q0, n = q1 - q0;
+    const int per = n >> 2, rem = n & 3;
+    const int pbase = lo + wave * per + min(wave, rem);
+    // the lane index is made opaque per segment, so that the compiler does not
+    // hoist the lane's geometry out of this loop and hold it across the probe
+    // loop (it would spill)
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    adj_segment<V, TAIL>(I, tile_of(sc, tmap, t), pbase, pbase + per + (wave < rem ? 1 : 0),
+                         g * sc.sl + sidx, m, k_ckpt, S, lane);
+    __syncthreads();                                     // LDS is staged again next segment
+    u += n;
+    sidx = 0;
   }
 }
 
@@ -1188,6 +1259,27 @@ template <int PW> struct StepKernels<double, PW> {
     adj_body<double, PW, TAIL>(insts, tmap, sc, m, k_ckpt);
   }
 };
+
+// Balanced-schedule adjoint steps (the probe block does not apply: a block's
+// share sets its waves' probes).  Same register budgets as the adjoint above.
+template <bool TAIL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+void k_adj_bal_f(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
+                 int k_ckpt) {
+  adj_bal_body<float, TAIL>(insts, tmap, sc, m, k_ckpt);
+}
+template <bool TAIL>
+__global__ __launch_bounds__(kBlock)
+void k_adj_bal_d(const InstDev* __restrict__ insts, const int4* __restrict__ tmap, Sched sc, int m,
+                 int k_ckpt) {
+  adj_bal_body<double, TAIL>(insts, tmap, sc, m, k_ckpt);
+}
+
+// p[0 .. n) = 0 (a fill kernel rather than a memset node, so graphs replay it)
+__global__ __launch_bounds__(kBlock) void k_zero2(double2* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+    p[i] = make_double2(0.0, 0.0);
+}
 
 // ------------------------------------------------------------- finishing
 // mu[p][m] = sum over tiles (fixed order); also the [R][M] user copy.  Threads
@@ -1535,8 +1627,21 @@ static int sched_mode(int which, int nranges, int req) {
 template <typename V, int PW>
 static hipError_t launch_all(int sched, int which, const InstDev* insts, const int4* tmap,
                              int ntiles, int tiles_x, int nranges, int m, int M, int k_ckpt,
-                             int flag, hipStream_t s) {
-  Sched sc{nranges, 0, ntiles, kSchedTileMajor, tiles_x};
+                             int flag, int4 bal, hipStream_t s) {
+  if (which == 3 && sched == kSchedBalanced && bal.x > 0 && tiles_x > 0) {
+    // balanced adjoint step: bal = (blocks, probes per group, slices per group, groups)
+    const Sched sb{bal.w, bal.x, ntiles, kSchedBalanced, tiles_x, bal.y, bal.z};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    prof::next(flag == 0 ? 3 : 0, m, M, s, e0, e1);
+    auto kern = sizeof(V) == 4 ? (flag ? k_adj_bal_f<true> : k_adj_bal_f<false>)
+                               : (flag ? k_adj_bal_d<true> : k_adj_bal_d<false>);
+    if (e0 != nullptr || e1 != nullptr)
+      hipExtLaunchKernelGGL(kern, dim3(bal.x), dim3(kBlock), 0, s, e0, e1, 0, insts, tmap, sb, m, k_ckpt);
+    else
+      hipLaunchKernelGGL(kern, dim3(bal.x), dim3(kBlock), 0, s, insts, tmap, sb, m, k_ckpt);
+    return hipGetLastError();
+  }
+  Sched sc{nranges, 0, ntiles, kSchedTileMajor, tiles_x, 0, 0};
   int nblocks = ntiles * nranges;
   const int mode = sched_mode(which, nranges, sched);
   if (mode == kSchedStrips || mode == kSchedStripTiles) {
@@ -1603,14 +1708,14 @@ static hipError_t launch_all(int sched, int which, const InstDev* insts, const i
 template <typename V>
 static hipError_t launch_p(int PW, int sched, int which, const InstDev* insts, const int4* tmap,
                            int ntiles, int tiles_x, int nranges, int m, int M, int k_ckpt, int flag,
-                           hipStream_t s) {
+                           int4 bal, hipStream_t s) {
   switch (PW) {
-    case 1: return launch_all<V, 1>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 2: return launch_all<V, 2>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 4: return launch_all<V, 4>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 8: return launch_all<V, 8>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 16: return launch_all<V, 16>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
-    case 32: return launch_all<V, 32>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, s);
+    case 1: return launch_all<V, 1>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, bal, s);
+    case 2: return launch_all<V, 2>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, bal, s);
+    case 4: return launch_all<V, 4>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, bal, s);
+    case 8: return launch_all<V, 8>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, bal, s);
+    case 16: return launch_all<V, 16>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, bal, s);
+    case 32: return launch_all<V, 32>(sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt, flag, bal, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1618,11 +1723,25 @@ static hipError_t launch_p(int PW, int sched, int which, const InstDev* insts, c
 // tiles_x > 0 for a single lattice (tiles_x tiles per row), 0 for a batch (tile table)
 hipError_t launch_cheb(bool fp32, int PW, int sched, int which, const InstDev* insts,
                        const int4* tmap, int ntiles, int tiles_x, int nranges, int m, int M,
-                       int k_ckpt, int flag, hipStream_t s) {
+                       int k_ckpt, int flag, int4 bal, hipStream_t s) {
   return fp32 ? launch_p<float>(PW, sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt,
-                                flag, s)
+                                flag, bal, s)
               : launch_p<double>(PW, sched, which, insts, tmap, ntiles, tiles_x, nranges, m, M, k_ckpt,
-                                 flag, s);
+                                 flag, bal, s);
+}
+
+// Blocks of the balanced adjoint step that one CU holds at once.
+hipError_t adj_bal_blocks_per_cu(bool fp32, int* nb) {
+  *nb = 0;
+  return fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_adj_bal_f<false>, kBlock, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_adj_bal_d<false>, kBlock, 0);
+}
+
+hipError_t launch_zero2(double2* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long nb = std::min<long long>((n + kBlock - 1) / kBlock, 2048);
+  hipLaunchKernelGGL(k_zero2, dim3((unsigned)nb), dim3(kBlock), 0, s, p, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_mom_reduce(const InstDev* insts, int ninst, int maxRM, int M, double* mu_user,

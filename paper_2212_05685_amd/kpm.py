@@ -26,6 +26,7 @@ KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_EBOUNDS, KPM_ENOTSUP, KPM_EWORK
 KPM_ENOCONV = -7
 KPM_ETOOBIG = -8
 KPM_SCHED_DEFAULT, KPM_SCHED_TILE_MAJOR, KPM_SCHED_RANGES, KPM_SCHED_STRIPS, KPM_SCHED_STRIP_TILES = -1, 0, 1, 2, 3
+KPM_SCHED_BALANCED = 4
 KPM_NOALLOC_SCRATCH_BYTES = 64 << 20
 KPM_RMFT_STATS_LEN = 520
 KPM_RMFT_BISECTION, KPM_RMFT_ILLINOIS = 0, 1

@@ -73,8 +73,8 @@ def test_host_validation():
     old = kpm.kpm_set_probe_block(4)
     assert kpm.kpm_set_probe_block(3) == 4       # invalid value leaves the setting
     assert kpm.kpm_set_probe_block(old) == 4
-    # block schedules: -1 (default) .. 2 (strips); anything else is rejected
-    for bad in ((4, 0), (0, 4), (-2, 0), (0, -2)):
+    # block schedules: -1 (default) .. 4 (balanced); anything else is rejected
+    for bad in ((5, 0), (0, 5), (-2, 0), (0, -2)):
         assert kpm._lib.kpm_set_schedule(*bad) == kpm.KPM_EINVAL
     assert kpm._lib.kpm_set_schedule(kpm.KPM_SCHED_STRIPS, kpm.KPM_SCHED_TILE_MAJOR) == kpm.KPM_OK
     assert kpm._lib.kpm_set_schedule(kpm.KPM_SCHED_DEFAULT, kpm.KPM_SCHED_DEFAULT) == kpm.KPM_OK

@@ -1,9 +1,10 @@
 """Kernel configuration choices against the oracle, through the C ABI.
 
 Every block schedule of the recursion kernels (tile-major, probe ranges per
-XCD, strips per XCD) must give the same energy, moments and density matrix:
-the schedule only permutes (tile, probe range) work items over blocks, and
-so reorders FP64 sums at most (App. B, eqs. alpha and dFdH).  The batch
+XCD, strips per XCD, strips tile by tile, and the balanced adjoint split) must
+give the same energy, moments and density matrix: the schedule only permutes
+(tile, probe) work over blocks, and so reorders FP64 sums at most (App. B,
+eqs. alpha and dFdH).  The batch
 autotuner times (probe block, schedule) pairs, remembers its picks per shape
 in the process and in a text file, and a plan configured from that file
 computes the same results as single lattices.
@@ -60,7 +61,7 @@ def _single(cfg, prec, P, sf, sa):
     return host(omega)[0], host(mu), rho
 
 
-SCHEDS = [(sf, sa) for sf in (0, 1, 2, 3) for sa in (0, 1, 2, 3)]
+SCHEDS = [(sf, sa) for sf in (0, 1, 2, 3) for sa in (0, 1, 2, 3, 4)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -91,7 +92,7 @@ def test_range_schedule_falls_back_when_ranges_do_not_divide_8(prec):
 
 def test_set_schedule_rejects_bad_values():
     from paper_2212_05685_amd import kpm
-    for bad in ((4, 0), (0, -2), (7, 7)):
+    for bad in ((5, 0), (0, -2), (7, 7)):
         with pytest.raises(RuntimeError):
             kpm.kpm_set_schedule(*bad)
 
