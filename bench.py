@@ -31,7 +31,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
-PMC_ARGS = "--moments 256 --steps 1 --warmup 1 --no-cpu-baseline --no-fp64-form --no-kernel-timing"
+PMC_ARGS = ("--moments 256 --steps 1 --warmup 1 --no-cpu-baseline --no-fp64-form --no-batched-form --no-rmft-form "
+            "--no-direct-form --no-supercell-form --no-kernel-timing")
 METRIC = "Chebyshev vector-steps/s + HBM GB/s; s per KPM energy+gradient at 100x100"
 
 

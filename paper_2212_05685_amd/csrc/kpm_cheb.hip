@@ -1409,19 +1409,35 @@ __global__ __launch_bounds__(kBlock) void k_map(int N, const double2* __restrict
 
 // Coefficients of the derivative series: with e_M = e_{M+1} = 0,
 // e_{k-1} = e_{k+1} + 2 k C_k (k = M-1 .. 1), D_0 = e_0 / 2, D_k = e_k.
-__global__ void k_direct_coef(const InstDev* __restrict__ insts, int M) {
-  if (threadIdx.x != 0) return;
+// Unrolled, e_{k-1} = sum of T_j = 2 j C_j over j = k, k+2, ... <= M-1: a
+// suffix sum within each parity of j.  One block per instance: thread t sums
+// its contiguous chunk of j per parity, the chunks' totals are combined in
+// LDS (each thread adds the totals above it, top down), and each thread then
+// walks its chunk from the top, writing D.  Fixed order for given M.
+__global__ __launch_bounds__(kBlock) void k_direct_coef(const InstDev* __restrict__ insts, int M) {
+  __shared__ double tot[2][kBlock];
   const InstDev& I = insts[blockIdx.x];
-  double* D = I.musum;
-  double e1 = 0.0, e2 = 0.0;                    // e_{k}, e_{k+1}
-  D[M - 1] = 0.0;
-  for (int k = M - 1; k >= 1; --k) {
-    const double e0 = e2 + 2.0 * (double)k * I.C[k];   // e_{k-1}
-    if (k - 1 >= 1) D[k - 1] = e0;
-    else D[0] = 0.5 * e0;
-    e2 = e1;
-    e1 = e0;
+  const double* __restrict__ C = I.C;
+  double* __restrict__ D = I.musum;
+  const int t = threadIdx.x;
+  const int n = M - 1;                                  // j = 1 .. M-1
+  const int chunk = (n + kBlock - 1) / kBlock;
+  const int j0 = 1 + t * chunk, j1 = min(1 + (t + 1) * chunk, M);   // [j0, j1)
+  double s[2] = {0.0, 0.0};
+  for (int j = j1 - 1; j >= j0; --j) s[j & 1] += 2.0 * (double)j * C[j];
+  tot[0][t] = s[0];
+  tot[1][t] = s[1];
+  __syncthreads();
+  double acc[2] = {0.0, 0.0};
+  for (int u = kBlock - 1; u > t; --u) {
+    acc[0] += tot[0][u];
+    acc[1] += tot[1][u];
   }
+  for (int j = j1 - 1; j >= j0; --j) {
+    acc[j & 1] += 2.0 * (double)j * C[j];
+    D[j - 1] = j == 1 ? 0.5 * acc[1] : acc[j & 1];
+  }
+  if (t == 0) D[M - 1] = 0.0;
 }
 
 // One thread per site i: over the probes with a non-zero entry at (i, a),
@@ -1771,7 +1787,7 @@ hipError_t launch_mom_double(const InstDev* insts, int ninst, int maxRM, int M, 
 }
 
 hipError_t launch_direct_coef(const InstDev* insts, int ninst, int M, hipStream_t s) {
-  hipLaunchKernelGGL(k_direct_coef, dim3(ninst), dim3(64), 0, s, insts, M);
+  hipLaunchKernelGGL(k_direct_coef, dim3(ninst), dim3(kBlock), 0, s, insts, M);
   return hipGetLastError();
 }
 
