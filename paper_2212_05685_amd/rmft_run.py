@@ -117,6 +117,11 @@ def main(argv=None):
     ap.add_argument("--vortex-dx", type=float, default=0.0,
                     help="shift of the seeded vortex centres along x (24.5 puts the 48-wide "
                          "lattice's pair on the x seam, where the gauge's torus holonomy holds them)")
+    ap.add_argument("--color", type=int, default=8,
+                    help="distance coloring of the probes: c x c colours, each split by Nambu component "
+                         "(2 c^2 probes per draw; c must divide both sides)")
+    ap.add_argument("--draws", type=int, default=1,
+                    help="independent Z4 phase draws of the colored probe set, each of weight 1/draws")
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--mix", type=float, default=0.1)
     ap.add_argument("--tol-n", type=float, default=1e-5)
@@ -132,6 +137,12 @@ def main(argv=None):
 
     cfg = wl.scaled(wl.RMFT(args.precision), Lx=args.lx, Ly=args.ly, n_v=args.nv, doping=args.doping,
                     M=args.moments, core=args.core, vortex_dx=args.vortex_dx)
+    if args.color != 8 or args.draws != 1:
+        if args.lx % args.color or args.ly % args.color or args.draws < 1:
+            ap.error("--color must divide both lattice sides and --draws must be positive")
+        base = cfg.probes[0]
+        cfg = wl.scaled(cfg, probes=(wl.ProbeSpec("colored_z4", args.draws, base.seed, args.color, args.color,
+                                                  1, 0, 1.0 / args.draws),))
     kinds = {"unit": kpm.KPM_PROBE_UNIT, "dense_z4": kpm.KPM_PROBE_DENSE_Z4,
              "colored_z4": kpm.KPM_PROBE_COLORED_Z4}
     specs = [kpm.ProbeSpec(kinds[p.kind], p.count, p.seed, p.px, p.py, p.split_nambu, p.first, p.weight)
@@ -171,7 +182,7 @@ def main(argv=None):
     nn, dd = n.cpu().numpy(), dlt.cpu().numpy()
     amp = np.abs(pairing_field(nn, dd, cfg.Lx, cfg.Ly, cfg.n_v))
     summary = {
-        "iterations": len(hist), "seconds": time.perf_counter() - t0, "mu": mu,
+        "iterations": len(hist), "seconds": time.perf_counter() - t0, "mu": mu, "probes": cfg.R,
         "residual_last": hist[-1]["residual"] if hist else None, "status": st,
         "evaluations": int(sum(x["evals"] for x in hist)),
         "hole_density_min_max": [float(1 - nn.max()), float(1 - nn.min())],
