@@ -13,6 +13,9 @@ from checkpoints.  Both sides take their own stencil, bounds and coefficients.
   which takes the lattice-strip schedule over the 8 XCDs and the sparse-row
   adjoint loop, as the benchmark's launches do; two probes per wave give one
   range.  FP64 to 1e-10, FP32 vectors to 1e-5 (relative to max |rho|).
+* The 64 x 64 workload (two vortices, doping 0.15, M = 2048) on all its 192
+  probes (64 colored + 128 dense Z4, each set of weight 1/2), in the tuned
+  launch configuration: FP64 to 1e-10, FP32 vectors to 1e-5.
 * The 48-lattice batch (M = 1024, 64 colored probes each), FP32, replayed as
   one hipGraph as the benchmark does: the smallest and the largest lattice and
   one with four vortices, against O2 on all their probes, to 1e-5.
@@ -63,6 +66,36 @@ def test_c5_rho_against_oracle(c5_oracle, prec, P):
     e_mu = float(np.max(np.abs(mu - ref["mu"])) / np.max(np.abs(ref["mu"])))
     e_rho = H.rel_err(rho, ref["rho"])
     print(f"100x100 {prec} P={P}: |dOmega|/|Omega| = {e_om:.2e}, moments {e_mu:.2e}, "
+          f"max|drho|/max|rho| = {e_rho:.2e}")
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert e_om < tol and e_mu < tol and e_rho < tol
+    del p
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def c3_oracle():
+    cfg = wl.C3()
+    st, a, b, C = H.oracle_inputs(cfg)
+    print(f"oracle: 64x64, M={cfg.M}, {cfg.R} probes ...", flush=True)
+    return cfg, H.plain_parallel(cfg, st, a, b, C)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c3_rho_against_oracle(c3_oracle, prec):
+    cfg, ref = c3_oracle
+    p = problem(cfg, precision=prec)
+    h = p.build_H(*theta_dev(cfg))
+    ab = p.bounds(h)
+    C = p.coefficients(ab)
+    om, mu = p.grand_potential(h, ab, C, want_mu=True)
+    rho = host(p.grand_potential_grad(h, ab, C))
+    assert p.status() == 0
+    om, mu = host(om)[0], host(mu)
+    e_om = abs(om - ref["omega"]) / abs(ref["omega"])
+    e_mu = float(np.max(np.abs(mu - ref["mu"])) / np.max(np.abs(ref["mu"])))
+    e_rho = H.rel_err(rho, ref["rho"])
+    print(f"64x64 {prec}: |dOmega|/|Omega| = {e_om:.2e}, moments {e_mu:.2e}, "
           f"max|drho|/max|rho| = {e_rho:.2e}")
     tol = 1e-10 if prec == "fp64" else 1e-5
     assert e_om < tol and e_mu < tol and e_rho < tol
