@@ -390,7 +390,7 @@ def rmft_form(iters: int, warmup: int):
     pool = OraclePool(host_workers())
     try:
         tasks = _oracle_tasks(cfg, pool.workers)
-        wall = pool.wall(tasks)
+        wall, _ = pool.wall(tasks)
     finally:
         pool.close()
     t_eval_cpu = wall * R / len(tasks)
@@ -618,15 +618,16 @@ def cpu_dense_ed():
 
 def _oracle_probe(task):
     """Pool worker: the oracle's plain FP64 forward recursion + beta adjoint
-    (O2, every vector stored) on one probe, single-threaded; returns seconds."""
+    (O2, every vector stored) on one probe, single-threaded; returns seconds,
+    the probe's moments and its (weighted) grand-potential term."""
     from threadpoolctl import threadpool_limits
 
     from oracle import kpm_plain
     Hs, a, b, r, w, C, Lx, Ly = task
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        kpm_plain.plain_kpm(Hs, a, b, r, w, C, Lx, Ly, want_grad=True)
-        return time.perf_counter() - t0
+        out = kpm_plain.plain_kpm(Hs, a, b, r, w, C, Lx, Ly, want_grad=True)
+        return time.perf_counter() - t0, out["mu"][0], out["omega"]
 
 
 def _oracle_tasks(cfg, nprobe):
@@ -668,10 +669,11 @@ class OraclePool:
         self.pool.map(_noop, range(workers))            # start-up outside the timed samples
 
     def wall(self, tasks, timeout=900):
-        """Wall-clock seconds to run `tasks` (one probe each) on the pool."""
+        """Wall-clock seconds to run `tasks` (one probe each) on the pool, and
+        the per-probe results in task order."""
         t0 = time.perf_counter()
-        self.pool.map_async(_oracle_probe, tasks, chunksize=1).get(timeout)
-        return time.perf_counter() - t0
+        res = self.pool.map_async(_oracle_probe, tasks, chunksize=1).get(timeout)
+        return time.perf_counter() - t0, res
 
     def close(self):
         self.pool.terminate()
@@ -691,11 +693,14 @@ def cpu_baseline(pool):
     bounded sample of one probe per core; its energy + gradient time is the
     sample's wall time scaled by the workload's probe work (probes x sites, M
     fixed), i.e. the model is perfect probe parallelism at `cores` processes.
-    The headline entry is the 100 x 100 workload."""
+    The headline entry is the 100 x 100 workload.  Also returns the oracle's
+    moments and grand-potential terms of the 100 x 100 sample's probes (the
+    first P), for the error of the GPU path against the oracle."""
     import workloads as wl
 
     P = pool.workers
     out = {}
+    c5_sample = []
     for name, cfgs in (("C1_8x8", [wl.C1()]), ("C2_32x32", [wl.C2("fp64")]), ("C3_64x64", [wl.C3()]),
                        ("C4_48_lattices", wl.C4_instances(48)), ("C5_100x100", [wl.C5("fp64")])):
         if len(cfgs) == 1:
@@ -706,7 +711,9 @@ def cpu_baseline(pool):
             sample_work = sum(c.N for c in cfgs[:P])
         total_work = sum(c.R * c.N for c in cfgs)
         M = cfgs[0].M
-        wall = pool.wall(tasks)
+        wall, res = pool.wall(tasks)
+        if name == "C5_100x100":
+            c5_sample = [(mu, om) for _, mu, om in res]
         s_eg = wall * total_work / sample_work
         vsteps = sum(c.R for c in cfgs) * (3 * M - 5)
         out[name] = {"s_per_energy_grad": s_eg, "vector_steps_per_s": vsteps / s_eg,
@@ -723,7 +730,7 @@ def cpu_baseline(pool):
                       f"single-threaded process per core on {P} cores, {c5['sample_wall_s']:.1f} s wall; "
                       f"energy + gradient time = wall x 256 / {c5['sample_probes']} (perfect probe "
                       f"parallelism at {P} processes)",
-            "per_config": out}
+            "per_config": out}, c5_sample
 
 
 def main():
@@ -854,6 +861,18 @@ def main():
         "hbm_GBs_algorithmic_whole_step": ((M - 1) * fwd_bytes + (M - 2) * adj_bytes) / dt / 1e9,
     }
 
+    # per-probe moments of the FP32 path (and its coefficients), for the error
+    # against the oracle on the probes the cpu_baseline leg runs
+    mu32 = C32 = None
+    if not args.no_cpu_baseline and not args.moments:
+        n, chi, dlt = th
+        h = prob.build_H(n, chi, dlt)
+        ab = prob.bounds(h)
+        C = prob.coefficients(ab)
+        _, mu = prob.grand_potential(h, ab, C, want_mu=True)
+        mu32, C32 = mu.cpu().numpy(), C.cpu().numpy()
+        w32 = float(cfg.probes[0].weight)
+
     if not args.no_direct_form and not args.moments:
         result["direct_form"] = direct_form(args.steps, prob, th, dt)
         result["doubling_form"] = doubling_form(args.steps, prob, th)
@@ -892,9 +911,23 @@ def main():
     if not args.no_cpu_baseline:
         pool = OraclePool(host_workers())
         try:
-            result["cpu_baseline"] = cpu_baseline(pool)
+            result["cpu_baseline"], c5_sample = cpu_baseline(pool)
         finally:
             pool.close()
+        if mu32 is not None and c5_sample:
+            e_mu = max(float(np.max(np.abs(mu32[q] - mu)) / np.max(np.abs(mu))) for q, (mu, _) in enumerate(c5_sample))
+            e_om = max(abs(w32 * float(np.dot(C32, mu32[q])) - om) / abs(om) for q, (_, om) in enumerate(c5_sample))
+            result["fp32_vs_oracle"] = {
+                "probes": len(c5_sample),
+                "moments_max_rel_err": e_mu,
+                "omega_term_max_rel_err": e_om,
+                "sample": f"the first {len(c5_sample)} of the 256 probes of the 100x100 workload, those the "
+                          "cpu_baseline leg runs through the oracle (O2, FP64, its own stencil, bounds and "
+                          "coefficients); per probe: max |mu_gpu - mu_oracle| / max |mu_oracle| over the 4096 "
+                          "moments, and the probe's term w C.mu of Omega",
+                "rho": "rho sums all probes on the GPU and is not compared here; against the oracle at this "
+                       "size it is tested in tests/test_gpu_fullsize_oracle.py (FP32 1e-7 with 8 dense probes)",
+            }
         result["cpu_dense_ed"] = cpu_dense_ed()
     print(json.dumps(result), flush=True)
 
