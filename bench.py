@@ -52,16 +52,23 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
+def halves_used(R: int, N: int, streams: int) -> bool:
+    """Whether a single-lattice call runs as two probe halves on two streams
+    (kpm_set_streams: 2 forced, 1 never, 0 the library's automatic rule)."""
+    return streams == 2 or (streams == 0 and R >= 128 and R * N >= 2 ** 19)
+
+
 def traffic_record(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    """HBM bytes per recursion step (all launches of one step) from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_c5_fp32_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("hbm_bytes_per_step")
 
 
 def _pmc_rows(d, counter):
@@ -96,6 +103,12 @@ def traffic_summary(base: str, copy_bytes: int) -> None:
     kib_f = max(v for rows in cf.values() for _, v in rows)   # the copy is the largest dispatch of its run
     kib_w = max(v for rows in cw.values() for _, v in rows)
     f_fetch, f_write = copy_bytes / (kib_f * 1024.0), copy_bytes / (kib_w * 1024.0)
+    import workloads as wl
+    c5 = wl.C5("fp32")
+    R = sum(p.nprobes() for p in c5.probes)
+    # the counter runs use the library's default streams: a step is then the two
+    # equal probe halves' launches (same kernel, same grid)
+    per_step = 2 if halves_used(R, c5.N, 0) else 1
     out = {}
     # the plain step launches (not the checkpoint-storing forward nor the last adjoint step)
     for short, tags in (("k_adj", (">::adj<false>(",)), ("k_fwd", (">::fwdp<false, false>(",))):
@@ -117,8 +130,11 @@ def traffic_summary(base: str, copy_bytes: int) -> None:
             "copy_calibration": {"bytes": copy_bytes, "FETCH_SIZE_KiB": kib_f, "WRITE_SIZE_KiB": kib_w,
                                  "fetch_factor": f_fetch, "write_factor": f_write},
             "hbm_bytes_per_launch": fk * 1024.0 * f_fetch + wk * 1024.0 * f_write,
+            "launches_per_step": per_step,
+            "hbm_bytes_per_step": per_step * (fk * 1024.0 * f_fetch + wk * 1024.0 * f_write),
             "note": "bytes leaving L2 for the memory fabric (Infinity Cache hits included), "
-                    "scaled by what the same counters read for a plain copy of known size",
+                    "scaled by what the same counters read for a plain copy of known size; a step of "
+                    "the 100x100 workload is the launches of its two probe halves (128 probes each)",
             "commands": [
                 "cd /tmp && export TMPDIR=/tmp",
                 "export KPM_TUNE_CACHE=<file>   # the kernel configuration tuned at the benchmark's M, "
@@ -138,7 +154,7 @@ def traffic_summary(base: str, copy_bytes: int) -> None:
         path = os.path.join(ROOT, "profiles", f"{short}_c5_fp32_traffic.json")
         with open(path, "w") as fh:
             json.dump(rec, fh, indent=1)
-        print(f"{path}: {rec['hbm_bytes_per_launch'] / 1e6:.1f} MB per launch")
+        print(f"{path}: {rec['hbm_bytes_per_step'] / 1e6:.1f} MB per step")
 
 
 def make_problem(cfg, precision):
@@ -756,6 +772,9 @@ def main():
                     help="profiling runs only: override M (same launch shape, fewer steps)")
     ap.add_argument("--probe-block", type=int, default=0,
                     help="probes per wave of the recursion kernels (0 = library default)")
+    ap.add_argument("--streams", type=int, default=0, choices=(0, 1, 2),
+                    help="kpm_set_streams: 0 automatic (probe halves on two streams for this "
+                         "workload), 1 one stream, 2 halves")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES (counter calibration) and exit")
     ap.add_argument("--traffic-summary", default="", metavar="DIR",
@@ -788,6 +807,9 @@ def main():
     if args.probe_block:
         from paper_2212_05685_amd import kpm
         kpm.kpm_set_probe_block(args.probe_block)
+    if args.streams:
+        from paper_2212_05685_amd import kpm
+        kpm.kpm_set_streams(args.streams)
     if args.only_batched_form:
         print(json.dumps({"batched_form": batched_form(args.steps)}), flush=True)
         return
@@ -815,6 +837,13 @@ def main():
     fwd_avg_s = fwd_ms / max(n_fwd, 1) * 1e-3
     achieved = adj_bytes / adj_avg_s / 1e9
     traffic = traffic_record("k_adj")
+    if halves_used(R, N, args.streams):
+        launch_note = (f"one recursion step of all {R} probes: the launches of the two probe halves "
+                       f"({(R + 1) // 2} and {R // 2} probes) that run side by side on two streams; "
+                       "timed as runs of 16 consecutive steps on the caller's stream while the other "
+                       "half runs beside them, so the average is the time per step of both halves")
+    else:
+        launch_note = f"one launch over all {R} probes on one stream"
 
     result = {
         "metric": METRIC,
@@ -852,11 +881,12 @@ def main():
             "algorithmic_bytes_per_launch": adj_bytes,
             "avg_launch_us": adj_avg_s * 1e6,
             "launches_timed": n_adj,
+            "launch": launch_note,
         },
         "forward_kernel": {
             "kernel": "k_fwd (forward step)", "algorithmic_bytes_per_launch": fwd_bytes,
             "avg_launch_us": fwd_avg_s * 1e6, "achieved_GBs": fwd_bytes / fwd_avg_s / 1e9,
-            "launches_timed": n_fwd,
+            "launches_timed": n_fwd, "launch": launch_note,
         },
         "hbm_GBs_algorithmic_whole_step": ((M - 1) * fwd_bytes + (M - 2) * adj_bytes) / dt / 1e9,
     }

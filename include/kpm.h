@@ -380,6 +380,26 @@ int kpm_batch_tuning(const void* plan, int32_t* out);
  * across processes. */
 int32_t kpm_set_probe_block(int32_t probes_per_thread);
 
+/* Streams of the single-lattice energy, gradient and moment calls
+ * (kpm_moments, kpm_grand_potential, kpm_grand_potential_grad,
+ * kpm_density_matrix): 1, everything on the caller's stream; 2, the probes in
+ * two halves (ceil(R/2) and floor(R/2) probes) whose recursions run side by
+ * side on the caller's stream and on a second stream of the device that the
+ * library creates once (default priority), with their step launches
+ * interleaved, so that one half's blocks fill the slots another launch leaves
+ * idle; Omega, the moments and rho are then reduced over both halves on the
+ * caller's stream, which waits for the second stream before it returns to
+ * its own work; 0 (default), automatic: halves when R >= 128 and
+ * R N >= 2^19 (fewer probes per half leave the chip short of work).
+ * A stream being captured into a graph always runs on one stream, and a
+ * gradient follows the layout of the forward call it completes.  Halves
+ * change results only through the order of floating-point sums (FP64 sums
+ * of the moments and the partial sums, 1e-14 relative; the FP32 per-wave
+ * sums of the adjoint, 1e-7).  The halves are tuned as a shape of R/2 probes.
+ * Process-wide; returns the previous value (values outside 0..2 leave the
+ * setting unchanged). */
+int32_t kpm_set_streams(int32_t n);
+
 /* Block schedules of the recursion kernels (how (tile, probe range) work
  * items map to blocks, and so to the 8 XCDs that blocks are dealt to in
  * turn): KPM_SCHED_TILE_MAJOR, tiles in order with the probe range fastest;

@@ -48,6 +48,7 @@ hipError_t launch_ldos(const InstDev*, int, int, const double*, int, double*, hi
 hipError_t launch_rho_direct(const InstDev*, const int2*, int, hipStream_t);
 hipError_t profile_begin(int);
 hipError_t profile_end(double*, int*, double*, int*);
+void profile_secondary(hipStream_t);
 
 // Sets every instance's status word (a kernel, not a memset, so that the
 // sequence can be captured in a hipGraph).
@@ -171,6 +172,10 @@ std::mutex g_mu;
 int g_probe_block = 0;   // 0 = automatic
 int g_sched_f = KPM_SCHED_DEFAULT, g_sched_a = KPM_SCHED_DEFAULT;   // single-lattice schedules
 
+// Partial-sum slices of an instance's buffer: ceil(R / 4) ranges of P = 1,
+// plus one for probe halves.
+int gpart_slices(int R) { return (R + kWaves - 1) / kWaves + 1; }
+
 // ------------------------------------------------------------ instance layout
 struct Sizes {
   int N, R, M, nchunk, ntile;
@@ -195,8 +200,9 @@ Sizes sizes(const kpm_lattice* L, int R, int M, int k, bool fp32, bool fwd_only 
   z.mom = align_up(sizeof(double) * (size_t)M * R * z.ntile);
   z.musum = align_up(sizeof(double) * (size_t)M * R);
   // one [19][N] FP64 slice per adjoint probe range; a range holds kWaves * P
-  // probes, so P = 1 (the smallest block) needs the most ranges
-  z.gpart = align_up(sizeof(double) * 2 * kNent * (size_t)z.N * (size_t)((R + kWaves - 1) / kWaves));
+  // probes, so P = 1 (the smallest block) needs the most ranges, and probe
+  // halves one more (their ranges round up separately)
+  z.gpart = align_up(sizeof(double) * 2 * kNent * (size_t)z.N * (size_t)gpart_slices(R));
   z.pcode = align_up((size_t)R * z.N);
   z.pw = align_up(sizeof(double) * (size_t)R);
   z.sink = align_up(4096);
@@ -377,13 +383,15 @@ int upload(Ctx& c, hipStream_t s) {
 }
 
 // Single-lattice calls: copy the tables into the per-workspace host store first.
-int upload_single(Ctx& c, const void* ws, hipStream_t s) {
+// extra: instances uploaded after the lattice's own (the probe halves).
+int upload_single(Ctx& c, const void* ws, hipStream_t s, const std::vector<InstDev>* extra = nullptr) {
   std::lock_guard<std::mutex> lk(g_tables_mu);
   HostTables& t = g_tables[ws];
   // the previous upload from this store may still be reading it
   if (t.done) KPM_HIP(hipEventSynchronize(t.done));
   else KPM_HIP(hipEventCreateWithFlags(&t.done, hipEventDisableTiming));
   t.inst = c.inst;
+  if (extra) t.inst.insert(t.inst.end(), extra->begin(), extra->end());
   t.cmap = c.cmap;
   t.tmap = c.tmap;
   t.last_use = ++g_tables_clock;
@@ -437,7 +445,8 @@ int run_adjoint(const Ctx& c, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ single lattice
-// Workspace = [InstDev][cmap][instance buffers].
+// Workspace = [InstDev x 3][cmap][tmap][instance buffers]: the lattice's
+// instance, then the instances of its two probe halves (see Halves).
 struct WsLayout {
   size_t off_inst, off_cmap, off_tmap, off_buf, total;
 };
@@ -445,7 +454,7 @@ struct WsLayout {
 WsLayout ws_layout(const Sizes& z) {
   WsLayout w{};
   size_t o = 0;
-  w.off_inst = o; o = align_up(o + sizeof(InstDev));
+  w.off_inst = o; o = align_up(o + 3 * sizeof(InstDev));
   w.off_cmap = o; o = align_up(o + sizeof(int2) * z.nchunk);
   w.off_tmap = o; o = align_up(o + sizeof(int4) * z.ntile);
   w.off_buf = o;  o += inst_bytes(z);
@@ -459,6 +468,7 @@ struct FwdSig {
   const double* C;
   int M, R, prec, k;
   bool consumed;   // an adjoint has run: the alpha ping-pong holds alpha_0, alpha_1
+  bool split;      // the forward ran as two probe halves (their buffer layout)
 };
 std::map<const void*, FwdSig> g_fwd;
 
@@ -783,6 +793,227 @@ int tune_single(Ctx& c, const void* ws, hipStream_t s) {
   return st;
 }
 
+// ------------------------------------------------------------ probe halves
+// The probes of a single lattice can run as two halves on two streams, the
+// caller's and a second one per device, with their step launches
+// interleaved.  A launch of one half leaves block slots idle while its last
+// blocks finish, and the other half's blocks take them; each half keeps the
+// probe lockstep of its own blocks.  Measured on the 100 x 100 workload
+// (M = 4096, 256 probes, FP32): 281 ms per energy + gradient for two
+// 128-probe halves side by side, 308 ms for the 256 probes on one stream.
+//
+// A half is an instance over its contiguous share of the probe-indexed
+// buffers: probes [poff, poff + R_h) of the vectors, code table, weights and
+// reduced moments; its own [S][R_h][N] share of the checkpoints and
+// [M][ntile][R_h] share of the moment partials; its own partial-sum slices
+// (half 1's after half 0's).  The lattice's instance then reduces over both:
+// Omega over all moments, rho over all slices.
+int g_streams = 0;                  // 0 automatic, 1 one stream, 2 probe halves
+
+struct Halves {
+  bool on = false;
+  Ctx h[2];
+  std::vector<InstDev> inst() const { return {h[0].inst[0], h[1].inst[0]}; }
+};
+
+// The second stream of the current device (created once, default priority).
+int secondary_stream(hipStream_t* out) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  KPM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it == streams.end()) {
+    hipStream_t st = nullptr;
+    KPM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    it = streams.emplace(dev, st).first;
+  }
+  *out = it->second;
+  return KPM_OK;
+}
+
+// Whether a call runs as probe halves: requested (kpm_set_streams(2)), or
+// automatically when each half still keeps the chip busy: R >= 128 and
+// R N >= 2^19 site-probes.  Measured (ms per energy + gradient, one stream
+// against halves): 100 x 100, R = 256, 75.8 / 69.3 (FP32) and 177.7 / 170.5
+// (FP64) at M = 1024; 48 x 96, R = 128, 26.0 / 24.1; 64 x 64, R = 192,
+// 60.7 / 59.1; 32 x 32, R = 2048, 16.8 / 16.8; but 64 x 64, R = 64,
+// 15.3 / 17.0.  Never while the stream is being captured.
+bool split_wanted(const Ctx& c, hipStream_t s) {
+  int mode;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    mode = g_streams;
+  }
+  const InstDev& F = c.inst[0];
+  if (mode == 1 || F.R < 2) return false;
+  if (mode == 0 && (F.R < 128 || (long long)F.R * F.N < (1LL << 19))) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+}
+
+// The two half contexts of c (ceil(R/2) and floor(R/2) probes) with c's probe
+// blocks and schedules; false (hv.on stays false) when their partial-sum
+// slices do not fit the lattice's buffer (gpart_slices).
+bool build_halves(Ctx& c, Halves& hv) {
+  hv.on = false;
+  const InstDev& F = c.inst[0];
+  const int R0 = (F.R + 1) / 2;
+  const size_t rec = c.fp32 ? 16 : 32;
+  const size_t nslots = 2 * (size_t)((c.M - 1) / c.k + 1);
+  for (int q = 0; q < 2; ++q) {
+    Ctx& h = hv.h[q];
+    h = c;
+    h.want_tune = false;
+    InstDev& I = h.inst[0];
+    const size_t off = q ? R0 : 0;
+    I.R = q ? F.R - R0 : R0;
+    I.poff = (int)off;
+    for (int j = 0; j < 2; ++j) {
+      I.A[j] = static_cast<char*>(F.A[j]) + off * F.N * rec;
+      I.G[j] = static_cast<char*>(F.G[j]) + off * F.N * rec;
+    }
+    I.ckpt = static_cast<char*>(F.ckpt) + nslots * off * F.N * rec;
+    I.mom = F.mom + (size_t)c.M * F.nchunk * off;
+    I.musum = F.musum + off * c.M;
+    I.pcode = F.pcode + off * F.N;
+    I.pw = F.pw + off;
+    h.Rmax = I.R;
+    h.d_inst = c.d_inst + 1 + q;
+    set_npb(h);
+  }
+  const int npb0 = hv.h[0].inst[0].npb, npb1 = hv.h[1].inst[0].npb;
+  if (npb0 + npb1 > gpart_slices(F.R)) return false;
+  hv.h[1].inst[0].gpart = F.gpart + (size_t)npb0 * kNent * F.N;
+  c.inst[0].npb = npb0 + npb1;
+  hv.on = true;
+  return true;
+}
+
+// Configures the halves: with the automatic probe block, the picks remembered
+// for the half shape, else (allow_timing: the first energy evaluation of the
+// shape) the tuner's run on half 0; then the halves are built again with
+// those picks.  The call runs on one stream if they no longer fit.
+int setup_halves(Ctx& c, Halves& hv, const void* ws, hipStream_t s, bool allow_timing) {
+  if (!build_halves(c, hv)) return KPM_OK;
+  int P;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    P = g_probe_block;
+  }
+  if (P != 0) return KPM_OK;
+  Ctx& h0 = hv.h[0];
+  Tune t{};
+  int src = 0;
+  if (!tune_lookup(shape_key(h0), t, &src)) {
+    if (!allow_timing) return KPM_OK;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_fwd.erase(ws);
+    }
+    const int st = tune_ctx(h0, ws, s, &src);
+    if (st != KPM_OK) return st;
+    t = Tune{h0.Pf, h0.Sf, h0.Pa, h0.Sa};
+  }
+  apply_tune(c, t);
+  c.want_tune = false;
+  build_halves(c, hv);
+  return KPM_OK;
+}
+
+// Fork/join between the caller's stream and the second stream; while forked,
+// the second stream's launches are not timed by the profiler.
+struct Fork {
+  hipStream_t s2 = nullptr;
+  hipEvent_t e = nullptr;
+  ~Fork() {
+    profile_secondary(nullptr);
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+
+int fork_from(Fork& f, hipStream_t s) {
+  const int st = secondary_stream(&f.s2);
+  if (st != KPM_OK) return st;
+  KPM_HIP(hipEventCreateWithFlags(&f.e, hipEventDisableTiming));
+  KPM_HIP(hipEventRecord(f.e, s));
+  KPM_HIP(hipStreamWaitEvent(f.s2, f.e, 0));
+  profile_secondary(f.s2);
+  return KPM_OK;
+}
+
+int join_to(Fork& f, hipStream_t s) {
+  profile_secondary(nullptr);
+  KPM_HIP(hipEventRecord(f.e, f.s2));
+  KPM_HIP(hipStreamWaitEvent(s, f.e, 0));
+  return KPM_OK;
+}
+
+// Forward recursion of both halves (alpha_0 ... alpha_{M-1}), then their
+// moment reductions (mu_user: the caller's [R][M] copy, or null).
+int run_forward_split(const Ctx& c, const Halves& hv, bool ckpt, double* mu_user, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, c.d_inst, 1, 0);
+  KPM_HIP(hipGetLastError());
+  KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
+  Fork f;
+  int st = fork_from(f, s);
+  if (st != KPM_OK) return st;
+  const hipStream_t ss[2] = {s, f.s2};
+  for (int q = 0; q < 2; ++q) {
+    const Ctx& h = hv.h[q];
+    KPM_HIP(launch_cheb(h.fp32, h.Pf, h.Sf, 0, h.d_inst, h.d_tmap, h.ntl(), h.tpx(), h.nrf(), 0, h.M, h.k,
+                        ckpt ? 1 : 0, h.bal, ss[q]));
+  }
+  for (int m = 0; m + 1 < c.M; ++m)
+    for (int q = 0; q < 2; ++q) {
+      const Ctx& h = hv.h[q];
+      KPM_HIP(launch_cheb(h.fp32, h.Pf, h.Sf, 1, h.d_inst, h.d_tmap, h.ntl(), h.tpx(), h.nrf(), m, h.M,
+                          h.k, ckpt ? 1 : 0, h.bal, ss[q]));
+    }
+  if ((st = join_to(f, s)) != KPM_OK) return st;
+  for (int q = 0; q < 2; ++q) {
+    const Ctx& h = hv.h[q];
+    double* mu = mu_user ? mu_user + (size_t)h.inst[0].poff * c.M : nullptr;
+    if ((st = run_moments(h, mu, s)) != KPM_OK) return st;
+  }
+  return KPM_OK;
+}
+
+// Adjoint of both halves into their partial-sum slices, then rho from all slices.
+int run_adjoint_split(const Ctx& c, const Halves& hv, hipStream_t s) {
+  Fork f;
+  int st = fork_from(f, s);
+  if (st != KPM_OK) return st;
+  const hipStream_t ss[2] = {s, f.s2};
+  for (int q = 0; q < 2; ++q)
+    if ((st = adj_init(hv.h[q], ss[q])) != KPM_OK) return st;
+  for (int m = c.M - 3; m >= 0; --m)
+    for (int q = 0; q < 2; ++q) {
+      const Ctx& h = hv.h[q];
+      KPM_HIP(launch_cheb(h.fp32, h.Pa, h.Sa, 3, h.d_inst, h.d_tmap, h.ntl(), h.tpx(), h.nra(), m, h.M, h.k,
+                          0, h.bal, ss[q]));
+    }
+  for (int q = 0; q < 2; ++q) {
+    const Ctx& h = hv.h[q];
+    KPM_HIP(launch_cheb(h.fp32, h.Pa, h.Sa, 3, h.d_inst, h.d_tmap, h.ntl(), h.tpx(), h.nra(), 0, h.M, h.k, 1,
+                        h.bal, ss[q]));
+  }
+  if ((st = join_to(f, s)) != KPM_OK) return st;
+  KPM_HIP(launch_rho(c.d_inst, c.d_cmap, c.nch(), s));
+  return KPM_OK;
+}
+
+// restore_alpha for both halves (a second adjoint after one forward).
+int restore_alpha_split(const Halves& hv, hipStream_t s) {
+  Fork f;
+  int st = fork_from(f, s);
+  if (st != KPM_OK) return st;
+  if ((st = restore_alpha(hv.h[0], s)) != KPM_OK) return st;
+  if ((st = restore_alpha(hv.h[1], f.s2)) != KPM_OK) return st;
+  return join_to(f, s);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ batch plans
@@ -937,9 +1168,16 @@ int kpm_moments(const kpm_lattice* lat, const double* h, const double* ab, const
   int st = prepare_single(c, lat, h, ab, probes, M, nullptr, precision, ckpt_k, ws, ws_bytes);
   if (st != KPM_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
-  if ((st = run_forward(c, false, M, s)) != KPM_OK) return st;
-  if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
+  Halves hv;
+  if (split_wanted(c, s) && (st = setup_halves(c, hv, ws, s, false)) != KPM_OK) return st;
+  const std::vector<InstDev> ex = hv.on ? hv.inst() : std::vector<InstDev>();
+  if ((st = upload_single(c, ws, s, hv.on ? &ex : nullptr)) != KPM_OK) return st;
+  if (hv.on) {
+    if ((st = run_forward_split(c, hv, false, mu, s)) != KPM_OK) return st;
+  } else {
+    if ((st = run_forward(c, false, M, s)) != KPM_OK) return st;
+    if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
+  }
   std::lock_guard<std::mutex> lk(g_mu);
   g_fwd.erase(ws);
   return KPM_OK;
@@ -985,13 +1223,21 @@ int kpm_grand_potential(const kpm_lattice* lat, const double* h, const double* a
   if (st != KPM_OK) return st;
   c.inst[0].omega = omega;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
-  if ((st = tune_single(c, ws, s)) != KPM_OK) return st;
-  if ((st = run_forward(c, true, M, s)) != KPM_OK) return st;
-  if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
+  Halves hv;
+  if (split_wanted(c, s) && (st = setup_halves(c, hv, ws, s, true)) != KPM_OK) return st;
+  if (hv.on) {
+    const std::vector<InstDev> ex = hv.inst();
+    if ((st = upload_single(c, ws, s, &ex)) != KPM_OK) return st;
+    if ((st = run_forward_split(c, hv, true, mu, s)) != KPM_OK) return st;
+  } else {
+    if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+    if ((st = tune_single(c, ws, s)) != KPM_OK) return st;
+    if ((st = run_forward(c, true, M, s)) != KPM_OK) return st;
+    if ((st = run_moments(c, mu, s)) != KPM_OK) return st;
+  }
   KPM_HIP(launch_omega(c.d_inst, 1, M, s));
   std::lock_guard<std::mutex> lk(g_mu);
-  g_fwd[ws] = FwdSig{h, ab, C, M, c.Rmax, precision, ckpt_k, false};
+  g_fwd[ws] = FwdSig{h, ab, C, M, c.Rmax, precision, ckpt_k, false, hv.on};
   return KPM_OK;
 }
 
@@ -1003,7 +1249,7 @@ int kpm_grand_potential_grad(const kpm_lattice* lat, const double* h, const doub
   Ctx c;
   int st = prepare_single(c, lat, h, ab, probes, M, C, precision, ckpt_k, ws, ws_bytes);
   if (st != KPM_OK) return st;
-  bool consumed;
+  bool consumed, split;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_fwd.find(ws);
@@ -1013,15 +1259,27 @@ int kpm_grand_potential_grad(const kpm_lattice* lat, const double* h, const doub
         f.k != ckpt_k)
       return KPM_EWORKSPACE;
     consumed = f.consumed;
+    split = f.split;
   }
   c.inst[0].rho = reinterpret_cast<double2*>(rho);
   c.inst[0].omega_bar = omega_bar;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
-  // a second adjoint after one forward (e.g. two backward passes): the first
-  // one left alpha_0, alpha_1 in the ping-pong buffers
-  if (consumed && (st = restore_alpha(c, s)) != KPM_OK) return st;
-  if ((st = run_adjoint(c, s)) != KPM_OK) return st;
+  // the adjoint follows the forward's layout: probe halves if it ran as halves
+  Halves hv;
+  if (split) {
+    if ((st = setup_halves(c, hv, ws, s, false)) != KPM_OK) return st;
+    if (!hv.on) return KPM_EWORKSPACE;
+    const std::vector<InstDev> ex = hv.inst();
+    if ((st = upload_single(c, ws, s, &ex)) != KPM_OK) return st;
+    // a second adjoint after one forward (e.g. two backward passes): the first
+    // one left alpha_0, alpha_1 in the ping-pong buffers
+    if (consumed && (st = restore_alpha_split(hv, s)) != KPM_OK) return st;
+    if ((st = run_adjoint_split(c, hv, s)) != KPM_OK) return st;
+  } else {
+    if ((st = upload_single(c, ws, s)) != KPM_OK) return st;
+    if (consumed && (st = restore_alpha(c, s)) != KPM_OK) return st;
+    if ((st = run_adjoint(c, s)) != KPM_OK) return st;
+  }
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_fwd.find(ws);
   if (it != g_fwd.end()) it->second.consumed = true;
@@ -1153,6 +1411,13 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread) {
   std::lock_guard<std::mutex> lk(g_mu);
   int32_t old = g_probe_block;
   if (probes_per_thread == 0 || valid_P(probes_per_thread)) g_probe_block = probes_per_thread;
+  return old;
+}
+
+int32_t kpm_set_streams(int32_t n) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int32_t old = g_streams;
+  if (n >= 0 && n <= 2) g_streams = n;
   return old;
 }
 

@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const InstDev* __restrict__ ins
   const int pend = min(pbase + PW, I.R);
   for (int p = pbase; p < pend; ++p) {
     double w;
-    const int k = probe_code(I, PL, L, p, w);
+    const int k = probe_code(I, PL, L, p + I.poff, w);
     const Cx<V> r = phase_times<V>(k, V(1));
     const unsigned rec = (unsigned)(p * I.N) + L.site;
     const unsigned nib = k >= 0 ? (8u | (unsigned)k) : 0u;
@@ -1513,7 +1513,12 @@ __global__ __launch_bounds__(kBlock) void k_rho_direct(const InstDev* __restrict
 // comes before its last launch: another kernel, a step that is not the next
 // one, another stream.  Kernels launched outside these launchers (moment
 // reduction, copies) only follow a complete loop, whose runs have closed.
+// The launches of a probe half on the second stream (the secondary stream of
+// the launching thread) are neither timed nor counted as interruptions: a run
+// on the caller's stream then covers steps whose other half runs beside it,
+// so its launch average is the time per step of both halves.
 namespace prof {
+thread_local hipStream_t secondary = nullptr;
 constexpr int kWindow = 16;
 std::mutex mu;
 bool on = false;
@@ -1539,6 +1544,7 @@ void abandon() {
 // kind (1, 3, or 0 for any other launch), m its step, M the moment count.
 void next(int k, int m, int M, hipStream_t s, hipEvent_t& a, hipEvent_t& b) {
   a = b = nullptr;
+  if (secondary != nullptr && s == secondary) return;
   std::lock_guard<std::mutex> lk(mu);
   if (!on) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1586,6 +1592,9 @@ void next(int k, int m, int M, hipStream_t s, hipEvent_t& a, hipEvent_t& b) {
   ++used;
 }
 }  // namespace prof
+
+// The calling thread's second stream of probe halves (null: none).
+void profile_secondary(hipStream_t s) { prof::secondary = s; }
 
 hipError_t profile_begin(int every) {
   std::lock_guard<std::mutex> lk(prof::mu);

@@ -41,7 +41,9 @@ struct ModelDev {
 };
 
 struct InstDev {
-  int Lx, Ly, N, R, nchunk, npb, ngroups, pad0;
+  // poff: global index of the instance's first probe (a probe half of a
+  // single lattice; 0 otherwise), for the probe hash of k_init
+  int Lx, Ly, N, R, nchunk, npb, ngroups, poff;
   GroupDev g[kMaxGroups];
   const double2* h;
   const double* ab;

@@ -43,7 +43,7 @@ EXPORTS = (
     "kpm_strerror", "kpm_rmft_update", "kpm_rmft_workspace_size", "kpm_rmft_iterate",
     "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
     "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_build_H_sdw_vjp", "kpm_bloch_H", "kpm_gutzwiller_weights", "kpm_supercell_workspace_size",
-    "kpm_supercell_ldos", "kpm_moments_noalloc", "kpm_set_schedule", "kpm_batch_tuning",
+    "kpm_supercell_ldos", "kpm_moments_noalloc", "kpm_set_schedule", "kpm_set_streams", "kpm_batch_tuning",
 )
 
 
@@ -120,6 +120,7 @@ def _load():
         "kpm_batch_destroy": (c_int32, [P]),
         "kpm_set_probe_block": (c_int32, [c_int32]),
         "kpm_set_schedule": (c_int32, [c_int32, c_int32]),
+        "kpm_set_streams": (c_int32, [c_int32]),
         "kpm_batch_tuning": (c_int32, [P, P]),
         "kpm_profile_begin": (c_int32, [c_int32]),
         "kpm_profile_end": (c_int32, [POINTER(c_double), POINTER(c_int32), POINTER(c_double),
@@ -376,6 +377,11 @@ def kpm_status_read(ws, stream=None) -> int:
 
 def kpm_set_probe_block(probes_per_thread: int) -> int:
     return int(_lib.kpm_set_probe_block(probes_per_thread))
+
+
+def kpm_set_streams(n: int) -> int:
+    """0 automatic, 1 one stream, 2 probe halves on two streams; returns the previous value."""
+    return int(_lib.kpm_set_streams(n))
 
 
 def kpm_set_schedule(fwd: int, adj: int) -> None:
