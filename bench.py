@@ -55,7 +55,7 @@ def kernel_source_hash() -> str:
 def halves_used(R: int, N: int, streams: int) -> bool:
     """Whether a single-lattice call runs as two probe halves on two streams
     (kpm_set_streams: 2 forced, 1 never, 0 the library's automatic rule)."""
-    return streams == 2 or (streams == 0 and R >= 128 and R * N >= 2 ** 19)
+    return streams == 2 or (streams == 0 and R >= 128 and R * N >= 2 ** 20)
 
 
 def traffic_record(kernel: str):
