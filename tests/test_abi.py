@@ -78,6 +78,10 @@ def test_host_validation():
         assert kpm._lib.kpm_set_schedule(*bad) == kpm.KPM_EINVAL
     assert kpm._lib.kpm_set_schedule(kpm.KPM_SCHED_STRIPS, kpm.KPM_SCHED_TILE_MAJOR) == kpm.KPM_OK
     assert kpm._lib.kpm_set_schedule(kpm.KPM_SCHED_DEFAULT, kpm.KPM_SCHED_DEFAULT) == kpm.KPM_OK
+    # streams: 0 (automatic) .. 2 (probe halves); other values leave the setting
+    old_streams = kpm.kpm_set_streams(2)
+    assert kpm.kpm_set_streams(3) == 2 and kpm.kpm_set_streams(-1) == 2
+    assert kpm.kpm_set_streams(old_streams) == 2
     out = (ctypes.c_int32 * 5)()
     assert kpm._lib.kpm_batch_tuning(None, out) == kpm.KPM_EINVAL
 

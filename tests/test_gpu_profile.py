@@ -21,15 +21,21 @@ def _reset():
     kpm.kpm_set_probe_block(4)
     yield
     kpm.kpm_set_probe_block(0)
+    kpm.kpm_set_streams(0)
     kpm.kpm_profile_end()
 
 
+@pytest.mark.parametrize("streams", [1, 2])
 @pytest.mark.parametrize("every", [1, 8, 32])
-def test_runs_cover_whole_windows(every):
+def test_runs_cover_whole_windows(every, streams):
     """Forward launches m = 0 .. M-2 and adjoint launches m = M-3 .. 0: a run
     of min(16, every) launches starts at every `every`-th launch of each kind
-    and only complete runs count."""
+    and only complete runs count.  With probe halves on two streams only the
+    caller's stream is timed, and the second stream's launches, interleaved
+    with them, neither count nor break a run: the counts are those of one
+    stream."""
     from paper_2212_05685_amd import kpm
+    kpm.kpm_set_streams(streams)
     M = 101
     cfg = _cfg(M)
     p = problem(cfg, precision="fp32")
