@@ -390,8 +390,7 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread);
  * idle; Omega, the moments and rho are then reduced over both halves on the
  * caller's stream, which waits for the second stream before it returns to
  * its own work; 0 (default), automatic: halves when R >= 128 and
- * R N >= 2^20 (fewer probes per half leave the chip short of work, and
- * shorter launches leave the host short of time to issue twice as many).
+ * R N >= 2^19 (with fewer probes a half leaves the chip short of work).
  * A stream being captured into a graph always runs on one stream, and a
  * gradient follows the layout of the forward call it completes.  Halves
  * change results only through the order of floating-point sums (FP64 sums

@@ -834,15 +834,13 @@ int secondary_stream(hipStream_t* out) {
 }
 
 // Whether a call runs as probe halves: requested (kpm_set_streams(2)), or
-// automatically when each half still keeps the chip busy and its launches
-// are long enough for the host to issue twice as many: R >= 128 and
-// R N >= 2^20 site-probes.  Measured (ms per energy + gradient, one stream
+// automatically when each half still keeps the chip busy: R >= 128 and
+// R N >= 2^19 site-probes.  Measured (ms per energy + gradient, one stream
 // against halves): 100 x 100, R = 256, 75.8 / 69.3 (FP32) and 177.7 / 170.5
-// (FP64) at M = 1024; 32 x 32, R = 2048, 16.8 / 16.8; 64 x 64, R = 192,
-// 60.7 / 59.1; 64 x 64, R = 64, 15.3 / 17.0; 48 x 96, R = 128, 26.0 / 24.1
-// alone, but 29.6 / 30.6 per evaluation inside the self-consistent loop,
-// where the halves' 8-16 us launches outrun the host.  Never while the
-// stream is being captured.
+// (FP64) at M = 1024; 48 x 96, R = 128, 26.0 / 24.1 (and 26.0 / 24.6 per
+// evaluation inside the self-consistent loop); 64 x 64, R = 192,
+// 60.7 / 59.1; 32 x 32, R = 2048, 16.8 / 16.8; but 64 x 64, R = 64,
+// 15.3 / 17.0.  Never while the stream is being captured.
 bool split_wanted(const Ctx& c, hipStream_t s) {
   int mode;
   {
@@ -851,7 +849,7 @@ bool split_wanted(const Ctx& c, hipStream_t s) {
   }
   const InstDev& F = c.inst[0];
   if (mode == 1 || F.R < 2) return false;
-  if (mode == 0 && (F.R < 128 || (long long)F.R * F.N < (1LL << 20))) return false;
+  if (mode == 0 && (F.R < 128 || (long long)F.R * F.N < (1LL << 19))) return false;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
 }
