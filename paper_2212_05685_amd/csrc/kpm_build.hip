@@ -600,23 +600,25 @@ template __global__ void k_rescale<double>(const InstDev*, const int4*);
 
 // C_m = (2 - delta_m0) g_m (1/K) sum_k cos(m th_k) f(a cos th_k + b).
 // cos(m th_k) = cospi(j/(2K)) with the exact integer j = m(2k+1) mod 4K.
-// A block handles kCoefM consecutive m: 16 lanes per m run over k (lane l
-// takes k = l, l + 16, ...), f(x_k) is evaluated once per block in LDS, and
-// the 16 lane sums of each m are added in a fixed butterfly order.
-constexpr int kCoefM = kBlock / 16;
-
+// A block handles kBlock / L consecutive m: L lanes per m run over k (lane l
+// takes k = l, l + L, ...), f(x_k) is evaluated once per block in LDS, and
+// the L lane sums of each m are added in a fixed butterfly order.  L is
+// chosen per M (coeff_lanes) so that the grid of M L / kBlock blocks covers
+// the chip (about 256 blocks) without more blocks, each of which evaluates
+// f at all K nodes again.
+template <int L>
 __global__ __launch_bounds__(kBlock) void k_coeffs(int M, int K, double T,
                                                    const double* __restrict__ ab,
                                                    double* __restrict__ C) {
   __shared__ double F[kBlock];
-  const int lane16 = threadIdx.x & 15;
-  const int m = blockIdx.x * kCoefM + (threadIdx.x >> 4);
+  const int lane = threadIdx.x & (L - 1);
+  const int m = blockIdx.x * (kBlock / L) + threadIdx.x / L;
   const double a = ab[0], b = ab[1];
   const long long fourK = 4LL * K;
   const double inv2K = 1.0 / (2.0 * (double)K);
   const long long mm = m < M ? m : 0;
-  long long j = (mm * (2LL * lane16 + 1)) % fourK;     // k = lane16
-  const long long step = (32LL * mm) % fourK;           // k -> k + 16
+  long long j = (mm * (2LL * lane + 1)) % fourK;           // k = lane
+  const long long step = (2LL * L * mm) % fourK;           // k -> k + L
   double acc = 0.0;
   for (int k0 = 0; k0 < K; k0 += kBlock) {
     const int k = k0 + threadIdx.x;
@@ -627,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_coeffs(int M, int K, double T,
     }
     __syncthreads();
     const int kmax = min(kBlock, K - k0);
-    for (int kk = lane16; kk < kmax; kk += 16) {
+    for (int kk = lane; kk < kmax; kk += L) {
       acc += F[kk] * cospi((double)j * inv2K);
       j += step;
       if (j >= fourK) j -= fourK;
@@ -635,8 +637,8 @@ __global__ __launch_bounds__(kBlock) void k_coeffs(int M, int K, double T,
     __syncthreads();
   }
 #pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 16);
-  if (m < M && lane16 == 0) {
+  for (int o = L / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, L);
+  if (m < M && lane == 0) {
     const double c = acc / (double)K;
     const double q = 1.0 / (double)(M + 1);
     const double g = ((double)(M - m + 1) * cospi(m * q) + sinpi(m * q) * cospi(q) / sinpi(q)) * q;
@@ -703,9 +705,17 @@ hipError_t launch_rescale(const InstDev* insts, const int4* tmap, int ntiles, bo
   return hipGetLastError();
 }
 
+// Lanes per coefficient of k_coeffs: measured at K = 16384, 200 us with 16
+// lanes and 93 us with 64 at M = 1024; 228 us with 16 and 274 us with 64 at
+// M = 4096 (where 64 lanes give 1024 blocks, each evaluating f again).
+int coeff_lanes(int M) { return M <= 1024 ? 64 : M <= 2048 ? 32 : 16; }
+
 hipError_t launch_coeffs(int M, int K, double T, const double* ab, double* C, hipStream_t s) {
-  dim3 grid((M + kCoefM - 1) / kCoefM);
-  hipLaunchKernelGGL(k_coeffs, grid, dim3(kBlock), 0, s, M, K, T, ab, C);
+  const int L = coeff_lanes(M);
+  dim3 grid((M * L + kBlock - 1) / kBlock);
+  if (L == 64) hipLaunchKernelGGL(k_coeffs<64>, grid, dim3(kBlock), 0, s, M, K, T, ab, C);
+  else if (L == 32) hipLaunchKernelGGL(k_coeffs<32>, grid, dim3(kBlock), 0, s, M, K, T, ab, C);
+  else hipLaunchKernelGGL(k_coeffs<16>, grid, dim3(kBlock), 0, s, M, K, T, ab, C);
   return hipGetLastError();
 }
 
