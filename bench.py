@@ -250,6 +250,7 @@ def batched_form(steps: int):
         kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=True)   # tune + capture
         torch.cuda.synchronize()
         tune = kpm.kpm_batch_tuning(plan)
+        streams = kpm.kpm_batch_streams(plan)
         t0 = time.perf_counter()
         for _ in range(steps):
             kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=True)
@@ -311,8 +312,11 @@ def batched_form(steps: int):
         "fp32_vs_fp64_max_rel_err_rho": e_rho,
         "ms_per_step_fp32_batched_direct_launches": dt_direct * 1e3,
         "tuning": tune,
+        "streams": streams,
         "roofline": {
-            "kernel": "k_adj (fused adjoint step, all 48 lattices per launch)",
+            "kernel": ("k_adj (fused adjoint step; two instance halves on two streams, one launch each per "
+                       "step, timed on the first stream while the second's overlaps it)" if streams == 2 else
+                       "k_adj (fused adjoint step, all 48 lattices per launch)"),
             "bound": "hbm",
             "achieved": adj_bytes / adj_s / 1e9,
             "peak": HBM_PEAK_GBS,

@@ -350,18 +350,35 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
  * [n_inst]) and rho[k] ([19][N_k] complex, device).  The forward and adjoint
  * recursions of all instances run as one sequence of batched kernels,
  * captured once into a hipGraph and replayed on later calls with the same
- * pointers (use_graph != 0). */
+ * pointers (use_graph != 0).  A plan of two instance halves (see
+ * kpm_batch_streams) runs the halves side by side on the caller's stream and
+ * on a second stream of the device that the library creates once (default
+ * priority): with use_graph, as one graph per half; else with their step
+ * launches interleaved.  The caller's stream waits for the second stream
+ * before it returns to its own work. */
 int kpm_batch_energy_grad(void* plan, const double* const* h, const double* const* ab,
                           const double* const* C, double* omega, double* const* rho,
                           int32_t use_graph, void* stream);
 
 int kpm_batch_destroy(void* plan);
 
+/* Streams a batch plan runs on: 2 when its instances form two halves of
+ * nearly equal R N (largest first, each to the lighter half), each half with
+ * its own kernel tables and tuning; 1 otherwise; KPM_EINVAL for a null plan.
+ * Fixed when the plan is created, from kpm_set_streams: 1, one stream; 2,
+ * halves (plans of two or more instances); 0 (default), automatic: halves
+ * when the instances hold sum R N >= 2^19 site-probes.  Each instance's
+ * results are the same either way, bit for bit, for a fixed probe block and
+ * schedule: an instance's kernels and sums do not depend on the other
+ * instances. */
+int32_t kpm_batch_streams(const void* plan);
+
 /* The plan's kernel configuration (host int32_t out[5]): forward probe block,
  * forward schedule, adjoint probe block, adjoint schedule, and where they
  * came from: 0 timed by this plan, 1 this process's cache, 2 the disk cache,
  * -1 not tuned (fixed by kpm_set_probe_block / kpm_set_schedule, or the plan
- * has not run yet).  Schedules are KPM_SCHED_* values. */
+ * has not run yet).  Schedules are KPM_SCHED_* values.  For a plan of two
+ * instance halves, those of the first half. */
 int kpm_batch_tuning(const void* plan, int32_t* out);
 
 /* Probes-per-thread blocking used by the single-lattice calls (0 = automatic,
@@ -382,7 +399,8 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread);
 
 /* Streams of the single-lattice energy, gradient and moment calls
  * (kpm_moments, kpm_grand_potential, kpm_grand_potential_grad,
- * kpm_density_matrix): 1, everything on the caller's stream; 2, the probes in
+ * kpm_density_matrix), and of the batch plans created while it is set (see
+ * kpm_batch_streams): 1, everything on the caller's stream; 2, the probes in
  * two halves (ceil(R/2) and floor(R/2) probes) whose recursions run side by
  * side on the caller's stream and on a second stream of the device that the
  * library creates once (default priority), with their step launches

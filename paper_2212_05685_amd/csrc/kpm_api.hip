@@ -952,9 +952,12 @@ int join_to(Fork& f, hipStream_t s) {
 }
 
 // Forward recursion of both halves (alpha_0 ... alpha_{M-1}), then their
-// moment reductions (mu_user: the caller's [R][M] copy, or null).
+// moment reductions (mu_user: the caller's [R][M] copy, or null; probe
+// halves of a single lattice only).  c: the whole call (one lattice, or all
+// instances of a batch), whose status words and rescaled rows are set here.
 int run_forward_split(const Ctx& c, const Halves& hv, bool ckpt, double* mu_user, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, s, c.d_inst, 1, 0);
+  const int ninst = (int)c.inst.size();
+  hipLaunchKernelGGL(k_set_status, dim3((ninst + 63) / 64), dim3(64), 0, s, c.d_inst, ninst, 0);
   KPM_HIP(hipGetLastError());
   KPM_HIP(launch_rescale(c.d_inst, c.d_tmap, c.ntl(), c.fp32, s));
   Fork f;
@@ -1018,6 +1021,13 @@ int restore_alpha_split(const Halves& hv, hipStream_t s) {
 }  // namespace
 
 // ------------------------------------------------------------ batch plans
+// A plan's instances can run as two instance halves (hv.on): two contexts
+// over disjoint subsets of the instances (idx[q]: positions in the plan's
+// instance list, ascending), each with its own instance, chunk and tile
+// tables and its own tuning, whose recursions run side by side on the
+// caller's stream and on the device's second stream.  The instance buffers
+// belong to the whole plan (c); a half's table holds copies of its
+// instances' entries.
 struct KpmBatchPlan {
   Ctx c;
   void* mem = nullptr;
@@ -1027,17 +1037,92 @@ struct KpmBatchPlan {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   std::vector<const void*> graph_ptrs;   // pointers the captured graph was built with
+  Halves hv;
+  std::vector<int> idx[2];
+  hipStream_t capture2 = nullptr;        // capture stream of the second half's graph
+  hipGraphExec_t exec2 = nullptr;
+  hipGraph_t graph2 = nullptr;
 };
 
 namespace {
 
-int batch_sequence(KpmBatchPlan* pl, hipStream_t s) {
-  Ctx& c = pl->c;
+int batch_sequence_ctx(Ctx& c, hipStream_t s) {
   int st = run_forward(c, true, c.M, s);
   if (st != KPM_OK) return st;
   if ((st = run_moments(c, nullptr, s)) != KPM_OK) return st;
   KPM_HIP(launch_omega(c.d_inst, (int)c.inst.size(), c.M, s));
   return run_adjoint(c, s);
+}
+
+int batch_sequence(KpmBatchPlan* pl, hipStream_t s) {
+  if (!pl->hv.on) return batch_sequence_ctx(pl->c, s);
+  // instance halves, step launches interleaved on two streams
+  Ctx& c = pl->c;
+  int st = run_forward_split(c, pl->hv, true, nullptr, s);
+  if (st != KPM_OK) return st;
+  KPM_HIP(launch_omega(c.d_inst, (int)c.inst.size(), c.M, s));
+  return run_adjoint_split(c, pl->hv, s);
+}
+
+// Copies the plan's instance entries (the call's pointers, the probe range
+// counts) into the halves' tables.
+void sync_halves(KpmBatchPlan* pl) {
+  for (int q = 0; q < 2; ++q)
+    for (size_t j = 0; j < pl->idx[q].size(); ++j) pl->hv.h[q].inst[j] = pl->c.inst[pl->idx[q][j]];
+}
+
+// After a half's probe blocks changed: its instances' probe range counts
+// (the partial-sum slices that k_rho adds) into the plan's entries.
+void npb_from_halves(KpmBatchPlan* pl) {
+  for (int q = 0; q < 2; ++q)
+    for (size_t j = 0; j < pl->idx[q].size(); ++j) pl->c.inst[pl->idx[q][j]].npb = pl->hv.h[q].inst[j].npb;
+}
+
+int upload_plan(KpmBatchPlan* pl, hipStream_t s) {
+  int st = upload(pl->c, s);
+  if (st != KPM_OK || !pl->hv.on) return st;
+  sync_halves(pl);
+  for (int q = 0; q < 2 && st == KPM_OK; ++q) st = upload(pl->hv.h[q], s);
+  return st;
+}
+
+// Whether a batch plan runs as instance halves: requested
+// (kpm_set_streams(2)), or automatically when the instances hold
+// sum R N >= 2^19 site-probes.  Measured (ms per energy + gradient, FP32,
+// M = 1024, the first n of 48 lattices of 24 ... 64 sites a side with 64
+// probes each, graph replays, one stream against halves): n = 2 (3.6e5
+// site-probes) 19.2 / 19.3; n = 3 (5.1e5) 23.6 / 22.9; n = 4 (7.1e5)
+// 28.8 / 28.5; n = 6 (9.8e5) 36.1 / 33.3; n = 12 (1.7e6) 61.2 / 50.0;
+// n = 24 (3.6e6) 137.4 / 131.4; n = 48 (7.2e6) 279.7 / 264.9.
+bool batch_split_wanted(const std::vector<InstDev>& inst) {
+  int mode;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    mode = g_streams;
+  }
+  if (inst.size() < 2 || mode == 1) return false;
+  long long rn = 0;
+  for (const auto& I : inst) rn += (long long)I.R * I.N;
+  return mode == 2 || rn >= (1LL << 19);
+}
+
+// Splits the plan's instances into two halves of nearly equal R N (largest
+// first, each to the lighter half), each half in the plan's order.
+void split_instances(const std::vector<InstDev>& inst, std::vector<int> idx[2]) {
+  std::vector<int> order(inst.size());
+  for (size_t q = 0; q < inst.size(); ++q) order[q] = (int)q;
+  auto w = [&](int q) { return (long long)inst[q].R * inst[q].N; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w(a) > w(b); });
+  long long load[2] = {0, 0};
+  idx[0].clear();
+  idx[1].clear();
+  for (int q : order) {
+    const int j = load[0] <= load[1] ? 0 : 1;
+    idx[j].push_back(q);
+    load[j] += w(q);
+  }
+  std::sort(idx[0].begin(), idx[0].end());
+  std::sort(idx[1].begin(), idx[1].end());
 }
 
 }  // namespace
@@ -1434,12 +1519,18 @@ int kpm_set_schedule(int32_t fwd, int32_t adj) {
 int kpm_batch_tuning(const void* plan, int32_t* out) {
   if (!plan || !out) return KPM_EINVAL;
   const KpmBatchPlan* pl = static_cast<const KpmBatchPlan*>(plan);
-  out[0] = pl->c.Pf;
-  out[1] = pl->c.Sf;
-  out[2] = pl->c.Pa;
-  out[3] = pl->c.Sa;
+  const Ctx& c = pl->hv.on ? pl->hv.h[0] : pl->c;
+  out[0] = c.Pf;
+  out[1] = c.Sf;
+  out[2] = c.Pa;
+  out[3] = c.Sa;
   out[4] = pl->tune_source;
   return KPM_OK;
+}
+
+int32_t kpm_batch_streams(const void* plan) {
+  if (!plan) return KPM_EINVAL;
+  return static_cast<const KpmBatchPlan*>(plan)->hv.on ? 2 : 1;
 }
 
 int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* probes, int32_t M,
@@ -1469,6 +1560,13 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
     total += inst_bytes(zs[q]);
   }
   total += align_up(sizeof(int2) * nch) + align_up(sizeof(int4) * ntl);
+  const bool split = batch_split_wanted(insts);
+  // the halves' tables: n_inst entries, nch chunks and ntl tiles between them
+  // (each table aligned on its own)
+  const size_t half_tables = split ? 2 * (align_up(sizeof(InstDev) * n_inst) + align_up(sizeof(int2) * nch) +
+                                          align_up(sizeof(int4) * ntl))
+                                   : 0;
+  total += half_tables;
   auto* pl = new (std::nothrow) KpmBatchPlan();
   if (!pl) return KPM_ENOMEM;
   if (hipMalloc(&pl->mem, total) != hipSuccess) {
@@ -1502,6 +1600,31 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
   pl->c.Pa = P ? P : auto_probe_adj(pl->c.ntl(), pl->c.Rmax);
   pl->tuned = P != 0;
   set_npb(pl->c);
+  if (split) {
+    split_instances(insts, pl->idx);
+    for (int q = 0; q < 2; ++q) {
+      Ctx& h = pl->hv.h[q];
+      h.inst.clear();
+      for (int j : pl->idx[q]) h.inst.push_back(pl->c.inst[j]);
+      h.M = M;
+      h.k = ckpt_k;
+      h.fp32 = fp32;
+      h.Sf = pl->c.Sf;
+      h.Sa = pl->c.Sa;
+      finish_ctx(h);
+      h.d_inst = reinterpret_cast<InstDev*>(o);
+      o += align_up(sizeof(InstDev) * h.inst.size());
+      h.d_cmap = reinterpret_cast<int2*>(o);
+      o += align_up(sizeof(int2) * h.cmap.size());
+      h.d_tmap = reinterpret_cast<int4*>(o);
+      o += align_up(sizeof(int4) * h.tmap.size());
+      h.Pf = P ? P : auto_probe_fwd(h.ntl(), h.Rmax);
+      h.Pa = P ? P : auto_probe_adj(h.ntl(), h.Rmax);
+      set_npb(h);
+    }
+    npb_from_halves(pl);
+    pl->hv.on = true;
+  }
   *plan = pl;
   return KPM_OK;
 }
@@ -1527,40 +1650,84 @@ int kpm_batch_energy_grad(void* plan, const double* const* h, const double* cons
   }
   int st;
   if (!pl->tuned) {
-    if ((st = upload(c, s)) != KPM_OK) return st;
-    if ((st = tune_ctx(pl->c, nullptr, s, &pl->tune_source)) != KPM_OK) return st;
+    if (pl->hv.on) {
+      // each half is tuned as its own shape
+      sync_halves(pl);
+      for (int q = 0; q < 2; ++q) {
+        int src = -1;
+        if ((st = upload(pl->hv.h[q], s)) != KPM_OK) return st;
+        if ((st = tune_ctx(pl->hv.h[q], nullptr, s, &src)) != KPM_OK) return st;
+        if (q == 0) pl->tune_source = src;
+      }
+      npb_from_halves(pl);
+    } else {
+      if ((st = upload(c, s)) != KPM_OK) return st;
+      if ((st = tune_ctx(pl->c, nullptr, s, &pl->tune_source)) != KPM_OK) return st;
+    }
     pl->tuned = true;
   }
-  if ((st = upload(c, s)) != KPM_OK) return st;
+  if ((st = upload_plan(pl, s)) != KPM_OK) return st;
   if (!use_graph) return batch_sequence(pl, s);
   if (pl->exec && pl->graph_ptrs != ptrs) {
     (void)hipGraphExecDestroy(pl->exec);
     (void)hipGraphDestroy(pl->graph);
     pl->exec = nullptr;
     pl->graph = nullptr;
+    if (pl->exec2) (void)hipGraphExecDestroy(pl->exec2);
+    if (pl->graph2) (void)hipGraphDestroy(pl->graph2);
+    pl->exec2 = nullptr;
+    pl->graph2 = nullptr;
   }
   if (!pl->exec) {
-    // The captured kernels read the instance table from device memory, so the
-    // graph stays valid as long as the table is re-uploaded before each replay.
-    // Capture on a private stream (the caller's may be the null stream, which
-    // cannot be captured); nothing runs during capture.
-    if (!pl->capture_stream) KPM_HIP(hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking));
-    hipStream_t cs = pl->capture_stream;
-    KPM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    st = batch_sequence(pl, cs);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(cs, &g);
-    if (st != KPM_OK) {
-      if (g) (void)hipGraphDestroy(g);
+    // The captured kernels read the instance tables from device memory, so a
+    // graph stays valid as long as the tables are re-uploaded before each
+    // replay.  Capture on private streams (the caller's may be the null
+    // stream, which cannot be captured); nothing runs during capture.  With
+    // instance halves each half is captured whole (its own status words,
+    // moments, Omega and rho) as a graph of its own, and the two graphs are
+    // launched on the two streams.
+    auto capture = [](hipStream_t& cs, Ctx& cc, hipGraph_t& graph, hipGraphExec_t& exec) -> int {
+      if (!cs) KPM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      KPM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      const int r = batch_sequence_ctx(cc, cs);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(cs, &g);
+      if (r != KPM_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return r != KPM_OK ? r : KPM_EDEVICE;
+      }
+      if (hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        exec = nullptr;
+        return KPM_EDEVICE;
+      }
+      graph = g;
+      return KPM_OK;
+    };
+    if (pl->hv.on) {
+      if ((st = capture(pl->capture_stream, pl->hv.h[0], pl->graph, pl->exec)) != KPM_OK) return st;
+      if ((st = capture(pl->capture2, pl->hv.h[1], pl->graph2, pl->exec2)) != KPM_OK) {
+        // capture again on the next call
+        if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+        if (pl->graph) (void)hipGraphDestroy(pl->graph);
+        pl->exec = nullptr;
+        pl->graph = nullptr;
+        return st;
+      }
+    } else if ((st = capture(pl->capture_stream, pl->c, pl->graph, pl->exec)) != KPM_OK) {
       return st;
     }
-    if (e != hipSuccess) return KPM_EDEVICE;
-    pl->graph = g;
-    KPM_HIP(hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0));
     pl->graph_ptrs = ptrs;
   }
+  if (!pl->hv.on) {
+    KPM_HIP(hipGraphLaunch(pl->exec, s));
+    return KPM_OK;
+  }
+  Fork f;
+  if ((st = fork_from(f, s)) != KPM_OK) return st;
   KPM_HIP(hipGraphLaunch(pl->exec, s));
-  return KPM_OK;
+  KPM_HIP(hipGraphLaunch(pl->exec2, f.s2));
+  return join_to(f, s);
 }
 
 int kpm_batch_destroy(void* plan) {
@@ -1568,7 +1735,10 @@ int kpm_batch_destroy(void* plan) {
   if (!pl) return KPM_EINVAL;
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->exec2) (void)hipGraphExecDestroy(pl->exec2);
+  if (pl->graph2) (void)hipGraphDestroy(pl->graph2);
   if (pl->capture_stream) (void)hipStreamDestroy(pl->capture_stream);
+  if (pl->capture2) (void)hipStreamDestroy(pl->capture2);
   if (pl->mem) {
     (void)hipDeviceSynchronize();
     (void)hipFree(pl->mem);

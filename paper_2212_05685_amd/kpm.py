@@ -44,6 +44,7 @@ EXPORTS = (
     "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
     "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_build_H_sdw_vjp", "kpm_bloch_H", "kpm_gutzwiller_weights", "kpm_supercell_workspace_size",
     "kpm_supercell_ldos", "kpm_moments_noalloc", "kpm_set_schedule", "kpm_set_streams", "kpm_batch_tuning",
+    "kpm_batch_streams",
 )
 
 
@@ -122,6 +123,7 @@ def _load():
         "kpm_set_schedule": (c_int32, [c_int32, c_int32]),
         "kpm_set_streams": (c_int32, [c_int32]),
         "kpm_batch_tuning": (c_int32, [P, P]),
+        "kpm_batch_streams": (c_int32, [P]),
         "kpm_profile_begin": (c_int32, [c_int32]),
         "kpm_profile_end": (c_int32, [POINTER(c_double), POINTER(c_int32), POINTER(c_double),
                                       POINTER(c_int32)]),
@@ -380,7 +382,9 @@ def kpm_set_probe_block(probes_per_thread: int) -> int:
 
 
 def kpm_set_streams(n: int) -> int:
-    """0 automatic, 1 one stream, 2 probe halves on two streams; returns the previous value."""
+    """0 automatic, 1 one stream, 2 halves on two streams (the probes of a single
+    lattice; the instances of a batch plan created while it is set); returns the
+    previous value."""
     return int(_lib.kpm_set_streams(n))
 
 
@@ -490,6 +494,13 @@ def kpm_batch_energy_grad(plan, h, ab, C, omega, rho, use_graph=True, stream=Non
 
 def kpm_batch_destroy(plan) -> None:
     _check(_lib.kpm_batch_destroy(plan), "kpm_batch_destroy")
+
+
+def kpm_batch_streams(plan) -> int:
+    """2 when the plan runs as two instance halves on two streams, else 1."""
+    r = _lib.kpm_batch_streams(plan)
+    _check(r if r < 0 else 0, "kpm_batch_streams")
+    return int(r)
 
 
 def kpm_batch_tuning(plan) -> dict:

@@ -84,6 +84,7 @@ def test_host_validation():
     assert kpm.kpm_set_streams(old_streams) == 2
     out = (ctypes.c_int32 * 5)()
     assert kpm._lib.kpm_batch_tuning(None, out) == kpm.KPM_EINVAL
+    assert kpm._lib.kpm_batch_streams(None) == kpm.KPM_EINVAL
 
 
 def test_rmft_host_validation():

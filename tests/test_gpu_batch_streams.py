@@ -1,0 +1,166 @@
+"""Batch plans as two instance halves on two streams, against the oracle
+(GPU, through the C ABI).
+
+With kpm_set_streams(2) at plan creation (or automatically, from
+sum R N >= 2^19 site-probes) a batch plan splits its instances into two
+halves of nearly equal R N, each with its own kernel tables and tuning; their
+recursions run side by side on the caller's stream and on a second stream,
+with interleaved step launches, or as one graph per half.  What each instance
+computes is unchanged (App. B: eq. alpha for the moments, eq. F_KPM for
+Omega, eq. dFdH with the beta recursion for rho).  The cases: three uneven
+lattices (halves of two instances and one; the one-instance half takes the
+single-lattice tile arithmetic and, when asked, the balanced adjoint split),
+direct launches and graph replays, FP64 and FP32, fixed probe blocks with
+several schedules and the automatic block (each half tuned as its own shape);
+the split plan reproduces the one-stream plan bit for bit at a fixed block;
+graph replays repeat bit for bit; and the automatic rule.  The 48-lattice
+batch against the oracle (tests/test_gpu_fullsize_oracle.py) runs split.
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from tests import helpers as H
+from tests.gpu_helpers import host, problem, theta_dev
+
+pytestmark = pytest.mark.gpu
+
+M, K = 40, 5
+
+
+def _cfg(Lx, Ly, nv, probes):
+    return wl.Config("bs", Lx, Ly, nv, 0.13, M, tuple(probes), "fp64", vortex=nv > 0, complex_noise=0.02,
+                     ckpt_k=K)
+
+
+CFGS = [
+    _cfg(16, 16, 4, (wl.ProbeSpec("colored_z4", 1, 71, 4, 4, 1, 0, 1.0),)),
+    _cfg(9, 7, 2, (wl.ProbeSpec("colored_z4", 1, 77, 4, 3, 1, 0, 1.0),
+                   wl.ProbeSpec("dense_z4", 3, 99, weight=1 / 3))),
+    _cfg(12, 10, 2, (wl.ProbeSpec("dense_z4", 24, 5, weight=1 / 24),)),
+]
+
+
+@pytest.fixture(autouse=True)
+def _reset():
+    from paper_2212_05685_amd import kpm
+    yield
+    kpm.kpm_set_streams(0)
+    kpm.kpm_set_probe_block(0)
+    kpm.kpm_set_schedule(kpm.KPM_SCHED_DEFAULT, kpm.KPM_SCHED_DEFAULT)
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle(q):
+    cfg = CFGS[q]
+    st, a, b, C = H.oracle_inputs(cfg)
+    return H.plain(cfg, st, a, b, C)
+
+
+@functools.lru_cache(maxsize=None)
+def _inputs(prec):
+    probs, hs, abs_, Cs = [], [], [], []
+    for cfg in CFGS:
+        p = problem(cfg, precision=prec)
+        h = p.build_H(*theta_dev(cfg))
+        ab = p.bounds(h)
+        probs.append(p)
+        hs.append(h)
+        abs_.append(ab)
+        Cs.append(p.coefficients(ab))
+    return probs, hs, abs_, Cs
+
+
+def _plan(prec, streams):
+    from paper_2212_05685_amd import kpm
+    probs = _inputs(prec)[0]
+    kpm.kpm_set_streams(streams)
+    plan = kpm.kpm_batch_create([q.lat for q in probs], [q.probes for q in probs], M,
+                                kpm.KPM_FP64 if prec == "fp64" else kpm.KPM_FP32, K)
+    kpm.kpm_set_streams(0)
+    return plan
+
+
+def _call(plan, prec, use_graph):
+    from paper_2212_05685_amd import kpm
+    _, hs, abs_, Cs = _inputs(prec)
+    omega = torch.zeros(len(CFGS), dtype=torch.float64, device="cuda")
+    rhos = [torch.zeros_like(h) for h in hs]
+    kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=use_graph)
+    return host(omega), [host(r) for r in rhos]
+
+
+def _check_oracle(om, rhos, prec):
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    for q in range(len(CFGS)):
+        ref = _oracle(q)
+        assert abs(om[q] - ref["omega"]) < tol * abs(ref["omega"])
+        assert H.rel_err(rhos[q], ref["rho"]) < tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("P,sa", [(4, -1), (2, 2), (1, 4), (0, -1)], ids=["P4", "P2strips", "P1bal", "auto"])
+def test_halves_against_oracle(prec, P, sa):
+    from paper_2212_05685_amd import kpm
+    kpm.kpm_set_probe_block(P)
+    kpm.kpm_set_schedule(kpm.KPM_SCHED_DEFAULT, sa)
+    plan = _plan(prec, 2)
+    try:
+        assert kpm.kpm_batch_streams(plan) == 2
+        for use_graph in (False, True, True):
+            om, rhos = _call(plan, prec, use_graph)
+            _check_oracle(om, rhos, prec)
+        tune = kpm.kpm_batch_tuning(plan)
+        assert tune["source"] == ("fixed" if P else "timed") or (P == 0 and tune["source"] != "fixed")
+    finally:
+        kpm.kpm_batch_destroy(plan)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_halves_match_one_stream_bitwise(prec):
+    """At a fixed probe block and schedule an instance's kernels and sums do
+    not depend on the other instances, so the split plan's results equal the
+    one-stream plan's bit for bit, and graph replays repeat them."""
+    from paper_2212_05685_amd import kpm
+    kpm.kpm_set_probe_block(2)
+    one, two = _plan(prec, 1), _plan(prec, 2)
+    try:
+        assert kpm.kpm_batch_streams(one) == 1 and kpm.kpm_batch_streams(two) == 2
+        om1, r1 = _call(one, prec, False)
+        runs = [_call(two, prec, g) for g in (False, True, True, True)]
+    finally:
+        kpm.kpm_batch_destroy(one)
+        kpm.kpm_batch_destroy(two)
+    for om2, r2 in runs:
+        assert np.array_equal(om1, om2)
+        assert all(np.array_equal(a, b) for a, b in zip(r1, r2))
+
+
+def test_automatic_rule():
+    from paper_2212_05685_amd import kpm
+    for streams, want in ((0, 1), (1, 1), (2, 2)):
+        plan = _plan("fp32", streams)
+        try:
+            assert kpm.kpm_batch_streams(plan) == want
+        finally:
+            kpm.kpm_batch_destroy(plan)
+    # the 48 uneven lattices (7.2e6 site-probes) and their first 4 (7.1e5)
+    # split automatically, their first 3 (5.1e5 < 2^19) do not; a plan of
+    # one lattice never does
+    cfgs = wl.C4_instances(48)
+    probs = [problem(c, precision="fp32") for c in cfgs]
+    rn = lambda n: sum(q.R * c.N for q, c in zip(probs[:n], cfgs[:n]))
+    assert rn(3) < 2 ** 19 <= rn(4)
+    for n, streams, want in ((48, 0, 2), (48, 1, 1), (4, 0, 2), (3, 0, 1), (1, 2, 1)):
+        kpm.kpm_set_streams(streams)
+        plan = kpm.kpm_batch_create([q.lat for q in probs[:n]], [q.probes for q in probs[:n]], cfgs[0].M,
+                                    kpm.KPM_FP32, cfgs[0].ckpt_k)
+        kpm.kpm_set_streams(0)
+        try:
+            assert kpm.kpm_batch_streams(plan) == want
+        finally:
+            kpm.kpm_batch_destroy(plan)
+    torch.cuda.empty_cache()
