@@ -337,7 +337,11 @@ int kpm_status_read(const void* ws, int32_t* status, void* stream);
  * KPM_TUNE_CACHE, else $XDG_CACHE_HOME/kpm_tune.txt, else
  * $HOME/.cache/kpm_tune.txt.  Each line of that file is
  * "<key> <Pf> <Sf> <Pa> <Sa>", with <key> =
- * "<arch>:<compute units>:<f|d>:<N_0>x<R_0>,<N_1>x<R_1>,...";
+ * "<arch>:<compute units>:<f|d>:<N_0>x<R_0>,<N_1>x<R_1>,...", followed by
+ * "/2" for a shape that runs as two halves on two streams (the probe halves
+ * of a single lattice, keyed by the whole lattice's N and R; the instance
+ * halves of a plan, keyed by all its instances), whose candidates are timed
+ * on both halves at once and whose pick serves both halves;
  * a shape tuned with M < 3 (no adjoint step to time) is not remembered;
  * the last valid line of a key is used, and a file that cannot be read or
  * written only disables the disk cache (so does KPM_TUNE_CACHE set to the
@@ -364,7 +368,8 @@ int kpm_batch_destroy(void* plan);
 
 /* Streams a batch plan runs on: 2 when its instances form two halves of
  * nearly equal R N (largest first, each to the lighter half), each half with
- * its own kernel tables and tuning; 1 otherwise; KPM_EINVAL for a null plan.
+ * its own kernel tables, both tuned together (one pick, timed on the pair);
+ * 1 otherwise; KPM_EINVAL for a null plan.
  * Fixed when the plan is created, from kpm_set_streams: 1, one stream; 2,
  * halves (plans of two or more instances); 0 (default), automatic: halves
  * when the instances hold sum R N >= 2^19 site-probes.  Each instance's
@@ -377,8 +382,8 @@ int32_t kpm_batch_streams(const void* plan);
  * forward schedule, adjoint probe block, adjoint schedule, and where they
  * came from: 0 timed by this plan, 1 this process's cache, 2 the disk cache,
  * -1 not tuned (fixed by kpm_set_probe_block / kpm_set_schedule, or the plan
- * has not run yet).  Schedules are KPM_SCHED_* values.  For a plan of two
- * instance halves, those of the first half. */
+ * has not run yet).  Schedules are KPM_SCHED_* values.  A plan of two
+ * instance halves runs one configuration on both. */
 int kpm_batch_tuning(const void* plan, int32_t* out);
 
 /* Probes-per-thread blocking used by the single-lattice calls (0 = automatic,
@@ -413,7 +418,8 @@ int32_t kpm_set_probe_block(int32_t probes_per_thread);
  * gradient follows the layout of the forward call it completes.  Halves
  * change results only through the order of floating-point sums (FP64 sums
  * of the moments and the partial sums, 1e-14 relative; the FP32 per-wave
- * sums of the adjoint, 1e-7).  The halves are tuned as a shape of R/2 probes.
+ * sums of the adjoint, 1e-7).  The halves are tuned as a pair (see
+ * kpm_batch_create for the cache key).
  * Process-wide; returns the previous value (values outside 0..2 leave the
  * setting unchanged). */
 int32_t kpm_set_streams(int32_t n);

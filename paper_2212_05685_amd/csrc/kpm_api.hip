@@ -892,37 +892,6 @@ bool build_halves(Ctx& c, Halves& hv) {
   return true;
 }
 
-// Configures the halves: with the automatic probe block, the picks remembered
-// for the half shape, else (allow_timing: the first energy evaluation of the
-// shape) the tuner's run on half 0; then the halves are built again with
-// those picks.  The call runs on one stream if they no longer fit.
-int setup_halves(Ctx& c, Halves& hv, const void* ws, hipStream_t s, bool allow_timing) {
-  if (!build_halves(c, hv)) return KPM_OK;
-  int P;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    P = g_probe_block;
-  }
-  if (P != 0) return KPM_OK;
-  Ctx& h0 = hv.h[0];
-  Tune t{};
-  int src = 0;
-  if (!tune_lookup(shape_key(h0), t, &src)) {
-    if (!allow_timing) return KPM_OK;
-    {
-      std::lock_guard<std::mutex> lk(g_mu);
-      g_fwd.erase(ws);
-    }
-    const int st = tune_ctx(h0, ws, s, &src);
-    if (st != KPM_OK) return st;
-    t = Tune{h0.Pf, h0.Sf, h0.Pa, h0.Sa};
-  }
-  apply_tune(c, t);
-  c.want_tune = false;
-  build_halves(c, hv);
-  return KPM_OK;
-}
-
 // Fork/join between the caller's stream and the second stream; while forked,
 // the second stream's launches are not timed by the profiler.
 struct Fork {
@@ -955,7 +924,9 @@ int join_to(Fork& f, hipStream_t s) {
 // moment reductions (mu_user: the caller's [R][M] copy, or null; probe
 // halves of a single lattice only).  c: the whole call (one lattice, or all
 // instances of a batch), whose status words and rescaled rows are set here.
-int run_forward_split(const Ctx& c, const Halves& hv, bool ckpt, double* mu_user, hipStream_t s) {
+int run_forward_split(const Ctx& c, const Halves& hv, bool ckpt, double* mu_user, hipStream_t s,
+                      int nsteps = -1, bool moments = true) {
+  if (nsteps < 0) nsteps = c.M;
   const int ninst = (int)c.inst.size();
   hipLaunchKernelGGL(k_set_status, dim3((ninst + 63) / 64), dim3(64), 0, s, c.d_inst, ninst, 0);
   KPM_HIP(hipGetLastError());
@@ -969,14 +940,14 @@ int run_forward_split(const Ctx& c, const Halves& hv, bool ckpt, double* mu_user
     KPM_HIP(launch_cheb(h.fp32, h.Pf, h.Sf, 0, h.d_inst, h.d_tmap, h.ntl(), h.tpx(), h.nrf(), 0, h.M, h.k,
                         ckpt ? 1 : 0, h.bal, ss[q]));
   }
-  for (int m = 0; m + 1 < c.M; ++m)
+  for (int m = 0; m + 1 < nsteps; ++m)
     for (int q = 0; q < 2; ++q) {
       const Ctx& h = hv.h[q];
       KPM_HIP(launch_cheb(h.fp32, h.Pf, h.Sf, 1, h.d_inst, h.d_tmap, h.ntl(), h.tpx(), h.nrf(), m, h.M,
                           h.k, ckpt ? 1 : 0, h.bal, ss[q]));
     }
   if ((st = join_to(f, s)) != KPM_OK) return st;
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < 2 && moments; ++q) {
     const Ctx& h = hv.h[q];
     double* mu = mu_user ? mu_user + (size_t)h.inst[0].poff * c.M : nullptr;
     if ((st = run_moments(h, mu, s)) != KPM_OK) return st;
@@ -1005,6 +976,168 @@ int run_adjoint_split(const Ctx& c, const Halves& hv, hipStream_t s) {
   }
   if ((st = join_to(f, s)) != KPM_OK) return st;
   KPM_HIP(launch_rho(c.d_inst, c.d_cmap, c.nch(), s));
+  return KPM_OK;
+}
+
+constexpr int kNoFit = 1;   // a candidate whose halves do not fit (tune_pair)
+
+// Tuning of two halves that run side by side (the probe halves of a single
+// lattice, the instance halves of a batch plan).  Each candidate is timed on
+// both halves at once, the same candidate for both, with their step launches
+// interleaved on the caller's stream and the second stream as the calls run
+// them; a half timed alone can favour a block that the pair runs slower
+// (forward probe block 8 against 16 on the 48-lattice batch: 264.5 against
+// 259.4 ms per energy + gradient).  Candidates, timing and the kept picks as
+// in tune_ctx; the picks are remembered under `key`.  c: the whole call,
+// whose status words and rescaled rows the timed forward sets.  prep(t) sets
+// candidate t on both halves and uploads the tables: KPM_OK, kNoFit (the
+// candidate is skipped) or an error.  With a remembered pick, or after the
+// timing, the pick is left set; with neither (allow_timing false), nothing
+// changes.
+template <typename Prep>
+int tune_pair(Ctx& c, Halves& hv, const std::string& key, Prep prep, hipStream_t s, bool allow_timing,
+              int* source) {
+  Tune t{};
+  if (tune_lookup(key, t, source)) {
+    const int r = prep(t);
+    return r == kNoFit ? KPM_OK : r;
+  }
+  if (!allow_timing) return KPM_OK;
+  const bool verbose = std::getenv("KPM_TUNE_VERBOSE") != nullptr;
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  KPM_HIP(hipEventCreate(&ev.a));
+  KPM_HIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
+  auto elapsed = [&](float* ms) -> int {
+    KPM_HIP(hipEventSynchronize(e1));
+    KPM_HIP(hipEventElapsedTime(ms, e0, e1));
+    return KPM_OK;
+  };
+  const int steps = std::min(c.M, 8);
+  float best_f = 1e30f, best_a = 1e30f;
+  Tune best{1, -1, 1, -1};
+  bool any = false;
+  int st = KPM_OK;
+  for (int P : {1, 2, 4, 8, 16, 32}) {
+    for (int S : {KPM_SCHED_TILE_MAJOR, KPM_SCHED_RANGES, KPM_SCHED_STRIPS, KPM_SCHED_STRIP_TILES,
+                  KPM_SCHED_BALANCED}) {
+      if (S == KPM_SCHED_BALANCED && P != 32) continue;
+      const int r = prep(Tune{P, S, P, S});
+      if (r == kNoFit) continue;
+      if ((st = r) != KPM_OK) break;
+      any = true;
+      // forward steps of both halves: warm once, then the faster of two timed runs
+      float tf = 1e30f;
+      for (int rep = 0; rep < 3 && st == KPM_OK; ++rep) {
+        KPM_HIP(hipEventRecord(e0, s));
+        if ((st = run_forward_split(c, hv, true, nullptr, s, steps, false)) != KPM_OK) break;
+        KPM_HIP(hipEventRecord(e1, s));
+        float ms = 0.f;
+        if ((st = elapsed(&ms)) != KPM_OK) break;
+        if (rep > 0) tf = std::min(tf, ms);
+      }
+      if (st != KPM_OK) break;
+      if (tf < best_f && S != KPM_SCHED_BALANCED) {
+        best_f = tf;
+        best.Pf = P;
+        best.Sf = S;
+      }
+      float ta = 1e30f;
+      if (c.M >= 3) {
+        // adjoint steps of both halves at m = M-3 (timing only) on the alpha
+        // just computed, gamma and the partial sums from k_adj_init
+        for (int q = 0; q < 2 && st == KPM_OK; ++q) st = adj_init(hv.h[q], s);
+        for (int rep = 0; rep < 3 && st == KPM_OK; ++rep) {
+          KPM_HIP(hipEventRecord(e0, s));
+          {
+            Fork f;
+            if ((st = fork_from(f, s)) != KPM_OK) break;
+            const hipStream_t ss[2] = {s, f.s2};
+            for (int i = 0; i < steps; ++i)
+              for (int q = 0; q < 2; ++q) {
+                const Ctx& h = hv.h[q];
+                KPM_HIP(launch_cheb(h.fp32, h.Pa, h.Sa, 3, h.d_inst, h.d_tmap, h.ntl(), h.tpx(), h.nra(),
+                                    h.M - 3, h.M, h.M + 1, 0, h.bal, ss[q]));
+              }
+            if ((st = join_to(f, s)) != KPM_OK) break;
+          }
+          KPM_HIP(hipEventRecord(e1, s));
+          float ms = 0.f;
+          if ((st = elapsed(&ms)) != KPM_OK) break;
+          if (rep > 0) ta = std::min(ta, ms);
+        }
+        if (st != KPM_OK) break;
+        if (ta < best_a) {
+          best_a = ta;
+          best.Pa = P;
+          best.Sa = S;
+        }
+      }
+      if (verbose)
+        std::fprintf(stderr, "[kpm tune] %s P=%d sched=%d forward %.1f us/step adjoint %.1f us/step (both halves)\n",
+                     key.c_str(), P, S, 1e3f * tf / steps, 1e3f * ta / steps);
+    }
+    if (st != KPM_OK) break;
+  }
+  if (st != KPM_OK) return st;
+  if (!any) return KPM_OK;
+  *source = 0;
+  if (c.M < 3) {
+    best.Pa = best.Pf;
+    best.Sa = best.Sf;
+  } else {
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_tune_cache[key] = best;
+    }
+    disk_store(key, best);
+  }
+  const int r = prep(best);
+  return r == kNoFit ? KPM_OK : r;
+}
+
+// Configures the probe halves of a single lattice: with the automatic probe
+// block, the picks remembered for the lattice's shape as halves, else
+// (allow_timing: the first energy evaluation of the shape) tune_pair's
+// timing on this call's workspace; the halves are built with those picks.
+// The call runs on one stream if they no longer fit.
+int setup_halves(Ctx& c, Halves& hv, const void* ws, hipStream_t s, bool allow_timing) {
+  if (!build_halves(c, hv)) return KPM_OK;
+  int P;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    P = g_probe_block;
+  }
+  if (P != 0) return KPM_OK;
+  const Tune orig{c.Pf, c.Sf, c.Pa, c.Sa};
+  const std::string key = shape_key(c) + "/2";
+  Tune t{};
+  int src = 0;
+  if (!tune_lookup(key, t, &src)) {
+    if (!allow_timing) return KPM_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_fwd.erase(ws);
+  }
+  auto prep = [&](const Tune& cand) -> int {
+    apply_tune(c, cand);
+    if (!build_halves(c, hv)) return kNoFit;
+    const std::vector<InstDev> ex = hv.inst();
+    return upload_single(c, ws, s, &ex);
+  };
+  const int st = tune_pair(c, hv, key, prep, s, allow_timing, &src);
+  if (st != KPM_OK) return st;
+  if (!hv.on) {
+    // no pick fits as halves: the size heuristic's picks, on one stream
+    apply_tune(c, orig);
+    build_halves(c, hv);
+  }
+  c.want_tune = false;
   return KPM_OK;
 }
 
@@ -1651,15 +1784,15 @@ int kpm_batch_energy_grad(void* plan, const double* const* h, const double* cons
   int st;
   if (!pl->tuned) {
     if (pl->hv.on) {
-      // each half is tuned as its own shape
-      sync_halves(pl);
-      for (int q = 0; q < 2; ++q) {
-        int src = -1;
-        if ((st = upload(pl->hv.h[q], s)) != KPM_OK) return st;
-        if ((st = tune_ctx(pl->hv.h[q], nullptr, s, &src)) != KPM_OK) return st;
-        if (q == 0) pl->tune_source = src;
-      }
-      npb_from_halves(pl);
+      // both halves take one pick, timed on the pair
+      auto prep = [&](const Tune& t) -> int {
+        for (int q = 0; q < 2; ++q) apply_tune(pl->hv.h[q], t);
+        npb_from_halves(pl);
+        return upload_plan(pl, s);
+      };
+      if ((st = upload_plan(pl, s)) != KPM_OK) return st;
+      if ((st = tune_pair(c, pl->hv, shape_key(c) + "/2", prep, s, true, &pl->tune_source)) != KPM_OK)
+        return st;
     } else {
       if ((st = upload(c, s)) != KPM_OK) return st;
       if ((st = tune_ctx(pl->c, nullptr, s, &pl->tune_source)) != KPM_OK) return st;

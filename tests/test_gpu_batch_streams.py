@@ -164,3 +164,46 @@ def test_automatic_rule():
         finally:
             kpm.kpm_batch_destroy(plan)
     torch.cuda.empty_cache()
+
+
+def _key(probs, fp32):
+    props = torch.cuda.get_device_properties(0)
+    arch = props.gcnArchName.split(":")[0]
+    inst = ",".join(f"{q.lat.Lx * q.lat.Ly}x{q.R}" for q in probs)
+    return f"{arch}:{props.multi_processor_count}:{'f' if fp32 else 'd'}:{inst}/2"
+
+
+def test_pair_tuning_cache(tmp_path, monkeypatch):
+    """Automatic block: the halves are tuned as a pair (each candidate timed on
+    both halves at once), one line "<key of all instances>/2" goes to the cache
+    file, both halves take its pick, and a second plan of the shape reuses it
+    from the process cache.  The lattices in reverse order: a shape no other
+    test of this process has tuned."""
+    from paper_2212_05685_amd import kpm
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("KPM_TUNE_CACHE", str(path))
+    kpm.kpm_set_probe_block(0)
+    probs, hs, abs_, Cs = (x[::-1] for x in _inputs("fp64"))
+    key = _key(probs, False)
+    picks = []
+    for source in ("timed", "process cache"):
+        kpm.kpm_set_streams(2)
+        plan = kpm.kpm_batch_create([q.lat for q in probs], [q.probes for q in probs], M, kpm.KPM_FP64, K)
+        kpm.kpm_set_streams(0)
+        try:
+            assert kpm.kpm_batch_streams(plan) == 2
+            omega = torch.zeros(len(probs), dtype=torch.float64, device="cuda")
+            rhos = [torch.zeros_like(h) for h in hs]
+            kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=True)
+            om, rh = host(omega)[::-1], [host(r) for r in rhos][::-1]
+            tune = kpm.kpm_batch_tuning(plan)
+        finally:
+            kpm.kpm_batch_destroy(plan)
+        assert tune["source"] == source
+        _check_oracle(om, rh, "fp64")
+        picks.append([tune["fwd_probe_block"], tune["fwd_schedule"], tune["adj_probe_block"],
+                      tune["adj_schedule"]])
+        lines = [ln.split() for ln in path.read_text().splitlines()]
+        assert [ln[0] for ln in lines] == [key]
+        assert [int(v) for v in lines[0][1:]] == picks[0]
+    assert picks[0] == picks[1]

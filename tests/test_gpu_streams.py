@@ -122,6 +122,26 @@ def test_halves_moments_entry_point():
     assert np.max(np.abs(mu - ref["mu"])) < TOL * np.max(np.abs(ref["mu"]))
 
 
+def test_halves_tuned_as_pair(tmp_path, monkeypatch):
+    """Automatic block: the first energy evaluation tunes the halves as a pair
+    (each candidate timed on both halves at once); the cache file gets one
+    line, keyed by the whole lattice's shape followed by "/2"; a second
+    evaluation reuses the pick; results match the oracle."""
+    from paper_2212_05685_amd import kpm
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("KPM_TUNE_CACHE", str(path))
+    kpm.kpm_set_streams(2)
+    kpm.kpm_set_probe_block(0)
+    cfg = _cfg()
+    props = torch.cuda.get_device_properties(0)
+    key = f"{props.gcnArchName.split(':')[0]}:{props.multi_processor_count}:d:{cfg.Lx * cfg.Ly}x27/2"
+    for _ in range(2):
+        om, mu, (rho,) = _run(cfg, "fp64")
+        _check(om, mu, rho, _oracle(), TOL)
+        lines = [ln.split() for ln in path.read_text().splitlines()]
+        assert [ln[0] for ln in lines] == [key]
+
+
 def test_set_streams_returns_previous_and_ignores_bad_values():
     from paper_2212_05685_amd import kpm
     assert kpm.kpm_set_streams(2) == 0
