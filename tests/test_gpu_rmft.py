@@ -99,11 +99,24 @@ def _gpu_loop(cfg, p, n_iter, mu0, precision=None, estimator="adjoint"):
     return (host(n), host(chi), host(dlt)), mu, hist, st
 
 
-@pytest.mark.parametrize("search,estimator,anderson", [("bisection", "adjoint", 0),
-                                                       ("illinois", "adjoint", 0),
-                                                       ("illinois", "direct", 0),
-                                                       ("illinois", "adjoint", 2)])
-def test_iterate_parity_fp64(search, estimator, anderson):
+@pytest.mark.parametrize("search,estimator,anderson,streams", [("bisection", "adjoint", 0, 0),
+                                                               ("illinois", "adjoint", 0, 0),
+                                                               ("illinois", "direct", 0, 0),
+                                                               ("illinois", "adjoint", 2, 0),
+                                                               ("illinois", "adjoint", 0, 2)])
+def test_iterate_parity_fp64(search, estimator, anderson, streams):
+    """streams 2: every density-matrix evaluation of the loop runs its probes
+    as two halves on two streams (the automatic setting keeps this 12 x 8
+    lattice's 32 probes on one stream)."""
+    from paper_2212_05685_amd import kpm
+    kpm.kpm_set_streams(streams)
+    try:
+        _check_iterate_parity(search, estimator, anderson)
+    finally:
+        kpm.kpm_set_streams(0)
+
+
+def _check_iterate_parity(search, estimator, anderson):
     cfg = _loop_cfg()
     prm = ormft.Params(doping=0.16, mix=0.1, tol_n=1e-5, tol_mu=1e-10, mu_step=0.004, max_evals=60,
                        search=search, anderson=anderson)
@@ -199,9 +212,23 @@ def _sdw_cfg():
                      "fp64", ckpt_k=16, vortex=False, complex_noise=0.01, seed=4242)
 
 
-@pytest.mark.parametrize("search,anderson,estimator", [("illinois", 0, "adjoint"), ("bisection", 0, "adjoint"),
-                                                       ("illinois", 2, "adjoint"), ("illinois", 0, "direct")])
-def test_iterate_sdw_parity_fp64(search, anderson, estimator):
+@pytest.mark.parametrize("search,anderson,estimator,streams", [("illinois", 0, "adjoint", 0),
+                                                               ("bisection", 0, "adjoint", 0),
+                                                               ("illinois", 2, "adjoint", 0),
+                                                               ("illinois", 0, "direct", 0),
+                                                               ("illinois", 0, "adjoint", 2)])
+def test_iterate_sdw_parity_fp64(search, anderson, estimator, streams):
+    """streams 2: the spin-resolved density-matrix evaluations run their probes
+    as two halves on two streams."""
+    from paper_2212_05685_amd import kpm
+    kpm.kpm_set_streams(streams)
+    try:
+        _check_iterate_sdw_parity(search, anderson, estimator)
+    finally:
+        kpm.kpm_set_streams(0)
+
+
+def _check_iterate_sdw_parity(search, anderson, estimator):
     from paper_2212_05685_amd import kpm
 
     cfg = _sdw_cfg()
