@@ -611,12 +611,15 @@ void apply_tune(Ctx& c, const Tune& t) {
   set_npb(c);
 }
 
-// Times a few forward steps and a few adjoint steps for each candidate
+// Times up to 16 plain forward steps and 16 adjoint steps for each candidate
 // (probe block, schedule), the faster of two runs after a warm-up one, and
-// keeps the fastest candidate of each kernel.  The forward
-// runs on the probes (the adjoint after it, on the alpha just computed, with
-// gamma and the partial sums from k_adj_init), so no step reads uninitialised
-// data.  KPM_TUNE_VERBOSE=1 prints every timing on stderr.
+// keeps the fastest candidate of each kernel.  The rescaled rows, alpha_0
+// and alpha_1 are set before the timed forward steps, so that a candidate's
+// time holds the step kernel alone (with them inside, 8 timed steps picked a
+// forward schedule 3 % slower than the best on the 100 x 100 workload).  The
+// forward runs on the probes (the adjoint after it, on the alpha just
+// computed, with gamma and the partial sums from k_adj_init), so no step
+// reads uninitialised data.  KPM_TUNE_VERBOSE=1 prints every timing on stderr.
 // single_ws: the workspace of a single-lattice call (its tables are uploaded
 // through the per-workspace host store), or null for a plan.
 int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
@@ -639,7 +642,10 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
   KPM_HIP(hipEventCreate(&ev.a));
   KPM_HIP(hipEventCreate(&ev.b));
   hipEvent_t e0 = ev.a, e1 = ev.b;
-  const int steps = std::min(c.M, 8);
+  // adjoint: `steps` launches at m = M-3; forward: the plain steps m = fm0 .. fm1
+  // (alpha_0, alpha_1 and the rescaled rows are set first, untimed)
+  const int steps = std::min(c.M, 16);
+  const int fm0 = c.M >= 3 ? 1 : 0, fm1 = std::min(c.M - 2, fm0 + 15);
   float best_f = 1e30f, best_a = 1e30f;
   Tune best{1, -1, 1, -1};
   int st = KPM_OK;
@@ -654,10 +660,13 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
       set_npb(c);
       if ((st = put(c)) != KPM_OK) break;
       // forward: warm once, then the faster of two timed runs
+      if ((st = run_forward(c, true, fm0 + 1, s)) != KPM_OK) break;
       float tf = 1e30f;
       for (int rep = 0; rep < 3 && st == KPM_OK; ++rep) {
         KPM_HIP(hipEventRecord(e0, s));
-        if ((st = run_forward(c, true, steps, s)) != KPM_OK) break;
+        for (int m = fm0; m <= fm1; ++m)
+          KPM_HIP(launch_cheb(c.fp32, c.Pf, c.Sf, 1, c.d_inst, c.d_tmap, c.ntl(), c.tpx(), c.nrf(), m, c.M,
+                              c.k, 1, c.bal, s));
         KPM_HIP(hipEventRecord(e1, s));
         KPM_HIP(hipEventSynchronize(e1));
         float t = 0.f;
@@ -696,7 +705,7 @@ int tune_ctx(Ctx& c, const void* single_ws, hipStream_t s, int* source) {
       }
       if (verbose)
         std::fprintf(stderr, "[kpm tune] %s P=%d sched=%d forward %.1f us/step adjoint %.1f us/step\n",
-                     key.c_str(), P, S, 1e3f * tf / steps, 1e3f * ta / steps);
+                     key.c_str(), P, S, 1e3f * tf / (fm1 - fm0 + 1), 1e3f * ta / steps);
     }
     if (st != KPM_OK) break;
   }
@@ -1019,7 +1028,8 @@ int tune_pair(Ctx& c, Halves& hv, const std::string& key, Prep prep, hipStream_t
     KPM_HIP(hipEventElapsedTime(ms, e0, e1));
     return KPM_OK;
   };
-  const int steps = std::min(c.M, 8);
+  const int steps = std::min(c.M, 16);
+  const int fm0 = c.M >= 3 ? 1 : 0, fm1 = std::min(c.M - 2, fm0 + 15);
   float best_f = 1e30f, best_a = 1e30f;
   Tune best{1, -1, 1, -1};
   bool any = false;
@@ -1032,11 +1042,24 @@ int tune_pair(Ctx& c, Halves& hv, const std::string& key, Prep prep, hipStream_t
       if (r == kNoFit) continue;
       if ((st = r) != KPM_OK) break;
       any = true;
-      // forward steps of both halves: warm once, then the faster of two timed runs
+      // forward steps of both halves (alpha_0, alpha_1 and the rescaled rows
+      // set first, untimed): warm once, then the faster of two timed runs
+      if ((st = run_forward_split(c, hv, true, nullptr, s, fm0 + 1, false)) != KPM_OK) break;
       float tf = 1e30f;
       for (int rep = 0; rep < 3 && st == KPM_OK; ++rep) {
         KPM_HIP(hipEventRecord(e0, s));
-        if ((st = run_forward_split(c, hv, true, nullptr, s, steps, false)) != KPM_OK) break;
+        {
+          Fork f;
+          if ((st = fork_from(f, s)) != KPM_OK) break;
+          const hipStream_t ss[2] = {s, f.s2};
+          for (int mm = fm0; mm <= fm1; ++mm)
+            for (int q = 0; q < 2; ++q) {
+              const Ctx& h = hv.h[q];
+              KPM_HIP(launch_cheb(h.fp32, h.Pf, h.Sf, 1, h.d_inst, h.d_tmap, h.ntl(), h.tpx(), h.nrf(), mm,
+                                  h.M, h.k, 1, h.bal, ss[q]));
+            }
+          if ((st = join_to(f, s)) != KPM_OK) break;
+        }
         KPM_HIP(hipEventRecord(e1, s));
         float ms = 0.f;
         if ((st = elapsed(&ms)) != KPM_OK) break;
@@ -1081,7 +1104,7 @@ int tune_pair(Ctx& c, Halves& hv, const std::string& key, Prep prep, hipStream_t
       }
       if (verbose)
         std::fprintf(stderr, "[kpm tune] %s P=%d sched=%d forward %.1f us/step adjoint %.1f us/step (both halves)\n",
-                     key.c_str(), P, S, 1e3f * tf / steps, 1e3f * ta / steps);
+                     key.c_str(), P, S, 1e3f * tf / (fm1 - fm0 + 1), 1e3f * ta / steps);
     }
     if (st != KPM_OK) break;
   }
