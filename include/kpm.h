@@ -378,12 +378,35 @@ int kpm_batch_destroy(void* plan);
  * instances. */
 int32_t kpm_batch_streams(const void* plan);
 
+/* Instance groups of a batch plan: the plan runs its instances as groups of
+ * nearly equal R N (largest first, each to the lightest group), one group
+ * after another, each group with its own kernel tables, tuning and (see
+ * kpm_batch_streams) halves.  Automatic (kpm_set_batch_groups(0), the
+ * default): as many groups as keep each group's adjoint step working set, 6
+ * vector sets of sum R N records (16 B FP32, 32 B FP64), within 240 MB, so
+ * that the step is served from the 256 MB Infinity Cache of the MI355X
+ * instead of HBM (the 48 uneven lattices of 24-64 sites a side with 64
+ * probes each: 3 groups in FP32, 191 ms per energy + gradient against
+ * 259 ms as one group).  Fixed when the plan is created.  Each instance's
+ * results are the same either way, bit for bit, for a fixed probe block and
+ * schedule.  Returns the group count (1: no groups), KPM_EINVAL for a null
+ * plan.  kpm_batch_tuning reports the first group's configuration;
+ * kpm_batch_streams is 2 when any group runs as halves. */
+int32_t kpm_batch_groups(const void* plan);
+
+/* Group count of the batch plans created from now on: 0 automatic (see
+ * kpm_batch_groups), else that many groups (at most one per instance).
+ * Process-wide; returns the previous value (negative values leave the
+ * setting unchanged). */
+int32_t kpm_set_batch_groups(int32_t groups);
+
 /* The plan's kernel configuration (host int32_t out[5]): forward probe block,
  * forward schedule, adjoint probe block, adjoint schedule, and where they
  * came from: 0 timed by this plan, 1 this process's cache, 2 the disk cache,
  * -1 not tuned (fixed by kpm_set_probe_block / kpm_set_schedule, or the plan
  * has not run yet).  Schedules are KPM_SCHED_* values.  A plan of two
- * instance halves runs one configuration on both. */
+ * instance halves runs one configuration on both; a plan of instance groups
+ * (kpm_batch_groups) reports its first group's. */
 int kpm_batch_tuning(const void* plan, int32_t* out);
 
 /* Probes-per-thread blocking used by the single-lattice calls (0 = automatic,

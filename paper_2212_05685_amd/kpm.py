@@ -44,7 +44,7 @@ EXPORTS = (
     "kpm_density_matrix_direct", "kpm_moments_doubling", "kpm_ldos", "kpm_build_H_sdw",
     "kpm_rmft_update_sdw", "kpm_rmft_iterate_sdw", "kpm_build_H_sdw_vjp", "kpm_bloch_H", "kpm_gutzwiller_weights", "kpm_supercell_workspace_size",
     "kpm_supercell_ldos", "kpm_moments_noalloc", "kpm_set_schedule", "kpm_set_streams", "kpm_batch_tuning",
-    "kpm_batch_streams",
+    "kpm_batch_streams", "kpm_batch_groups", "kpm_set_batch_groups",
 )
 
 
@@ -124,6 +124,8 @@ def _load():
         "kpm_set_streams": (c_int32, [c_int32]),
         "kpm_batch_tuning": (c_int32, [P, P]),
         "kpm_batch_streams": (c_int32, [P]),
+        "kpm_batch_groups": (c_int32, [P]),
+        "kpm_set_batch_groups": (c_int32, [c_int32]),
         "kpm_profile_begin": (c_int32, [c_int32]),
         "kpm_profile_end": (c_int32, [POINTER(c_double), POINTER(c_int32), POINTER(c_double),
                                       POINTER(c_int32)]),
@@ -501,6 +503,19 @@ def kpm_batch_streams(plan) -> int:
     r = _lib.kpm_batch_streams(plan)
     _check(r if r < 0 else 0, "kpm_batch_streams")
     return int(r)
+
+
+def kpm_batch_groups(plan) -> int:
+    """Instance groups the plan runs one after another (1: no groups)."""
+    r = _lib.kpm_batch_groups(plan)
+    _check(r if r < 0 else 0, "kpm_batch_groups")
+    return int(r)
+
+
+def kpm_set_batch_groups(groups: int) -> int:
+    """0 automatic (groups sized to the Infinity Cache), else that many groups for
+    batch plans created from now on; returns the previous value."""
+    return int(_lib.kpm_set_batch_groups(groups))
 
 
 def kpm_batch_tuning(plan) -> dict:

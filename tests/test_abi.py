@@ -85,6 +85,9 @@ def test_host_validation():
     out = (ctypes.c_int32 * 5)()
     assert kpm._lib.kpm_batch_tuning(None, out) == kpm.KPM_EINVAL
     assert kpm._lib.kpm_batch_streams(None) == kpm.KPM_EINVAL
+    assert kpm._lib.kpm_batch_groups(None) == kpm.KPM_EINVAL
+    old_groups = kpm.kpm_set_batch_groups(3)
+    assert kpm.kpm_set_batch_groups(-1) == 3 and kpm.kpm_set_batch_groups(old_groups) == 3
 
 
 def test_rmft_host_validation():

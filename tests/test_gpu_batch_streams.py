@@ -13,8 +13,10 @@ single-lattice tile arithmetic and, when asked, the balanced adjoint split),
 direct launches and graph replays, FP64 and FP32, fixed probe blocks with
 several schedules and the automatic block (each half tuned as its own shape);
 the split plan reproduces the one-stream plan bit for bit at a fixed block;
-graph replays repeat bit for bit; and the automatic rule.  The 48-lattice
-batch against the oracle (tests/test_gpu_fullsize_oracle.py) runs split.
+graph replays repeat bit for bit; and the automatic rule.  Instance groups
+(kpm_batch_groups: groups of lattices run one after another, each sized to
+the Infinity Cache) likewise.  The 48-lattice batch against the oracle
+(tests/test_gpu_fullsize_oracle.py) runs as 3 groups, each split.
 """
 import functools
 
@@ -49,6 +51,7 @@ def _reset():
     from paper_2212_05685_amd import kpm
     yield
     kpm.kpm_set_streams(0)
+    kpm.kpm_set_batch_groups(0)
     kpm.kpm_set_probe_block(0)
     kpm.kpm_set_schedule(kpm.KPM_SCHED_DEFAULT, kpm.KPM_SCHED_DEFAULT)
 
@@ -74,13 +77,15 @@ def _inputs(prec):
     return probs, hs, abs_, Cs
 
 
-def _plan(prec, streams):
+def _plan(prec, streams, groups=0):
     from paper_2212_05685_amd import kpm
     probs = _inputs(prec)[0]
     kpm.kpm_set_streams(streams)
+    kpm.kpm_set_batch_groups(groups)
     plan = kpm.kpm_batch_create([q.lat for q in probs], [q.probes for q in probs], M,
                                 kpm.KPM_FP64 if prec == "fp64" else kpm.KPM_FP32, K)
     kpm.kpm_set_streams(0)
+    kpm.kpm_set_batch_groups(0)
     return plan
 
 
@@ -207,3 +212,51 @@ def test_pair_tuning_cache(tmp_path, monkeypatch):
         assert [ln[0] for ln in lines] == [key]
         assert [int(v) for v in lines[0][1:]] == picks[0]
     assert picks[0] == picks[1]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("groups,streams", [(2, 1), (2, 2), (3, 2)])
+def test_groups(prec, groups, streams):
+    """Instance groups run one after another (forced here: the 16 x 16 lattice
+    alone and the other two together, or one group per lattice), with and
+    without instance halves inside a group: every instance matches the oracle,
+    and at a fixed probe block the results equal the one-group one-stream
+    plan's bit for bit, in direct launches and graph replays."""
+    from paper_2212_05685_amd import kpm
+    kpm.kpm_set_probe_block(2)
+    one = _plan(prec, 1, 1)
+    plan = _plan(prec, streams, groups)
+    try:
+        assert kpm.kpm_batch_groups(one) == 1 and kpm.kpm_batch_groups(plan) == groups
+        # a group of two lattices splits into halves when asked; single-lattice groups cannot
+        assert kpm.kpm_batch_streams(plan) == (2 if streams == 2 and groups == 2 else 1)
+        om1, r1 = _call(one, prec, False)
+        runs = [_call(plan, prec, g) for g in (False, True, True)]
+    finally:
+        kpm.kpm_batch_destroy(one)
+        kpm.kpm_batch_destroy(plan)
+    _check_oracle(*runs[0], prec)
+    for om2, r2 in runs:
+        assert np.array_equal(om1, om2)
+        assert all(np.array_equal(a, b) for a, b in zip(r1, r2))
+
+
+def test_group_rule():
+    """Automatic groups: as many as keep each group's adjoint working set
+    (6 x 16 B (FP32) or 32 B (FP64) x sum R N) within 240 MB: the 48 uneven
+    lattices (7.2e6 site-probes) in 3 groups in FP32 and 6 in FP64; their
+    first 3 lattices in one."""
+    from paper_2212_05685_amd import kpm
+    cfgs = wl.C4_instances(48)
+    probs = [problem(c, precision="fp32") for c in cfgs]
+    rn = sum(q.R * c.N for q, c in zip(probs, cfgs))
+    want = {kpm.KPM_FP32: -(-6 * 16 * rn // 240_000_000), kpm.KPM_FP64: -(-6 * 32 * rn // 240_000_000)}
+    assert want == {kpm.KPM_FP32: 3, kpm.KPM_FP64: 6}
+    for n, prec in ((48, kpm.KPM_FP32), (48, kpm.KPM_FP64), (3, kpm.KPM_FP32)):
+        plan = kpm.kpm_batch_create([q.lat for q in probs[:n]], [q.probes for q in probs[:n]], cfgs[0].M,
+                                    prec, cfgs[0].ckpt_k)
+        try:
+            assert kpm.kpm_batch_groups(plan) == (want[prec] if n == 48 else 1)
+        finally:
+            kpm.kpm_batch_destroy(plan)
+    torch.cuda.empty_cache()

@@ -17,7 +17,8 @@ from checkpoints.  Both sides take their own stencil, bounds and coefficients.
   probes (64 colored + 128 dense Z4, each set of weight 1/2), in the tuned
   launch configuration: FP64 to 1e-10, FP32 vectors to 1e-5.
 * The 48-lattice batch (M = 1024, 64 colored probes each), FP32, replayed as
-  the benchmark does (two instance halves on two streams, one graph each):
+  the benchmark does (3 groups of lattices one after another, each as two
+  instance halves on two streams, one graph each):
   the smallest and the largest lattice and one with four vortices, against
   O2 on all their probes, to 1e-5.
 """
@@ -129,7 +130,7 @@ def test_c4_batched_rho_against_oracle():
     try:
         omega = torch.zeros(len(cfgs), dtype=torch.float64, device="cuda")
         rhos = [torch.zeros_like(h) for h in hs]
-        assert kpm.kpm_batch_streams(plan) == 2
+        assert kpm.kpm_batch_streams(plan) == 2 and kpm.kpm_batch_groups(plan) == 3
         for _ in range(2):          # tune + capture, then a replay of the graphs
             kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=True)
         om = host(omega)
