@@ -382,12 +382,13 @@ int32_t kpm_batch_streams(const void* plan);
  * nearly equal R N (largest first, each to the lightest group), one group
  * after another, each group with its own kernel tables, tuning and (see
  * kpm_batch_streams) halves.  Automatic (kpm_set_batch_groups(0), the
- * default): as many groups as keep each group's adjoint step working set, 6
- * vector sets of sum R N records (16 B FP32, 32 B FP64), within 240 MB, so
- * that the step is served from the 256 MB Infinity Cache of the MI355X
- * instead of HBM (the 48 uneven lattices of 24-64 sites a side with 64
- * probes each: 3 groups in FP32, 191 ms per energy + gradient against
- * 259 ms as one group).  Fixed when the plan is created.  Each instance's
+ * default): as many groups as keep each group's adjoint step traffic, 6
+ * passes of sum R N records (16 B FP32, 32 B FP64) over 4 distinct vector
+ * sets, within 240 MB, so that those sets stay in the 256 MB Infinity Cache
+ * of the MI355X from one step to the next instead of streaming from HBM
+ * (the 48 uneven lattices of 24-64 sites a side with 64 probes each: 3
+ * groups in FP32, 191 ms per energy + gradient against 259 ms as one
+ * group).  Fixed when the plan is created.  Each instance's
  * results are the same either way, bit for bit, for a fixed probe block and
  * schedule.  Returns the group count (1: no groups), KPM_EINVAL for a null
  * plan.  kpm_batch_tuning reports the first group's configuration;

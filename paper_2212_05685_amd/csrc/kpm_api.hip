@@ -1287,14 +1287,16 @@ void split_instances(const std::vector<InstDev>& inst, std::vector<int> idx[2]) 
 }
 
 // Instance groups of a batch plan, run one after another: kpm_set_batch_groups
-// when set, else as many as keep each group's adjoint step working set (6
-// vector sets of its sum R N records: alpha and gamma at m+2, m+1 read, at m
-// written) within kGroupBytes, so that the step is served from the 256 MB
-// Infinity Cache rather than HBM.  Measured (the 48 uneven lattices, FP32,
-// M = 1024, 7.2e6 site-probes, 693 MB per adjoint step; groups balanced by
-// R N, each as two instance halves; ms per energy + gradient): 1 group 258.9,
-// 2: 230.9, 3: 190.9 (232 MB per group), 4: 201.2, 5: 212.2, 6: 225.7,
-// 8: 241.4.
+// when set, else as many as keep each group's adjoint step traffic (6 passes
+// of its sum R N records: alpha and gamma at m+1 and m+2 read, alpha_m and
+// gamma_m written over the m+2 sets) within kGroupBytes, i.e. its 4 distinct
+// vector sets within 160 MB, so that they stay in the 256 MB Infinity Cache
+// from one step to the next (with the coefficients and partial sums) rather
+// than streaming from HBM.  Measured (the 48 uneven lattices, FP32, M = 1024,
+// 7.2e6 site-probes, 693 MB of adjoint traffic and 462 MB of distinct vectors
+// per step; groups balanced by R N, each as two instance halves; ms per
+// energy + gradient): 1 group 258.9, 2: 230.9 (231 MB distinct per group),
+// 3: 190.9 (154 MB), 4: 201.2, 5: 212.2, 6: 225.7, 8: 241.4.
 constexpr double kGroupBytes = 240e6;
 int32_t g_batch_groups = 0;   // 0 automatic, else the group count (at most one per instance)
 
