@@ -1296,7 +1296,9 @@ void split_instances(const std::vector<InstDev>& inst, std::vector<int> idx[2]) 
 // 7.2e6 site-probes, 693 MB of adjoint traffic and 462 MB of distinct vectors
 // per step; groups balanced by R N, each as two instance halves; ms per
 // energy + gradient): 1 group 258.9, 2: 230.9 (231 MB distinct per group),
-// 3: 190.9 (154 MB), 4: 201.2, 5: 212.2, 6: 225.7, 8: 241.4.
+// 3: 190.9 (154 MB), 4: 201.2, 5: 212.2, 6: 225.7, 8: 241.4; in FP64 (twice
+// the bytes): 1 group 527.1, 2: 516.1, 3: 472.1, 4: 464.0, 6: 450.7 (154 MB),
+// 8: 464.7.
 constexpr double kGroupBytes = 240e6;
 int32_t g_batch_groups = 0;   // 0 automatic, else the group count (at most one per instance)
 
