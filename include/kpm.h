@@ -328,7 +328,10 @@ int kpm_status_read(const void* ws, int32_t* status, void* stream);
 
 /* Create a plan for n_inst lattices of possibly different size, vortex count
  * and probes, all with the same M, precision and checkpoint interval.  The
- * plan owns its device memory.  On first use it chooses the probes-per-thread
+ * plan owns its device memory.  It runs its instances in groups sized to the
+ * Infinity Cache (kpm_batch_groups), each group, when large enough, as two
+ * halves on two streams (kpm_batch_streams).  On first use it chooses the
+ * probes-per-thread
  * blocking and the block schedule of the forward and of the adjoint kernel by
  * timing every pair (autotune), unless kpm_set_probe_block fixed the block.
  * Picks are remembered per shape (device, precision, every instance's N and
@@ -352,9 +355,10 @@ int kpm_batch_create(int32_t n_inst, const kpm_lattice* lats, const kpm_probes* 
 /* Energy + gradient for every instance: for instance k, with h[k], ab[k],
  * C[k] (host arrays of device pointers), writes omega[k] (device double
  * [n_inst]) and rho[k] ([19][N_k] complex, device).  The forward and adjoint
- * recursions of all instances run as one sequence of batched kernels,
- * captured once into a hipGraph and replayed on later calls with the same
- * pointers (use_graph != 0).  A plan of two instance halves (see
+ * recursions of all instances of a group run as one sequence of batched
+ * kernels (the groups one after another on the caller's stream), captured
+ * once into a hipGraph and replayed on later calls with the same pointers
+ * (use_graph != 0).  A group of two instance halves (see
  * kpm_batch_streams) runs the halves side by side on the caller's stream and
  * on a second stream of the device that the library creates once (default
  * priority): with use_graph, as one graph per half; else with their step
@@ -366,13 +370,14 @@ int kpm_batch_energy_grad(void* plan, const double* const* h, const double* cons
 
 int kpm_batch_destroy(void* plan);
 
-/* Streams a batch plan runs on: 2 when its instances form two halves of
- * nearly equal R N (largest first, each to the lighter half), each half with
- * its own kernel tables, both tuned together (one pick, timed on the pair);
- * 1 otherwise; KPM_EINVAL for a null plan.
- * Fixed when the plan is created, from kpm_set_streams: 1, one stream; 2,
- * halves (plans of two or more instances); 0 (default), automatic: halves
- * when the instances hold sum R N >= 2^19 site-probes.  Each instance's
+/* Streams a batch plan runs on: 2 when its instances (or those of any of its
+ * groups, see kpm_batch_groups) form two halves of nearly equal R N (largest
+ * first, each to the lighter half), each half with its own kernel tables,
+ * both tuned together (one pick, timed on the pair); 1 otherwise;
+ * KPM_EINVAL for a null plan.  Fixed when the plan is created, from
+ * kpm_set_streams: 1, one stream; 2, halves (groups of two or more
+ * instances); 0 (default), automatic: halves when the group's instances hold
+ * sum R N >= 2^19 site-probes.  Each instance's
  * results are the same either way, bit for bit, for a fixed probe block and
  * schedule: an instance's kernels and sums do not depend on the other
  * instances. */
