@@ -20,8 +20,10 @@ from checkpoints.  Both sides take their own stencil, bounds and coefficients.
   the benchmark does (3 groups of lattices one after another, each as two
   instance halves on two streams, one graph each):
   the smallest and the largest lattice and one with four vortices, against
-  O2 on all their probes, to 1e-5.
+  O2 on all their probes, to 1e-5; and the FP64 batch (6 groups) to 1e-10.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -113,12 +115,21 @@ def _c4_pick(cfgs):
     return [small, large, four]
 
 
-def test_c4_batched_rho_against_oracle():
+@functools.lru_cache(maxsize=None)
+def _c4_oracle(q):
+    cfg = wl.C4_instances(48)[q]
+    st, a, b, C = H.oracle_inputs(cfg)
+    return H.plain_parallel(cfg, st, a, b, C)
+
+
+@pytest.mark.parametrize("prec,groups,tol", [("fp32", 3, 1e-5), ("fp64", 6, 1e-10)])
+def test_c4_batched_rho_against_oracle(prec, groups, tol):
+    """FP32: 3 instance groups; FP64 (twice the bytes per record): 6."""
     from paper_2212_05685_amd import kpm
     cfgs = wl.C4_instances(48)
     probs, hs, abs_, Cs = [], [], [], []
     for cfg in cfgs:
-        q = problem(cfg, precision="fp32")
+        q = problem(cfg, precision=prec)
         h = q.build_H(*theta_dev(cfg))
         ab = q.bounds(h)
         probs.append(q)
@@ -126,23 +137,25 @@ def test_c4_batched_rho_against_oracle():
         abs_.append(ab)
         Cs.append(q.coefficients(ab))
     M, k = cfgs[0].M, cfgs[0].ckpt_k
-    plan = kpm.kpm_batch_create([q.lat for q in probs], [q.probes for q in probs], M, kpm.KPM_FP32, k)
+    plan = kpm.kpm_batch_create([q.lat for q in probs], [q.probes for q in probs], M,
+                                kpm.KPM_FP32 if prec == "fp32" else kpm.KPM_FP64, k)
     try:
         omega = torch.zeros(len(cfgs), dtype=torch.float64, device="cuda")
         rhos = [torch.zeros_like(h) for h in hs]
-        assert kpm.kpm_batch_streams(plan) == 2 and kpm.kpm_batch_groups(plan) == 3
+        assert kpm.kpm_batch_streams(plan) == 2 and kpm.kpm_batch_groups(plan) == groups
         for _ in range(2):          # tune + capture, then a replay of the graphs
             kpm.kpm_batch_energy_grad(plan, hs, abs_, Cs, omega, rhos, use_graph=True)
         om = host(omega)
         got = {q: host(rhos[q]) for q in range(len(cfgs))}
     finally:
         kpm.kpm_batch_destroy(plan)
+    del probs, hs, abs_, Cs, rhos
+    torch.cuda.empty_cache()
     for q in _c4_pick(cfgs):
         cfg = cfgs[q]
-        st, a, b, C = H.oracle_inputs(cfg)
-        ref = H.plain_parallel(cfg, st, a, b, C)
+        ref = _c4_oracle(q)
         e_om = abs(om[q] - ref["omega"]) / abs(ref["omega"])
         e_rho = H.rel_err(got[q], ref["rho"])
-        print(f"batch instance {q} ({cfg.Lx}x{cfg.Ly}, n_v={cfg.n_v}, doping {cfg.doping:.3f}): "
+        print(f"batch instance {q} ({cfg.Lx}x{cfg.Ly}, n_v={cfg.n_v}, doping {cfg.doping:.3f}, {prec}): "
               f"|dOmega|/|Omega| = {e_om:.2e}, max|drho|/max|rho| = {e_rho:.2e}")
-        assert e_om < 1e-5 and e_rho < 1e-5
+        assert e_om < tol and e_rho < tol
